@@ -1,0 +1,247 @@
+"""CPU oracle for the SU(2) Wilson-action heat-bath sweep (test infrastructure).
+
+Only the tests, the package's smoke check and the CPU-baseline leg of the
+benchmark may import this package.  The product path (the HIP library and its
+Python binding) never does, and the two share no code: the lattice chain is
+plain C in ``su2_oracle.c`` (FP64 arithmetic, FP32 link storage as the paper
+fixes in Sec. 2.4), wrapped here with ctypes; the learned-proposal pieces are
+plain NumPy in ``cdf.py`` and ``mlp.py``.
+
+Link arrays on this side are float64 numpy arrays of shape [V, 4, 4] indexed
+(site lex, direction mu, quaternion component), lex = x0 + L0*(x1 + L1*(x2 +
+L2*x3)), direction 3 = time.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIBPATH = os.path.join(_HERE, "libsu2_oracle.so")
+_lib = None
+
+COLD, HOT = 0, 1
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIBPATH):
+        from . import build as _b
+        _b.build()
+    lib = ctypes.CDLL(_LIBPATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    i8p = ctypes.POINTER(ctypes.c_int8)
+    lib.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+    lib.oracle_philox4x32_10.restype = None
+    lib.oracle_uniform.argtypes = [ctypes.c_uint32]
+    lib.oracle_uniform.restype = ctypes.c_double
+    lib.oracle_qmul.argtypes = [dp, dp, dp]
+    lib.oracle_qmul.restype = None
+    lib.oracle_staple.argtypes = [i32p, dp, ctypes.c_long, ctypes.c_int, dp]
+    lib.oracle_staple.restype = None
+    lib.oracle_kp_draw.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                   ctypes.c_int, ctypes.c_uint32, ctypes.c_int, dp, dp, dp]
+    lib.oracle_kp_draw.restype = ctypes.c_int
+    lib.oracle_init.argtypes = [i32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_init.restype = ctypes.c_int
+    lib.oracle_pass.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, i8p, dp, u64p]
+    lib.oracle_pass.restype = ctypes.c_int
+    lib.oracle_sweep.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                 ctypes.c_int, dp, u64p]
+    lib.oracle_sweep.restype = ctypes.c_int
+    lib.oracle_plaquette.argtypes = [i32p, dp, dp]
+    lib.oracle_plaquette.restype = ctypes.c_int
+    lib.oracle_polyakov.argtypes = [i32p, dp, dp]
+    lib.oracle_polyakov.restype = ctypes.c_int
+    lib.oracle_staple_action.argtypes = [i32p, dp, dp]
+    lib.oracle_staple_action.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _dims(dims):
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+    if d.shape != (4,):
+        raise ValueError("dims must have 4 entries")
+    return d
+
+
+def volume(dims):
+    return int(np.prod(np.asarray(dims, dtype=np.int64)))
+
+
+def philox4x32_10(counter, key):
+    """Philox-4x32-10 block for counter (4 x u32) and key (2 x u32)."""
+    lib = _load()
+    c = np.ascontiguousarray(np.asarray(counter, dtype=np.uint32))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32))
+    o = np.zeros(4, dtype=np.uint32)
+    lib.oracle_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
+                             _ptr(o, ctypes.c_uint32))
+    return o
+
+
+def uniform(word):
+    return _load().oracle_uniform(int(word))
+
+
+def qmul(a, b):
+    lib = _load()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    c = np.zeros(4)
+    lib.oracle_qmul(_ptr(a, ctypes.c_double), _ptr(b, ctypes.c_double), _ptr(c, ctypes.c_double))
+    return c
+
+
+def init(dims, seed, start, prec32=True):
+    """Cold (start=0) or hot (start=1) lattice, float64 [V, 4, 4]."""
+    lib = _load()
+    d = _dims(dims)
+    U = np.zeros((volume(dims), 4, 4))
+    rc = lib.oracle_init(_ptr(d, ctypes.c_int32), ctypes.c_uint64(seed), int(start),
+                         int(bool(prec32)), _ptr(U, ctypes.c_double))
+    if rc:
+        raise ValueError("oracle_init rejected its arguments")
+    return U
+
+
+def _links(U):
+    U = np.ascontiguousarray(U, dtype=np.float64)
+    if U.ndim != 3 or U.shape[1:] != (4, 4):
+        raise ValueError("links must have shape [V, 4, 4]")
+    return U
+
+
+def staple(dims, U, lex, mu):
+    lib = _load()
+    d = _dims(dims)
+    U = _links(U)
+    w = np.zeros(4)
+    lib.oracle_staple(_ptr(d, ctypes.c_int32), _ptr(U, ctypes.c_double), int(lex), int(mu),
+                      _ptr(w, ctypes.c_double))
+    return w
+
+
+def kp_draw(alpha, seed, site, mu, sweep, prec32=True):
+    """One capped KP draw.  Returns (attempt index or -1, x0, |a|, margin)."""
+    lib = _load()
+    a0 = ctypes.c_double(np.nan)
+    am = ctypes.c_double(np.nan)
+    m = ctypes.c_double(np.nan)
+    t = lib.oracle_kp_draw(float(alpha), ctypes.c_uint64(seed), int(site), int(mu), int(sweep),
+                           int(bool(prec32)), ctypes.byref(a0), ctypes.byref(am), ctypes.byref(m))
+    return t, a0.value, am.value, m.value
+
+
+class PassResult:
+    def __init__(self, tries, margin, attempts, failures):
+        self.tries = tries
+        self.margin = margin
+        self.attempts = attempts
+        self.failures = failures
+
+
+def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True):
+    """In-place heat-bath pass over links U_mu(x), parity(x) == parity."""
+    lib = _load()
+    d = _dims(dims)
+    if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
+        raise ValueError("U must be a C-contiguous float64 array")
+    V = volume(dims)
+    tries = np.full(V, -1, dtype=np.int8)
+    margin = np.full(V, np.nan)
+    stats = np.zeros(2, dtype=np.uint64)
+    rc = lib.oracle_pass(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed), int(sweep),
+                         int(parity), int(mu), int(bool(prec32)), _ptr(U, ctypes.c_double),
+                         _ptr(tries, ctypes.c_int8), _ptr(margin, ctypes.c_double),
+                         _ptr(stats, ctypes.c_uint64))
+    if rc:
+        raise ValueError("oracle_pass rejected its arguments")
+    return PassResult(tries, margin, int(stats[0]), int(stats[1]))
+
+
+def sweep(dims, U, beta, seed, sweep_index, prec32=True):
+    """In-place full sweep; returns (attempts, cap failures)."""
+    lib = _load()
+    d = _dims(dims)
+    if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
+        raise ValueError("U must be a C-contiguous float64 array")
+    stats = np.zeros(2, dtype=np.uint64)
+    rc = lib.oracle_sweep(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
+                          int(sweep_index), int(bool(prec32)), _ptr(U, ctypes.c_double),
+                          _ptr(stats, ctypes.c_uint64))
+    if rc:
+        raise ValueError("oracle_sweep rejected its arguments")
+    return int(stats[0]), int(stats[1])
+
+
+def plaquette(dims, U):
+    """(P, P_spatial, P_temporal) in FP64."""
+    lib = _load()
+    d = _dims(dims)
+    U = _links(U)
+    out = np.zeros(3)
+    if lib.oracle_plaquette(_ptr(d, ctypes.c_int32), _ptr(U, ctypes.c_double),
+                            _ptr(out, ctypes.c_double)):
+        raise ValueError("bad dims")
+    return out
+
+
+def polyakov(dims, U):
+    lib = _load()
+    d = _dims(dims)
+    U = _links(U)
+    out = ctypes.c_double(np.nan)
+    if lib.oracle_polyakov(_ptr(d, ctypes.c_int32), _ptr(U, ctypes.c_double), ctypes.byref(out)):
+        raise ValueError("bad dims")
+    return out.value
+
+
+def staple_action(dims, U):
+    lib = _load()
+    d = _dims(dims)
+    U = _links(U)
+    out = ctypes.c_double(np.nan)
+    if lib.oracle_staple_action(_ptr(d, ctypes.c_int32), _ptr(U, ctypes.c_double),
+                                ctypes.byref(out)):
+        raise ValueError("bad dims")
+    return out.value
+
+
+class Chain:
+    """A running oracle chain: links + sweep counter, mirroring the library's
+    global context (init, sweep(n), plaquette, polyakov, links)."""
+
+    def __init__(self, dims, beta, seed, start, prec32=True):
+        self.dims = tuple(int(x) for x in dims)
+        self.beta = float(beta)
+        self.seed = int(seed)
+        self.prec32 = bool(prec32)
+        self.U = init(dims, seed, start, prec32)
+        self.s = 0
+        self.attempts = 0
+        self.failures = 0
+
+    def sweep(self, n=1):
+        for _ in range(n):
+            a, f = sweep(self.dims, self.U, self.beta, self.seed, self.s, self.prec32)
+            self.attempts += a
+            self.failures += f
+            self.s += 1
+
+    def plaquette(self):
+        return plaquette(self.dims, self.U)
+
+    def polyakov(self):
+        return polyakov(self.dims, self.U)

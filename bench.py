@@ -1,0 +1,166 @@
+"""Benchmark of the SU(2) heat-bath sweep on one MI355X.
+
+Workload (default): 64^4 periodic lattice (1.07 GB of FP32 links), beta = 2.4,
+hot start from Philox seed 1, plain Kennedy-Pendleton heat-bath -- the lattice
+on which the HBM-roofline fraction is quoted.  One step = one full sweep (eight
+(parity, mu) passes, Sec. 2.4) followed by the plaquette and Polyakov
+measurements into a device-resident history, i.e. every row of the hot path
+after initialisation.  Inputs (the initialised lattice) are resident in HBM
+before the timed region starts.
+
+Prints one JSON line: throughput in link updates/s, the roofline of the
+dominant kernel (k_pass, measured with HIP events on the library's stream
+inside the timed region), and the CPU oracle timed on a bounded sample of the
+same workload.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "SU(2) link updates/s + HBM GB/s fraction; learned vs KP proposal at same <P>"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 128  # one lattice streamed per (parity, mu) pass: 4N links x 16 B / (N/2) updates
+WORKLOADS = {
+    64: dict(name="su2_64x64x64x64_b2.4_hot", dims=(64, 64, 64, 64), beta=2.4, seed=1, start=1),
+    32: dict(name="su2_32x32x32x32_b2.3_hot", dims=(32, 32, 32, 32), beta=2.3, seed=1, start=1),
+}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_0903_3053_amd", "csrc", f)
+                  for f in ("su2_kernels.hip", "su2_device.hpp")]
+
+
+def kernel_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, bytes_per_launch):
+    """HBM bytes per k_pass launch from the committed rocprofv3 counter runs,
+    or None if they were taken on another version of the kernel."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = t.get(workload)
+    if not rec or rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, sweeps=8):
+    """The oracle (plain C, FP64, OpenMP over sites) on a bounded sample of the
+    same workload: the first `sweeps` sweeps of the same lattice from the same
+    hot start (initialisation not timed)."""
+    import oracle
+    U = oracle.init(w["dims"], w["seed"], oracle.HOT)
+    t0 = time.perf_counter()
+    for s in range(sweeps):
+        oracle.sweep(w["dims"], U, w["beta"], w["seed"], s)
+    dt = time.perf_counter() - t0
+    n = 4 * U.shape[0] * sweeps
+    del U
+    return {"value": n / dt, "unit": "link updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"the first {sweeps} sweeps ({n} link updates) of the same {w['name']} "
+                      f"lattice from the same hot start, {dt:.2f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--lattice", type=int, default=64, choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(replicas and couplings would shard with no communication)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_0903_3053_amd import su2
+
+    w = WORKLOADS[args.lattice]
+    dims = w["dims"]
+    V = int(np.prod(dims))
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    su2.su2_set_stream(stream)
+    su2.su2_init(dims, w["beta"], w["seed"], w["start"])
+    hist = torch.zeros((args.steps, 4), dtype=torch.float64, device="cuda")
+
+    # warm-up: sweeps and measurements, graphs built and replayed
+    for _ in range(args.warmup):
+        su2.su2_sweep(1)
+    su2.su2_plaquette_st()
+    su2.su2_polyakov()
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start_ev = torch.cuda.Event(enable_timing=True)
+    end_ev = torch.cuda.Event(enable_timing=True)
+    start_ev.record(stream)
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        su2.su2_sweep(1)
+        ev[i][1].record(stream)
+        su2.su2_measure_device(hist[i])
+    end_ev.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    total_ms = start_ev.elapsed_time(end_ev)
+    sweep_ms = sum(a.elapsed_time(b) for a, b in ev)
+    ms_per_step = max(total_ms, wall * 1e3) / args.steps
+    updates = 4 * V * args.steps
+    value = updates / (ms_per_step * args.steps / 1e3)
+    h = hist.cpu().numpy()
+    P, poly = h[-1, :3], h[-1, 3]
+
+    # roofline of k_pass: 8 launches per sweep, V/2 updates x 128 B each
+    pass_ms = sweep_ms / (8 * args.steps)
+    bytes_per_launch = (V // 2) * BYTES_PER_UPDATE
+    achieved = bytes_per_launch / (pass_ms * 1e-3) / 1e9
+    traffic = measured_traffic(w["name"], bytes_per_launch)
+
+    rec = {
+        "metric": METRIC, "value": value, "unit": "link updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "dims": list(dims), "beta": w["beta"], "seed": w["seed"],
+                   "start": "hot", "proposal": "kennedy-pendleton",
+                   "step": "1 sweep (8 passes) + plaquette + Polyakov on device"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_pass", "avg_launch_ms": pass_ms,
+                     "algorithmic_bytes_per_launch": bytes_per_launch},
+        "observables": {"plaquette": float(P[0]), "plaquette_spatial": float(P[1]),
+                        "plaquette_temporal": float(P[2]), "polyakov": float(poly)},
+    }
+    att, fail = su2.su2_counters()
+    rec["observables"]["kp_attempts_per_update"] = att / max(1, 4 * V * (args.steps + args.warmup))
+    if not args.no_cpu_baseline:
+        rec["cpu_baseline"] = cpu_baseline(w)
+    su2.su2_finalize()
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,143 @@
+/*
+ * su2.h -- C ABI of libsu2.so: the SU(2) pure-gauge Wilson-action heat-bath
+ * sweep on a periodic 4-D lattice, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Demchik & Strelchenko, "Monte Carlo simulations on Graphics
+ * Processing Units" (arXiv:0903.3053), Sec. 2.4: links U_mu(x) in SU(2) as unit
+ * quaternions (Eq. (4)), Wilson action (Eqs. (2)-(3)), heat-bath link update
+ * towards the staple sum (Eqs. (5)-(7)), odd sites then even sites for each
+ * direction, at most 8 attempts per update, FP64 plaquette averages.
+ *
+ * Conventions shared by every entry point:
+ *   - dims = {L0, L1, L2, L3}: extents, each even and >= 2, direction 3 is
+ *     time; the product V must be below 2^32.  lex = x0 + L0*(x1 + L1*(x2 +
+ *     L2*x3)); parity p(x) = (x0+x1+x2+x3) mod 2, odd = 1.
+ *   - Host link layout: float32 [V][4][4] = (lex, direction mu, component),
+ *     component 0 the identity part, 1..3 the i*sigma_j parts (Eq. (4)).
+ *   - Random numbers: Philox-4x32-10, key = (seed mod 2^32, seed >> 32),
+ *     counter = (lex, mu | purpose << 8, sweep index, slot); purpose 0 = heat
+ *     bath (slots 0..7 attempts, 8 direction, 9 Haar draw at alpha = 0),
+ *     1 = hot start, 2 = learned independence-Metropolis proposal.
+ *
+ * State: one global lattice context (no handle), created by su2_init /
+ * su2_init_ex and released by su2_finalize or the next init.  Calls are not
+ * thread-safe.  All work is enqueued on the library's stream (the null stream
+ * unless su2_set_stream was called); entry points that return host data
+ * synchronise that stream.
+ *
+ * Errors: every int-returning function returns SU2_OK (0) or a negative code;
+ * su2_last_error() gives a message.  Nothing aborts and no C++ exception
+ * crosses the ABI.  Functions returning double return NaN on error.
+ * Ownership: the library owns the device memory it allocates; host buffers
+ * always belong to the caller and are not retained after the call returns.
+ */
+#ifndef SU2_H
+#define SU2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SU2_OK = 0,
+    SU2_EINVAL = -1,  /* argument out of range / wrong size */
+    SU2_ESTATE = -2,  /* no lattice initialised, or wrong call order */
+    SU2_ENOMEM = -3,  /* device allocation failed */
+    SU2_EDEVICE = -4  /* a HIP runtime call or kernel launch failed */
+};
+
+enum { SU2_COLD = 0, SU2_HOT = 1 };
+
+/* Lattice initialisation (Sec. 2.1: done on the GPU; Sec. 2.4: cold or hot).
+ * Allocates the links on the device and fills them: SU2_COLD = identity on
+ * every link, SU2_HOT = a Haar-random unit quaternion per link from Philox
+ * purpose 1 (Shoemake's three-uniform construction).  beta = 4/g^2 (Sec. 2.4)
+ * must be finite and >= 0; start must be SU2_COLD or SU2_HOT.  Resets the
+ * sweep counter and the update counters to 0.  Replaces any previous lattice. */
+int su2_init(const int32_t dims[4], double beta, uint64_t seed, int32_t start);
+
+/* As su2_init, but the links live in a caller-owned device buffer (e.g. a
+ * torch tensor) of at least 64*V bytes, 16-byte aligned; the caller keeps it
+ * alive until su2_finalize or the next init.  dev_links == NULL allocates. */
+int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start,
+                void *dev_links, size_t bytes);
+
+/* n >= 0 full sweeps (Sec. 2.4: for each direction mu = 0..3 the odd sites,
+ * then for each mu the even sites; each link update draws its staple, Eq. (6),
+ * a Kennedy-Pendleton x0 with at most 8 attempts, a direction, rotates, and
+ * reunitarises with an FP64 norm, Eqs. (5)-(7)).  The sweep index used in the
+ * Philox counters advances by one per sweep.  Asynchronous. */
+int su2_sweep(int32_t n);
+
+/* One pass: the links U_mu(x) with parity(x) == parity (0 or 1), mu in 0..3,
+ * at the current sweep index (which does not advance). */
+int su2_pass(int32_t parity, int32_t mu);
+
+/* Mean plaquette P = (P_s + P_t)/2 of (1/2)Tr U_mu,nu(x) (Eq. (3)), FP64
+ * reduction.  Synchronises.  NaN on error. */
+double su2_plaquette(void);
+
+/* out[0] = P, out[1] = P_s (planes 01, 02, 12), out[2] = P_t (planes 03, 13,
+ * 23) -- the spatial/temporal split of Sec. 2.4.  Synchronises. */
+int su2_plaquette_st(double out[3]);
+
+/* Polyakov loop: mean over spatial sites of (1/2)Tr of the ordered product of
+ * U_3(x, t), t = 0..L3-1.  FP32 products, FP64 reduction.  Synchronises. */
+int su2_polyakov(double *out);
+
+/* Enqueue the measurements of the current configuration without waiting:
+ * dev_out[0..2] = (P, P_s, P_t) as su2_plaquette_st, dev_out[3] = the
+ * Polyakov loop.  dev_out is caller-owned DEVICE memory (4 doubles, 8-byte
+ * aligned, e.g. a row of a torch tensor): the averages stay on the GPU until
+ * the caller copies them (Sec. 2.4). */
+int su2_measure_device(double *dev_out);
+
+/* n sweeps, with (P, P_s, P_t) measured after every `every`-th sweep into a
+ * device history that is copied once, at the end, to host_hist
+ * [n / every][3] (Sec. 2.4: averages stay on the GPU until the run ends).
+ * every >= 1; n must be a multiple of every. */
+int su2_sweep_measure(int32_t n, int32_t every, double *host_hist);
+
+/* Copy the links to host_out (float32 [V][4][4]); n_floats must be 16*V.
+ * Synchronises. */
+int su2_links(float *host_out, size_t n_floats);
+
+/* Replace the links from host_in (float32 [V][4][4], n_floats = 16*V, values
+ * taken as given -- not renormalised) and set the sweep index.  With the same
+ * seed and sweep index, a run resumed this way is bit-identical to an
+ * uninterrupted one. */
+int su2_set_links(const float *host_in, size_t n_floats, uint64_t sweep_index);
+
+/* Current sweep index. */
+int su2_sweep_index(uint64_t *out);
+
+/* out[0] = KP attempts evaluated, out[1] = updates whose 8 attempts all
+ * failed, summed since init. */
+int su2_counters(uint64_t out[2]);
+
+/* Enqueue all later work on this HIP stream (hipStream_t, e.g. a torch
+ * stream); NULL selects the null stream.  Synchronises the previous stream. */
+int su2_set_stream(void *hip_stream);
+
+/* Device Philox-4x32-10 blocks for n host counters ctr[n][4] and key = (seed
+ * mod 2^32, seed >> 32), written to host out[n][4]; for bit-exact checks of
+ * the generator the sweep uses. */
+int su2_philox(uint64_t seed, const uint32_t *ctr, size_t n, uint32_t *out);
+
+/* Wait for all enqueued work. */
+int su2_synchronize(void);
+
+/* Message for the last error (static storage, never NULL). */
+const char *su2_last_error(void);
+
+/* Release the lattice and every device resource; safe to call twice. */
+void su2_finalize(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SU2_H */

@@ -52,6 +52,10 @@ def _load():
     lib.oracle_pass.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, i8p, dp, u64p]
     lib.oracle_pass.restype = ctypes.c_int
+    lib.oracle_update_sites.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                        ctypes.c_int, ctypes.c_int, dp,
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.c_long, dp, i8p, dp]
+    lib.oracle_update_sites.restype = ctypes.c_int
     lib.oracle_sweep.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                  ctypes.c_int, dp, u64p]
     lib.oracle_sweep.restype = ctypes.c_int
@@ -61,6 +65,8 @@ def _load():
     lib.oracle_polyakov.restype = ctypes.c_int
     lib.oracle_staple_action.argtypes = [i32p, dp, dp]
     lib.oracle_staple_action.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -89,6 +95,10 @@ def philox4x32_10(counter, key):
     lib.oracle_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(k, ctypes.c_uint32),
                              _ptr(o, ctypes.c_uint32))
     return o
+
+
+def num_threads():
+    return int(_load().oracle_num_threads())
 
 
 def uniform(word):
@@ -169,6 +179,28 @@ def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True):
     if rc:
         raise ValueError("oracle_pass rejected its arguments")
     return PassResult(tries, margin, int(stats[0]), int(stats[1]))
+
+
+def update_sites(dims, U, beta, seed, sweep_index, mu, sites, prec32=True):
+    """New values of U_mu at the listed sites (one parity) as a pass at
+    sweep_index would write them; U is not modified.  Returns (links [n,4],
+    tries [n], margin [n])."""
+    lib = _load()
+    d = _dims(dims)
+    U = _links(U)
+    sites = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    n = len(sites)
+    out = np.zeros((n, 4))
+    tries = np.full(n, -1, dtype=np.int8)
+    margin = np.full(n, np.nan)
+    rc = lib.oracle_update_sites(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
+                                 int(sweep_index), int(mu), int(bool(prec32)),
+                                 _ptr(U, ctypes.c_double), _ptr(sites, ctypes.c_int64), n,
+                                 _ptr(out, ctypes.c_double), _ptr(tries, ctypes.c_int8),
+                                 _ptr(margin, ctypes.c_double))
+    if rc:
+        raise ValueError("oracle_update_sites rejected its arguments")
+    return out, tries, margin
 
 
 def sweep(dims, U, beta, seed, sweep_index, prec32=True):

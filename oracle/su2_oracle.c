@@ -24,6 +24,9 @@
  * counter, so the result does not depend on the split).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -280,6 +283,7 @@ int oracle_init(const int dims[4], uint64_t seed, int start, int prec32, double 
     geom_t g;
     if (geom_init(&g, dims)) return -1;
     if (start != 0 && start != 1) return -1;
+#pragma omp parallel for schedule(static)
     for (long lex = 0; lex < g.V; ++lex) {
         for (int mu = 0; mu < 4; ++mu) {
             double q[4] = { 1.0, 0.0, 0.0, 0.0 };
@@ -295,16 +299,51 @@ int oracle_init(const int dims[4], uint64_t seed, int start, int prec32, double 
 }
 
 /* ------------------------------------------------------------------------- */
-/* One heat-bath pass: every link U_mu(x) with parity(x) == parity.           */
+/* One link update U_mu(x), written to out[4] (U itself is not modified):     */
 /*   w = staple sum; alpha = beta |w|;                                        */
 /*   alpha == 0: the conditional is Haar, draw it (slot 9);                   */
 /*   else KP for x0; after 8 failures the link is kept;                       */
 /*   X = (x0, |a| n), V = w/|w|, U' = X V, normalised (Eqs. (5)-(7)).         */
-/* Per-site outputs (optional, indexed by lex): tries[lex] = attempt that     */
-/* accepted (0..7), 8 after a cap failure, 9 for the Haar branch;             */
-/* margin[lex] = the KP decision margin.  stats[0] += attempts evaluated,     */
-/* stats[1] += cap failures.                                                  */
+/* *tries = attempt that accepted (0..7), 8 after a cap failure, 9 for the    */
+/* Haar branch; *margin = the KP decision margin.                             */
 /* ------------------------------------------------------------------------- */
+static void update_one(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int mu,
+                       int prec32, const double *U, long lex, double out[4], int *tries,
+                       double *margin)
+{
+    double w[4];
+    oracle_staple(dims, U, lex, mu, w);
+    double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    double alpha = beta * k;
+    if (alpha == 0.0) {
+        double u[4], q[4];
+        draw4(seed, (uint32_t)lex, mu, PURPOSE_UPDATE, sweep, SLOT_HAAR, u);
+        haar_from_uniforms(u, q);
+        store_unit(out, q, prec32);
+        *tries = 9;
+        *margin = INFINITY;
+        return;
+    }
+    double a0, amag;
+    int t = oracle_kp_draw(alpha, seed, (uint32_t)lex, mu, sweep, prec32, &a0, &amag, margin);
+    if (t < 0) {
+        memcpy(out, link(U, lex, mu), 4 * sizeof(double));
+        *tries = 8;
+        return;
+    }
+    *tries = t;
+    double n[3];
+    direction(seed, (uint32_t)lex, mu, sweep, n);
+    double X[4] = { a0, amag * n[0], amag * n[1], amag * n[2] };
+    double V[4] = { w[0] / k, w[1] / k, w[2] / k, w[3] / k };
+    double Un[4];
+    oracle_qmul(X, V, Un);
+    store_unit(out, Un, prec32);
+}
+
+/* One heat-bath pass: every link U_mu(x) with parity(x) == parity, in place.
+ * Per-site outputs (optional, indexed by lex): tries[lex], margin[lex] as in
+ * update_one.  stats[0] += KP attempts evaluated, stats[1] += cap failures. */
 int oracle_pass(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int parity,
                 int mu, int prec32, double *U, int8_t *tries, double *margin, uint64_t stats[2])
 {
@@ -317,40 +356,41 @@ int oracle_pass(const int dims[4], double beta, uint64_t seed, uint32_t sweep, i
         int x[4];
         coords(&g, lex, x);
         if (((x[0] + x[1] + x[2] + x[3]) & 1) != parity) continue;
-        double w[4];
-        oracle_staple(dims, U, lex, mu, w);
-        double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
-        double alpha = beta * k;
-        double *dst = U + (lex * 4 + mu) * 4;
-        if (alpha == 0.0) {
-            double u[4], q[4];
-            draw4(seed, (uint32_t)lex, mu, PURPOSE_UPDATE, sweep, SLOT_HAAR, u);
-            haar_from_uniforms(u, q);
-            store_unit(dst, q, prec32);
-            if (tries) tries[lex] = 9;
-            if (margin) margin[lex] = INFINITY;
-            continue;
-        }
-        double a0, amag, m;
-        int t = oracle_kp_draw(alpha, seed, (uint32_t)lex, mu, sweep, prec32, &a0, &amag, &m);
-        if (margin) margin[lex] = m;
-        if (t < 0) {
-            attempts += 8;
-            failures += 1;
-            if (tries) tries[lex] = 8;
-            continue;
-        }
-        attempts += (uint64_t)t + 1;
+        double out[4], m;
+        int t;
+        update_one(dims, beta, seed, sweep, mu, prec32, U, lex, out, &t, &m);
+        /* the staples of this pass never read the links it writes (they are
+         * U_mu at the other parity, and U_nu with nu != mu), so writing in
+         * place is the same as writing to a copy */
+        memcpy(U + (lex * 4 + mu) * 4, out, sizeof out);
         if (tries) tries[lex] = (int8_t)t;
-        double n[3];
-        direction(seed, (uint32_t)lex, mu, sweep, n);
-        double X[4] = { a0, amag * n[0], amag * n[1], amag * n[2] };
-        double V[4] = { w[0] / k, w[1] / k, w[2] / k, w[3] / k };
-        double Un[4];
-        oracle_qmul(X, V, Un);
-        store_unit(dst, Un, prec32);
+        if (margin) margin[lex] = m;
+        if (t <= 7) attempts += (uint64_t)t + 1;
+        else if (t == 8) { attempts += 8; failures += 1; }
     }
     if (stats) { stats[0] += attempts; stats[1] += failures; }
+    return 0;
+}
+
+/* The update a pass would give the listed sites (all of one parity), without
+ * modifying U: out[i*4 .. i*4+3] for sites[i]; tries/margin optional. */
+int oracle_update_sites(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int mu,
+                        int prec32, const double *U, const int64_t *sites, long n, double *out,
+                        int8_t *tries, double *margin)
+{
+    geom_t g;
+    if (geom_init(&g, dims)) return -1;
+    if (mu < 0 || mu > 3 || !(beta >= 0.0)) return -1;
+    for (long i = 0; i < n; ++i)
+        if (sites[i] < 0 || sites[i] >= g.V) return -1;
+#pragma omp parallel for schedule(static)
+    for (long i = 0; i < n; ++i) {
+        double m;
+        int t;
+        update_one(dims, beta, seed, sweep, mu, prec32, U, (long)sites[i], out + 4 * i, &t, &m);
+        if (tries) tries[i] = (int8_t)t;
+        if (margin) margin[i] = m;
+    }
     return 0;
 }
 
@@ -438,4 +478,14 @@ int oracle_staple_action(const int dims[4], const double *U, double *out)
         }
     *out = s;
     return 0;
+}
+
+/* Threads the OpenMP loops of this file use (1 without OpenMP). */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }

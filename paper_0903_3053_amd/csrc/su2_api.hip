@@ -1,0 +1,463 @@
+// su2_api.hip -- the C ABI of libsu2.so (declared in include/su2.h): one
+// global lattice context, device-resident state, graph-replayed sweeps.
+//
+// Program model (Sec. 2.1): all data stay in GPU memory, every kernel is
+// launched by the host and does one complete operation, and results cross to
+// the host only when asked for.  A sweep is eight pass launches plus a one-lane
+// kernel that advances the device-resident sweep index, so the same captured
+// hipGraph replays any number of sweeps with no host round trip.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "su2.h"
+#include "su2_kernels.hpp"
+
+using namespace su2;
+
+namespace {
+
+constexpr int kGraphSweeps = 16;  // sweeps per replay of the large graph
+
+struct Context {
+    bool ready = false;
+    Geo g{};
+    Key key{};
+    double beta = 0.0;
+    uint64_t V = 0;
+    float4 *links = nullptr;
+    bool owns_links = false;
+    uint32_t *d_sweep = nullptr;        // device-resident sweep index
+    uint64_t sweep = 0;                 // host mirror
+    unsigned long long *d_counters = nullptr;  // per-wave (attempts, failures)
+    uint32_t n_waves = 0;
+    double2 *d_partials = nullptr;
+    double *d_out = nullptr;            // 3 doubles for scalar results
+    hipStream_t stream = nullptr;
+    hipGraphExec_t graph1 = nullptr;    // one sweep
+    hipGraphExec_t graphN = nullptr;    // kGraphSweeps sweeps
+};
+
+Context ctx;
+char last_error[512] = "no error";
+
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(last_error, sizeof last_error, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                     \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return fail(SU2_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+    } while (0)
+
+void release_graphs()
+{
+    if (ctx.graph1) hipGraphExecDestroy(ctx.graph1);
+    if (ctx.graphN) hipGraphExecDestroy(ctx.graphN);
+    ctx.graph1 = ctx.graphN = nullptr;
+}
+
+void release_all()
+{
+    if (ctx.stream || ctx.links) hipStreamSynchronize(ctx.stream);
+    release_graphs();
+    if (ctx.owns_links && ctx.links) hipFree(ctx.links);
+    if (ctx.d_sweep) hipFree(ctx.d_sweep);
+    if (ctx.d_counters) hipFree(ctx.d_counters);
+    if (ctx.d_partials) hipFree(ctx.d_partials);
+    if (ctx.d_out) hipFree(ctx.d_out);
+    hipStream_t keep = ctx.stream;
+    ctx = Context{};
+    ctx.stream = keep;
+}
+
+int check_dims(const int32_t dims[4], uint64_t *V)
+{
+    if (!dims) return fail(SU2_EINVAL, "dims is NULL");
+    uint64_t v = 1;
+    for (int d = 0; d < 4; ++d) {
+        if (dims[d] < 2 || (dims[d] & 1))
+            return fail(SU2_EINVAL, "dims[%d] = %d: every extent must be even and >= 2", d,
+                        dims[d]);
+        v *= (uint64_t)dims[d];
+        if (v >= (1ull << 32)) return fail(SU2_EINVAL, "lattice volume must be below 2^32");
+    }
+    *V = v;
+    return SU2_OK;
+}
+
+Geo make_geo(const int32_t dims[4], uint64_t V)
+{
+    Geo g{};
+    for (int d = 0; d < 4; ++d) g.L[d] = (uint32_t)dims[d];
+    g.H0 = g.L[0] / 2;
+    g.half = (uint32_t)(V / 2);
+    g.st[0] = 1;
+    g.st[1] = g.H0;
+    g.st[2] = g.H0 * g.L[1];
+    g.st[3] = g.H0 * g.L[1] * g.L[2];
+    g.dH0 = make_fastdiv(g.H0);
+    g.dL1 = make_fastdiv(g.L[1]);
+    g.dL2 = make_fastdiv(g.L[2]);
+    g.dL0 = make_fastdiv(g.L[0]);
+    return g;
+}
+
+int build_graph(int nsweeps, hipGraphExec_t *out)
+{
+    hipGraph_t graph;
+    HIP_TRY(hipGraphCreate(&graph, 0));
+    hipGraphNode_t prev = nullptr;
+    int rc = SU2_OK;
+    for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
+        // Sec. 2.4: odd sites for every direction, then even sites
+        for (int p = 1; p >= 0 && rc == SU2_OK; --p) {
+            for (int mu = 0; mu < 4; ++mu) {
+                PassLaunch pl = pass_launch(ctx.links, ctx.g, ctx.key, (float)ctx.beta,
+                                            (uint32_t)p, (uint32_t)mu, ctx.d_sweep,
+                                            ctx.d_counters);
+                pl.bind();
+                hipKernelNodeParams kp{};
+                kp.func = const_cast<void *>(pl.func);
+                kp.gridDim = pl.grid;
+                kp.blockDim = pl.block;
+                kp.sharedMemBytes = 0;
+                kp.kernelParams = pl.args;
+                kp.extra = nullptr;
+                hipGraphNode_t node;
+                hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr,
+                                                     prev ? 1 : 0, &kp);
+                if (e != hipSuccess) {
+                    rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+                    break;
+                }
+                prev = node;
+            }
+        }
+        if (rc != SU2_OK) break;
+        uint32_t *sp = ctx.d_sweep;
+        void *targs[1] = { &sp };
+        hipKernelNodeParams kt{};
+        kt.func = const_cast<void *>(tick_func());
+        kt.gridDim = dim3(1);
+        kt.blockDim = dim3(1);
+        kt.kernelParams = targs;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, graph, &prev, 1, &kt);
+        if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+        prev = node;
+    }
+    if (rc == SU2_OK) {
+        hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    hipGraphDestroy(graph);
+    return rc;
+}
+
+int require_ready()
+{
+    if (!ctx.ready) return fail(SU2_ESTATE, "no lattice: call su2_init first");
+    return SU2_OK;
+}
+
+int run_sweeps(int32_t n)
+{
+    if (!ctx.graph1) {
+        int rc = build_graph(1, &ctx.graph1);
+        if (rc) return rc;
+    }
+    if (n >= kGraphSweeps && !ctx.graphN) {
+        int rc = build_graph(kGraphSweeps, &ctx.graphN);
+        if (rc) return rc;
+    }
+    int32_t left = n;
+    while (left >= kGraphSweeps) {
+        HIP_TRY(hipGraphLaunch(ctx.graphN, ctx.stream));
+        left -= kGraphSweeps;
+    }
+    while (left-- > 0) HIP_TRY(hipGraphLaunch(ctx.graph1, ctx.stream));
+    ctx.sweep += (uint64_t)n;
+    return SU2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start, void *dev_links,
+                size_t bytes)
+{
+    uint64_t V;
+    int rc = check_dims(dims, &V);
+    if (rc) return rc;
+    if (!std::isfinite(beta) || beta < 0.0) return fail(SU2_EINVAL, "beta must be finite and >= 0");
+    if (start != SU2_COLD && start != SU2_HOT) return fail(SU2_EINVAL, "start must be 0 or 1");
+    const size_t link_bytes = (size_t)V * 4 * sizeof(float4);
+    if (dev_links) {
+        if (bytes < link_bytes)
+            return fail(SU2_EINVAL, "device buffer holds %zu bytes, %zu needed", bytes, link_bytes);
+        if ((uintptr_t)dev_links % 16)
+            return fail(SU2_EINVAL, "device buffer must be 16-byte aligned");
+    }
+    release_all();
+    ctx.g = make_geo(dims, V);
+    ctx.V = V;
+    ctx.beta = beta;
+    ctx.key = Key{ (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    ctx.n_waves = counter_waves(ctx.g);
+    const uint32_t nb = std::max(plaquette_blocks(ctx.g), polyakov_blocks(ctx.g));
+    if (dev_links) {
+        ctx.links = static_cast<float4 *>(dev_links);
+        ctx.owns_links = false;
+    } else {
+        if (hipMalloc(&ctx.links, link_bytes) != hipSuccess) {
+            hipGetLastError();
+            ctx.links = nullptr;
+            release_all();
+            return fail(SU2_ENOMEM, "cannot allocate %zu bytes of links", link_bytes);
+        }
+        ctx.owns_links = true;
+    }
+    if (hipMalloc(&ctx.d_sweep, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ctx.d_counters, (size_t)ctx.n_waves * 2 * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&ctx.d_partials, (size_t)nb * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&ctx.d_out, 3 * sizeof(double)) != hipSuccess) {
+        hipGetLastError();
+        release_all();
+        return fail(SU2_ENOMEM, "cannot allocate work buffers");
+    }
+    HIP_TRY(hipMemsetAsync(ctx.d_sweep, 0, sizeof(uint32_t), ctx.stream));
+    HIP_TRY(hipMemsetAsync(ctx.d_counters, 0, (size_t)ctx.n_waves * 2 * sizeof(unsigned long long),
+                           ctx.stream));
+    HIP_TRY(launch_init(ctx.links, ctx.g, ctx.key, start == SU2_HOT, ctx.stream));
+    ctx.sweep = 0;
+    ctx.ready = true;
+    return SU2_OK;
+}
+
+int su2_init(const int32_t dims[4], double beta, uint64_t seed, int32_t start)
+{
+    return su2_init_ex(dims, beta, seed, start, nullptr, 0);
+}
+
+int su2_sweep(int32_t n)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (n < 0) return fail(SU2_EINVAL, "n must be >= 0");
+    if (ctx.sweep + (uint64_t)n > 0xffffffffull)
+        return fail(SU2_EINVAL, "sweep index would pass 2^32 - 1");
+    return run_sweeps(n);
+}
+
+int su2_pass(int32_t parity, int32_t mu)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (parity < 0 || parity > 1 || mu < 0 || mu > 3)
+        return fail(SU2_EINVAL, "parity must be 0/1 and mu 0..3");
+    HIP_TRY(launch_pass(ctx.links, ctx.g, ctx.key, (float)ctx.beta, (uint32_t)parity,
+                        (uint32_t)mu, ctx.d_sweep, ctx.d_counters, ctx.stream));
+    return SU2_OK;
+}
+
+int su2_plaquette_st(double out[3])
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    HIP_TRY(launch_plaquette(ctx.links, ctx.g, ctx.d_partials, ctx.d_out, ctx.stream));
+    HIP_TRY(hipMemcpyAsync(out, ctx.d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    return SU2_OK;
+}
+
+double su2_plaquette(void)
+{
+    double o[3];
+    if (su2_plaquette_st(o) != SU2_OK) return NAN;
+    return o[0];
+}
+
+int su2_polyakov(double *out)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    double o[3];
+    HIP_TRY(launch_polyakov(ctx.links, ctx.g, ctx.d_partials, ctx.d_out, ctx.stream));
+    HIP_TRY(hipMemcpyAsync(o, ctx.d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    *out = o[0];
+    return SU2_OK;
+}
+
+int su2_measure_device(double *dev_out)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!dev_out || (uintptr_t)dev_out % 8) return fail(SU2_EINVAL, "dev_out must be 8-byte aligned device memory");
+    HIP_TRY(launch_plaquette(ctx.links, ctx.g, ctx.d_partials, dev_out, ctx.stream));
+    HIP_TRY(launch_polyakov(ctx.links, ctx.g, ctx.d_partials, dev_out + 3, ctx.stream));
+    return SU2_OK;
+}
+
+int su2_sweep_measure(int32_t n, int32_t every, double *host_hist)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (every < 1 || n < 0 || n % every) return fail(SU2_EINVAL, "need every >= 1 and n % every == 0");
+    if (!host_hist && n > 0) return fail(SU2_EINVAL, "host_hist is NULL");
+    if (ctx.sweep + (uint64_t)n > 0xffffffffull)
+        return fail(SU2_EINVAL, "sweep index would pass 2^32 - 1");
+    const int32_t m = n / every;
+    if (m == 0) return SU2_OK;
+    double *d_hist = nullptr;
+    if (hipMalloc(&d_hist, (size_t)m * 3 * sizeof(double)) != hipSuccess) {
+        hipGetLastError();
+        return fail(SU2_ENOMEM, "cannot allocate the measurement history");
+    }
+    for (int32_t i = 0; i < m && rc == SU2_OK; ++i) {
+        rc = run_sweeps(every);
+        if (rc == SU2_OK) {
+            hipError_t e = launch_plaquette(ctx.links, ctx.g, ctx.d_partials, d_hist + 3 * i, ctx.stream);
+            if (e != hipSuccess) rc = fail(SU2_EDEVICE, "plaquette launch: %s", hipGetErrorString(e));
+        }
+    }
+    if (rc == SU2_OK) {
+        hipError_t e = hipMemcpyAsync(host_hist, d_hist, (size_t)m * 3 * sizeof(double),
+                                      hipMemcpyDeviceToHost, ctx.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
+        if (e != hipSuccess) rc = fail(SU2_EDEVICE, "history copy: %s", hipGetErrorString(e));
+    }
+    hipStreamSynchronize(ctx.stream);
+    hipFree(d_hist);
+    return rc;
+}
+
+int su2_links(float *host_out, size_t n_floats)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!host_out) return fail(SU2_EINVAL, "host_out is NULL");
+    if (n_floats != (size_t)ctx.V * 16)
+        return fail(SU2_EINVAL, "n_floats = %zu, expected 16*V = %zu", n_floats, (size_t)ctx.V * 16);
+    float4 *stage = nullptr;
+    if (hipMalloc(&stage, n_floats * sizeof(float)) != hipSuccess) {
+        hipGetLastError();
+        return fail(SU2_ENOMEM, "cannot allocate the staging buffer");
+    }
+    hipError_t e = launch_pack(ctx.links, ctx.g, stage, ctx.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host_out, stage, n_floats * sizeof(float), hipMemcpyDeviceToHost, ctx.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
+    hipStreamSynchronize(ctx.stream);
+    hipFree(stage);
+    if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_links: %s", hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int su2_set_links(const float *host_in, size_t n_floats, uint64_t sweep_index)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!host_in) return fail(SU2_EINVAL, "host_in is NULL");
+    if (n_floats != (size_t)ctx.V * 16)
+        return fail(SU2_EINVAL, "n_floats = %zu, expected 16*V = %zu", n_floats, (size_t)ctx.V * 16);
+    if (sweep_index > 0xffffffffull) return fail(SU2_EINVAL, "sweep index must be below 2^32");
+    float4 *stage = nullptr;
+    if (hipMalloc(&stage, n_floats * sizeof(float)) != hipSuccess) {
+        hipGetLastError();
+        return fail(SU2_ENOMEM, "cannot allocate the staging buffer");
+    }
+    const uint32_t s32 = (uint32_t)sweep_index;
+    hipError_t e = hipMemcpyAsync(stage, host_in, n_floats * sizeof(float), hipMemcpyHostToDevice,
+                                  ctx.stream);
+    if (e == hipSuccess) e = launch_unpack(ctx.links, ctx.g, stage, ctx.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx.d_sweep, &s32, sizeof s32, hipMemcpyHostToDevice, ctx.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
+    hipStreamSynchronize(ctx.stream);
+    hipFree(stage);
+    if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_set_links: %s", hipGetErrorString(e));
+    ctx.sweep = sweep_index;
+    return SU2_OK;
+}
+
+int su2_sweep_index(uint64_t *out)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    *out = ctx.sweep;
+    return SU2_OK;
+}
+
+int su2_counters(uint64_t out[2])
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    std::vector<unsigned long long> h((size_t)ctx.n_waves * 2);
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx.d_counters, h.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, ctx.stream));
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    out[0] = out[1] = 0;
+    for (uint32_t w = 0; w < ctx.n_waves; ++w) {
+        out[0] += h[2 * w];
+        out[1] += h[2 * w + 1];
+    }
+    return SU2_OK;
+}
+
+int su2_set_stream(void *hip_stream)
+{
+    if (ctx.ready || ctx.stream) HIP_TRY(hipStreamSynchronize(ctx.stream));
+    ctx.stream = static_cast<hipStream_t>(hip_stream);
+    return SU2_OK;
+}
+
+int su2_philox(uint64_t seed, const uint32_t *ctr, size_t n, uint32_t *out)
+{
+    if (n == 0) return SU2_OK;
+    if (!ctr || !out) return fail(SU2_EINVAL, "NULL buffer");
+    if (n > (1u << 28)) return fail(SU2_EINVAL, "at most 2^28 blocks per call");
+    uint4 *d = nullptr;
+    if (hipMalloc(&d, 2 * n * sizeof(uint4)) != hipSuccess) {
+        hipGetLastError();
+        return fail(SU2_ENOMEM, "cannot allocate %zu blocks", n);
+    }
+    const Key key{ (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    hipError_t e = hipMemcpyAsync(d, ctr, n * sizeof(uint4), hipMemcpyHostToDevice, ctx.stream);
+    if (e == hipSuccess) e = launch_philox(d, (uint32_t)n, key, d + n, ctx.stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(out, d + n, n * sizeof(uint4), hipMemcpyDeviceToHost, ctx.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
+    hipStreamSynchronize(ctx.stream);
+    hipFree(d);
+    if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_philox: %s", hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int su2_synchronize(void)
+{
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    return SU2_OK;
+}
+
+const char *su2_last_error(void) { return last_error; }
+
+void su2_finalize(void) { release_all(); }
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+// su2_device.hpp -- device-side building blocks of the SU(2) heat-bath path on
+// gfx950: Philox-4x32-10, quaternion algebra of Eq. (4), checkerboard lattice
+// geometry, and the uniform / Haar / direction draws the update needs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace su2 {
+
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 (Salmon et al., SC'11).  Counter-based: nothing is stored,
+// each draw is a pure function of (key, counter) -- the paper's Sec. 2.2 point
+// that generating numbers inside the consumer, never storing them, is what
+// makes the generator fast.  The key words are wave-uniform, so the Weyl key
+// schedule stays on the scalar unit.
+// ---------------------------------------------------------------------------
+struct Key {
+    uint32_t lo, hi;
+};
+
+__device__ __forceinline__ uint4 philox(uint4 c, Key k)
+{
+    constexpr uint32_t kMulA = 0xD2511F53u, kMulB = 0xCD9E8D57u;
+    constexpr uint32_t kWeylA = 0x9E3779B9u, kWeylB = 0xBB67AE85u;
+    uint32_t ka = k.lo, kb = k.hi;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t pa = (uint64_t)kMulA * c.x;  // one v_mad_u64_u32 each
+        const uint64_t pb = (uint64_t)kMulB * c.z;
+        c = make_uint4((uint32_t)(pb >> 32) ^ c.y ^ ka, (uint32_t)pb,
+                       (uint32_t)(pa >> 32) ^ c.w ^ kb, (uint32_t)pa);
+        ka += kWeylA;
+        kb += kWeylB;
+    }
+    return c;
+}
+
+// top 24 bits of a word, as a uniform in (0, 1] -- exact in FP32
+__device__ __forceinline__ float unit24(uint32_t w)
+{
+    return (float)((w >> 8) + 1u) * 0x1p-24f;
+}
+
+enum : uint32_t { kPurposeUpdate = 0u, kPurposeHot = 1u, kPurposeImh = 2u };
+enum : uint32_t { kSlotDirection = 8u, kSlotHaar = 9u };
+
+__device__ __forceinline__ uint4 draw(Key k, uint32_t site, uint32_t mu, uint32_t purpose,
+                                      uint32_t sweep, uint32_t slot)
+{
+    return philox(make_uint4(site, mu | (purpose << 8), sweep, slot), k);
+}
+
+// ---------------------------------------------------------------------------
+// Quaternions U = u0 I + i sigma.u, Eq. (4), held in a float4 (x = u0).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float4 qmul(float4 a, float4 b)  // a b
+{
+    return make_float4(a.x * b.x - a.y * b.y - a.z * b.z - a.w * b.w,
+                       a.x * b.y + b.x * a.y - a.z * b.w + a.w * b.z,
+                       a.x * b.z + b.x * a.z - a.w * b.y + a.y * b.w,
+                       a.x * b.w + b.x * a.w - a.y * b.z + a.z * b.y);
+}
+
+__device__ __forceinline__ float4 qdag(float4 a) { return make_float4(a.x, -a.y, -a.z, -a.w); }
+
+__device__ __forceinline__ float4 qadd(float4 a, float4 b)
+{
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+
+__device__ __forceinline__ float qdot(float4 a, float4 b)  // (1/2) Re Tr(a b^dag)
+{
+    return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+}
+
+// Reunitarisation, Eq. (7): divide by the norm, summed in FP64.
+__device__ __forceinline__ float4 unitize(float4 q)
+{
+    const double n2 = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
+    const double inv = 1.0 / sqrt(n2);
+    return make_float4((float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv),
+                       (float)(q.w * inv));
+}
+
+// Haar-uniform unit quaternion from three uniforms (Shoemake 1992).
+__device__ __forceinline__ float4 haar(uint4 r)
+{
+    const float u0 = unit24(r.x), u1 = unit24(r.y), u2 = unit24(r.z);
+    const float ra = sqrtf(1.0f - u0), rb = sqrtf(u0);
+    float s1, c1, s2, c2;
+    sincospif(2.0f * u1, &s1, &c1);
+    sincospif(2.0f * u2, &s2, &c2);
+    return make_float4(ra * s1, ra * c1, rb * s2, rb * c2);
+}
+
+// ---------------------------------------------------------------------------
+// Unsigned division by a runtime-invariant divisor via a multiply-high
+// (Granlund & Montgomery, PLDI'94, the round-up method with a 33-bit
+// multiplier split as 2^32 + m): q = (t + ((n - t) >> s1)) >> s2.
+// ---------------------------------------------------------------------------
+struct FastDiv {
+    uint32_t d, m, s1, s2;
+};
+
+inline FastDiv make_fastdiv(uint32_t d)
+{
+    uint32_t l = 0;
+    while (l < 32 && (1ull << l) < d) ++l;  // l = ceil(log2 d)
+    FastDiv f;
+    f.d = d;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << l) - d)) / d + 1ull);
+    f.s1 = l < 1 ? l : 1u;
+    f.s2 = l > 1 ? l - 1u : 0u;
+    return f;
+}
+
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f)
+{
+    const uint32_t t = __umulhi(f.m, n);
+    return (t + ((n - t) >> f.s1)) >> f.s2;
+}
+
+// ---------------------------------------------------------------------------
+// Checkerboard geometry.  Links of direction mu on sites of parity p form one
+// contiguous array of V/2 float4, indexed by the half-site index
+// h = (x0 >> 1) + H0*(x1 + L1*(x2 + L2*x3)), H0 = L0/2: coalesced 16-byte
+// accesses along x0, and a pass touches whole arrays.  Array (mu, p) starts at
+// (2*mu + p) * V/2.
+// ---------------------------------------------------------------------------
+struct Geo {
+    uint32_t L[4];
+    uint32_t H0;       // L0 / 2
+    uint32_t half;     // V / 2
+    uint32_t st[4];    // half-index strides of x0 (pairs), x1, x2, x3: 1, H0, H0*L1, H0*L1*L2
+    FastDiv dH0, dL1, dL2, dL0;
+};
+
+struct Site {
+    uint32_t x[4];
+};
+
+// site of parity p with half index h
+__device__ __forceinline__ Site site_of(const Geo &g, uint32_t h, uint32_t p)
+{
+    Site s;
+    const uint32_t r = fdiv(h, g.dH0);
+    const uint32_t hx = h - r * g.H0;
+    const uint32_t r2 = fdiv(r, g.dL1);
+    s.x[1] = r - r2 * g.L[1];
+    s.x[3] = fdiv(r2, g.dL2);
+    s.x[2] = r2 - s.x[3] * g.L[2];
+    s.x[0] = 2u * hx + ((p + s.x[1] + s.x[2] + s.x[3]) & 1u);
+    return s;
+}
+
+__device__ __forceinline__ uint32_t lex_of(const Geo &g, const Site &s)
+{
+    return s.x[0] + g.L[0] * (s.x[1] + g.L[1] * (s.x[2] + g.L[2] * s.x[3]));
+}
+
+__device__ __forceinline__ uint32_t half_of(const Geo &g, const Site &s)
+{
+    return (s.x[0] >> 1) + s.x[1] * g.st[1] + s.x[2] * g.st[2] + s.x[3] * g.st[3];
+}
+
+__device__ __forceinline__ Site step(const Geo &g, Site s, int d, int dir)
+{
+    if (dir > 0)
+        s.x[d] = (s.x[d] + 1u == g.L[d]) ? 0u : s.x[d] + 1u;
+    else
+        s.x[d] = (s.x[d] == 0u) ? g.L[d] - 1u : s.x[d] - 1u;
+    return s;
+}
+
+__device__ __forceinline__ size_t arr(const Geo &g, uint32_t mu, uint32_t p)
+{
+    return (size_t)(2u * mu + p) * g.half;
+}
+
+}  // namespace su2

@@ -1,0 +1,405 @@
+// su2_kernels.hip -- gfx950 kernels of the SU(2) heat-bath sweep.
+//
+//   k_init       cold / hot lattice (Sec. 2.1: initialisation on the GPU)
+//   k_pass       one (parity, mu) pass: staple, Kennedy-Pendleton x0, direction,
+//                rotation, FP64-normed reunitarisation, store (Eqs. (5)-(7)).
+//                The paper's separate staple and update kernels and its staple
+//                buffer (Sec. 2.4) are fused: the staple stays in registers.
+//   k_tick       advances the device-resident sweep index (graph-friendly)
+//   k_plaquette  per-workgroup FP64 partial sums of spatial / temporal
+//                plaquettes (Sec. 2.4, Eq. (3))
+//   k_polyakov   per-workgroup FP64 partial sums of the Polyakov loop
+//   k_reduce     fixed-order FP64 reduction of the partials (deterministic)
+//   k_pack / k_unpack   device checkerboard layout <-> host [V][4][4]
+//   k_philox     raw generator blocks, for bit-exact checks
+#include "su2_kernels.hpp"
+
+namespace su2 {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_init(float4 *__restrict__ links, Geo g, Key key,
+                                                 int hot)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;  // half-site index
+    const uint32_t mu = blockIdx.y >> 1, p = blockIdx.y & 1u;  // one (mu, p) array per grid row
+    if (i >= g.half) return;
+    float4 q = make_float4(1.0f, 0.0f, 0.0f, 0.0f);
+    if (hot) {
+        const Site s = site_of(g, i, p);
+        q = haar(draw(key, lex_of(g, s), mu, kPurposeHot, 0u, 0u));
+    }
+    links[arr(g, mu, p) + i] = q;
+}
+
+// ---------------------------------------------------------------------------
+// Staple sum of Eq. (6) for U_mu(x), x of parity p, over the six plaquettes
+// that contain the link (all nu != mu).
+__device__ __forceinline__ float4 staple(const float4 *__restrict__ L, const Geo &g,
+                                         const Site &x, uint32_t h, uint32_t p, uint32_t mu)
+{
+    const uint32_t q = p ^ 1u;
+    const Site xpm = step(g, x, mu, +1);
+    const uint32_t h_pm = half_of(g, xpm);
+    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+    for (uint32_t nu = 0; nu < 4; ++nu) {
+        if (nu == mu) continue;
+        const uint32_t h_pn = half_of(g, step(g, x, nu, +1));
+        const uint32_t h_mn = half_of(g, step(g, x, nu, -1));
+        const uint32_t h_pm_mn = half_of(g, step(g, xpm, nu, -1));
+        const float4 a = L[arr(g, nu, p) + h];        // U_nu(x)
+        const float4 b = L[arr(g, mu, q) + h_pn];     // U_mu(x+nu)
+        const float4 c = L[arr(g, nu, q) + h_pm];     // U_nu(x+mu)
+        const float4 d = L[arr(g, nu, q) + h_mn];     // U_nu(x-nu)
+        const float4 e = L[arr(g, mu, q) + h_mn];     // U_mu(x-nu)
+        const float4 f = L[arr(g, nu, p) + h_pm_mn];  // U_nu(x+mu-nu)
+        w = qadd(w, qmul(qmul(a, b), qdag(c)));
+        w = qadd(w, qmul(qmul(qdag(d), e), f));
+    }
+    return w;
+}
+
+// lambda^2 of one Kennedy-Pendleton attempt; evaluated without contraction so
+// each operation rounds as written (the accept decision is taken in FP32)
+__device__ __forceinline__ float kp_lambda2(float u0, float u1, float u2, float alpha)
+{
+#pragma clang fp contract(off)
+    const float c = cospif(2.0f * u1);
+    const float num = logf(u0) + c * c * logf(u2);
+    return -num / (2.0f * alpha);
+}
+
+__device__ __forceinline__ bool kp_accept(float u3, float lam2)
+{
+#pragma clang fp contract(off)
+    return u3 * u3 <= 1.0f - lam2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, Key key,
+                                                 float beta, uint32_t p, uint32_t mu,
+                                                 const uint32_t *__restrict__ sweep_ptr,
+                                                 unsigned long long *__restrict__ counters)
+{
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = h < g.half;
+    const uint32_t s = *sweep_ptr;  // wave-uniform scalar load
+    Site x{};
+    uint32_t lex = 0;
+    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid) {
+        x = site_of(g, h, p);
+        lex = lex_of(g, x);
+        w = staple(L, g, x, h, p, mu);
+    }
+    const float k = sqrtf(qdot(w, w));
+    const float alpha = beta * k;
+    const bool haar_branch = valid && alpha == 0.0f;
+    bool done = !valid || haar_branch;
+    float lam2 = 0.0f;
+    unsigned long long attempts = 0;
+    for (uint32_t t = 0; t < 8u; ++t) {
+        const unsigned long long pending = __ballot(!done);
+        if (pending == 0ull) break;
+        attempts += __popcll(pending);
+        if (!done) {
+            const uint4 r = draw(key, lex, mu, kPurposeUpdate, s, t);
+            const float l = kp_lambda2(unit24(r.x), unit24(r.y), unit24(r.z), alpha);
+            if (kp_accept(unit24(r.w), l)) {
+                done = true;
+                lam2 = l;
+            }
+        }
+    }
+    const bool failed = valid && !done;
+    const unsigned long long failures = __popcll(__ballot(failed));
+    if (valid && !failed) {
+        float4 un;
+        if (haar_branch) {
+            un = unitize(haar(draw(key, lex, mu, kPurposeUpdate, s, kSlotHaar)));
+        } else {
+            const uint4 r = draw(key, lex, mu, kPurposeUpdate, s, kSlotDirection);
+            const float cz = 2.0f * unit24(r.x) - 1.0f;
+            float sphi, cphi;
+            sincospif(2.0f * unit24(r.y), &sphi, &cphi);
+            const float sn = sqrtf(1.0f - cz * cz);
+            const float a0 = 1.0f - 2.0f * lam2;
+            const float am = 2.0f * sqrtf(lam2 * (1.0f - lam2));
+            const float4 X = make_float4(a0, am * sn * cphi, am * sn * sphi, am * cz);
+            const float ik = 1.0f / k;
+            const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
+            un = unitize(qmul(X, V));
+        }
+        L[arr(g, mu, p) + h] = un;
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+        counters[2 * wave] += attempts;
+        counters[2 * wave + 1] += failures;
+    }
+}
+
+__global__ void k_tick(uint32_t *sweep_ptr)
+{
+    if (threadIdx.x == 0) *sweep_ptr += 1u;
+}
+
+// ---------------------------------------------------------------------------
+// Block-level FP64 sum of two values: wave butterflies, then waves in order.
+__device__ __forceinline__ double2 block_sum2(double a, double b)
+{
+    __shared__ double sh[2][kBlock / kWave];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        sh[0][wv] = a;
+        sh[1][wv] = b;
+    }
+    __syncthreads();
+    double2 r = make_double2(0.0, 0.0);
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < kBlock / kWave; ++i) {
+            r.x += sh[0][i];
+            r.y += sh[1][i];
+        }
+    }
+    return r;
+}
+
+// One site per lane (index over both parities); the six plaquettes whose
+// corner is x, split spatial (nu < 3) / temporal (nu == 3).
+__global__ __launch_bounds__(kBlock) void k_plaquette(const float4 *__restrict__ L, Geo g,
+                                                      double2 *__restrict__ partials)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    double ps = 0.0, pt = 0.0;
+    if (i < 2u * g.half) {
+        const uint32_t p = i >= g.half ? 1u : 0u;
+        const uint32_t h = i - p * g.half;
+        const uint32_t q = p ^ 1u;
+        const Site x = site_of(g, h, p);
+        float4 u[4];
+        uint32_t hn[4];
+#pragma unroll
+        for (uint32_t mu = 0; mu < 4; ++mu) {
+            u[mu] = L[arr(g, mu, p) + h];
+            hn[mu] = half_of(g, step(g, x, mu, +1));
+        }
+#pragma unroll
+        for (uint32_t mu = 0; mu < 4; ++mu) {
+#pragma unroll
+            for (uint32_t nu = mu + 1; nu < 4; ++nu) {
+                // U_mu(x) U_nu(x+mu) . [U_nu(x) U_mu(x+nu)]^dag
+                const float4 a = qmul(u[mu], L[arr(g, nu, q) + hn[mu]]);
+                const float4 b = qmul(u[nu], L[arr(g, mu, q) + hn[nu]]);
+                const double v = (double)qdot(a, b);
+                if (nu == 3) pt += v; else ps += v;
+            }
+        }
+    }
+    const double2 r = block_sum2(ps, pt);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// One spatial site per lane: ordered product of U_3(x, t), t = 0..L3-1.
+__global__ __launch_bounds__(kBlock) void k_polyakov(const float4 *__restrict__ L, Geo g,
+                                                     uint32_t vs, double2 *__restrict__ partials)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    double acc = 0.0;
+    if (i < vs) {
+        const uint32_t x0 = i % g.L[0];
+        const uint32_t r = i / g.L[0];
+        const uint32_t x1 = r % g.L[1];
+        const uint32_t x2 = r / g.L[1];
+        float4 P = make_float4(1.f, 0.f, 0.f, 0.f);
+        for (uint32_t t = 0; t < g.L[3]; ++t) {
+            const uint32_t p = (x0 + x1 + x2 + t) & 1u;
+            const uint32_t h = (x0 >> 1) + x1 * g.st[1] + x2 * g.st[2] + t * g.st[3];
+            P = qmul(P, L[arr(g, 3, p) + h]);
+        }
+        acc = (double)P.x;
+    }
+    const double2 r = block_sum2(acc, 0.0);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+// Single workgroup: thread j sums partials j, j+256, ... in order, then a
+// fixed tree.  Mode 0 (plaquette): out[0] = (a*sa + b*sb)/2, out[1] = a*sa,
+// out[2] = b*sb.  Mode 1 (single value): out[0] = a*sa.
+__global__ __launch_bounds__(kBlock) void k_reduce(const double2 *__restrict__ partials,
+                                                   uint32_t n, double sa, double sb, int mode,
+                                                   double *__restrict__ out)
+{
+    __shared__ double sh[2][kBlock];
+    double a = 0.0, b = 0.0;
+    for (uint32_t j = threadIdx.x; j < n; j += kBlock) {
+        a += partials[j].x;
+        b += partials[j].y;
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int off = kBlock / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const double A = sh[0][0] * sa, B = sh[1][0] * sb;
+        if (mode == 0) {
+            out[0] = 0.5 * (A + B);
+            out[1] = A;
+            out[2] = B;
+        } else {
+            out[0] = A;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_pack(const float4 *__restrict__ L, Geo g,
+                                                 float4 *__restrict__ host_layout)
+{
+    const uint32_t lex = blockIdx.x * kBlock + threadIdx.x;
+    if (lex >= 2u * g.half) return;
+    Site s;
+    uint32_t r = lex;
+    s.x[0] = r % g.L[0]; r /= g.L[0];
+    s.x[1] = r % g.L[1]; r /= g.L[1];
+    s.x[2] = r % g.L[2];
+    s.x[3] = r / g.L[2];
+    const uint32_t p = (s.x[0] + s.x[1] + s.x[2] + s.x[3]) & 1u;
+    const uint32_t h = half_of(g, s);
+#pragma unroll
+    for (uint32_t mu = 0; mu < 4; ++mu) host_layout[(size_t)lex * 4 + mu] = L[arr(g, mu, p) + h];
+}
+
+__global__ __launch_bounds__(kBlock) void k_unpack(float4 *__restrict__ L, Geo g,
+                                                   const float4 *__restrict__ host_layout)
+{
+    const uint32_t lex = blockIdx.x * kBlock + threadIdx.x;
+    if (lex >= 2u * g.half) return;
+    Site s;
+    uint32_t r = lex;
+    s.x[0] = r % g.L[0]; r /= g.L[0];
+    s.x[1] = r % g.L[1]; r /= g.L[1];
+    s.x[2] = r % g.L[2];
+    s.x[3] = r / g.L[2];
+    const uint32_t p = (s.x[0] + s.x[1] + s.x[2] + s.x[3]) & 1u;
+    const uint32_t h = half_of(g, s);
+#pragma unroll
+    for (uint32_t mu = 0; mu < 4; ++mu) L[arr(g, mu, p) + h] = host_layout[(size_t)lex * 4 + mu];
+}
+
+__global__ __launch_bounds__(kBlock) void k_philox(const uint4 *__restrict__ ctr, uint32_t n,
+                                                   Key key, uint4 *__restrict__ out)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) out[i] = philox(ctr[i], key);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side)
+// ---------------------------------------------------------------------------
+static inline uint32_t blocks_for(size_t n) { return (uint32_t)((n + kBlock - 1) / kBlock); }
+
+hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st)
+{
+    dim3 grid(blocks_for(g.half), 8);
+    hipLaunchKernelGGL(k_init, grid, dim3(kBlock), 0, st, links, g, key, hot);
+    return hipGetLastError();
+}
+
+PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
+                       const uint32_t *sweep_ptr, unsigned long long *counters)
+{
+    PassLaunch pl;
+    pl.func = reinterpret_cast<const void *>(&k_pass);
+    pl.grid = dim3(blocks_for(g.half));
+    pl.block = dim3(kBlock);
+    pl.links = links;
+    pl.g = g;
+    pl.key = key;
+    pl.beta = beta;
+    pl.p = p;
+    pl.mu = mu;
+    pl.sweep_ptr = sweep_ptr;
+    pl.counters = counters;
+    pl.bind();
+    return pl;
+}
+
+const void *tick_func() { return reinterpret_cast<const void *>(&k_tick); }
+
+hipError_t launch_pass(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
+                       const uint32_t *sweep_ptr, unsigned long long *counters, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pass, dim3(blocks_for(g.half)), dim3(kBlock), 0, st, links, g, key, beta,
+                       p, mu, sweep_ptr, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, st, sweep_ptr);
+    return hipGetLastError();
+}
+
+uint32_t plaquette_blocks(const Geo &g) { return blocks_for(2ull * g.half); }
+uint32_t polyakov_blocks(const Geo &g)
+{
+    return blocks_for((size_t)g.L[0] * g.L[1] * g.L[2]);
+}
+uint32_t counter_waves(const Geo &g) { return blocks_for(g.half) * (kBlock / kWave); }
+
+hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials, double *out,
+                            hipStream_t st)
+{
+    const uint32_t nb = plaquette_blocks(g);
+    hipLaunchKernelGGL(k_plaquette, dim3(nb), dim3(kBlock), 0, st, links, g, partials);
+    const double scale = 1.0 / (3.0 * 2.0 * (double)g.half);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nb, scale, scale, 0, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials, double *out,
+                           hipStream_t st)
+{
+    const uint32_t vs = g.L[0] * g.L[1] * g.L[2];
+    const uint32_t nb = polyakov_blocks(g);
+    hipLaunchKernelGGL(k_polyakov, dim3(nb), dim3(kBlock), 0, st, links, g, vs, partials);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nb, 1.0 / (double)vs, 0.0,
+                       1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack(const float4 *links, const Geo &g, float4 *stage, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_pack, dim3(blocks_for(2ull * g.half)), dim3(kBlock), 0, st, links, g,
+                       stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpack(float4 *links, const Geo &g, const float4 *stage, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_unpack, dim3(blocks_for(2ull * g.half)), dim3(kBlock), 0, st, links, g,
+                       stage);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox(const uint4 *ctr, uint32_t n, Key key, uint4 *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_philox, dim3(blocks_for(n)), dim3(kBlock), 0, st, ctr, n, key, out);
+    return hipGetLastError();
+}
+
+}  // namespace su2

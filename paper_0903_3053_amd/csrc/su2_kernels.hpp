@@ -1,0 +1,53 @@
+// su2_kernels.hpp -- host-side launchers of the lattice kernels.
+#pragma once
+
+#include "su2_device.hpp"
+
+namespace su2 {
+
+// Arguments of one k_pass launch, kept together so a graph node can point at them.
+struct PassLaunch {
+    const void *func;
+    dim3 grid, block;
+    float4 *links;
+    Geo g;
+    Key key;
+    float beta;
+    uint32_t p, mu;
+    const uint32_t *sweep_ptr;
+    unsigned long long *counters;
+    void *args[8];
+    // point args at this object's own fields (call after every copy)
+    void bind()
+    {
+        args[0] = &links;
+        args[1] = &g;
+        args[2] = &key;
+        args[3] = &beta;
+        args[4] = &p;
+        args[5] = &mu;
+        args[6] = &sweep_ptr;
+        args[7] = &counters;
+    }
+};
+
+hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st);
+hipError_t launch_pass(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
+                       const uint32_t *sweep_ptr, unsigned long long *counters, hipStream_t st);
+hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st);
+PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
+                       const uint32_t *sweep_ptr, unsigned long long *counters);
+const void *tick_func();
+
+uint32_t plaquette_blocks(const Geo &g);
+uint32_t polyakov_blocks(const Geo &g);
+uint32_t counter_waves(const Geo &g);
+hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials, double *out,
+                            hipStream_t st);
+hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials, double *out,
+                           hipStream_t st);
+hipError_t launch_pack(const float4 *links, const Geo &g, float4 *stage, hipStream_t st);
+hipError_t launch_unpack(float4 *links, const Geo &g, const float4 *stage, hipStream_t st);
+hipError_t launch_philox(const uint4 *ctr, uint32_t n, Key key, uint4 *out, hipStream_t st);
+
+}  // namespace su2

@@ -1,0 +1,226 @@
+"""Thin ctypes binding of libsu2.so (include/su2.h): the same entry points,
+argument marshalling only.  Every step of the path runs in the library's HIP
+kernels; there is no fallback, and a missing library raises.
+
+PyTorch supplies device memory and streams: by default the link field is a
+torch CUDA tensor handed to su2_init_ex, and set_stream() accepts a
+torch.cuda.Stream.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libsu2.so")
+
+SU2_OK, SU2_EINVAL, SU2_ESTATE, SU2_ENOMEM, SU2_EDEVICE = 0, -1, -2, -3, -4
+COLD, HOT = 0, 1
+
+# every symbol include/su2.h declares
+EXPORTS = (
+    "su2_init", "su2_init_ex", "su2_sweep", "su2_pass", "su2_plaquette", "su2_plaquette_st",
+    "su2_polyakov", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
+    "su2_counters", "su2_set_stream", "su2_philox", "su2_synchronize", "su2_last_error",
+    "su2_finalize",
+)
+
+
+class Su2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"su2 error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_keep = {}  # torch objects the library points into
+
+
+def load():
+    """Load libsu2.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise ImportError(f"{LIBPATH} is missing: build it with paper_0903_3053_amd/build.py")
+    # PyTorch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+    # Importing torch first makes libsu2.so bind to that already-loaded copy, so
+    # the process holds one HIP runtime and torch memory/streams are valid here.
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIBPATH)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    dp = ctypes.POINTER(ctypes.c_double)
+    fp = ctypes.POINTER(ctypes.c_float)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    sig = {
+        "su2_init": ([i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32], ctypes.c_int),
+        "su2_init_ex": ([i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
+                         ctypes.c_size_t], ctypes.c_int),
+        "su2_sweep": ([ctypes.c_int32], ctypes.c_int),
+        "su2_pass": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "su2_plaquette": ([], ctypes.c_double),
+        "su2_plaquette_st": ([dp], ctypes.c_int),
+        "su2_polyakov": ([dp], ctypes.c_int),
+        "su2_measure_device": ([ctypes.c_void_p], ctypes.c_int),
+        "su2_sweep_measure": ([ctypes.c_int32, ctypes.c_int32, dp], ctypes.c_int),
+        "su2_links": ([fp, ctypes.c_size_t], ctypes.c_int),
+        "su2_set_links": ([fp, ctypes.c_size_t, ctypes.c_uint64], ctypes.c_int),
+        "su2_sweep_index": ([u64p], ctypes.c_int),
+        "su2_counters": ([u64p], ctypes.c_int),
+        "su2_set_stream": ([ctypes.c_void_p], ctypes.c_int),
+        "su2_philox": ([ctypes.c_uint64, u32p, ctypes.c_size_t, u32p], ctypes.c_int),
+        "su2_synchronize": ([], ctypes.c_int),
+        "su2_last_error": ([], ctypes.c_char_p),
+        "su2_finalize": ([], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != SU2_OK:
+        raise Su2Error(rc, _lib.su2_last_error().decode())
+    return rc
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _dims(dims):
+    d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
+    if d.shape != (4,):
+        raise ValueError("dims must have 4 entries")
+    return d
+
+
+def su2_init(dims, beta, seed, start, torch_memory=True):
+    """Create the lattice.  With torch_memory the link field is a torch CUDA
+    tensor of 16*V float32 (kept alive here); otherwise the library allocates."""
+    lib = load()
+    d = _dims(dims)
+    V = int(np.prod(d.astype(np.int64)))
+    if torch_memory:
+        import torch
+        buf = torch.empty(16 * V, dtype=torch.float32, device="cuda")
+        _keep["links"] = buf
+        _check(lib.su2_init_ex(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
+                               int(start), ctypes.c_void_p(buf.data_ptr()), buf.numel() * 4))
+    else:
+        _keep.pop("links", None)
+        _check(lib.su2_init(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
+                            int(start)))
+    _keep["dims"] = tuple(int(x) for x in d)
+
+
+def su2_init_ex(dims, beta, seed, start, dev_ptr, nbytes):
+    lib = load()
+    d = _dims(dims)
+    _check(lib.su2_init_ex(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
+                           int(start), ctypes.c_void_p(dev_ptr), int(nbytes)))
+    _keep["dims"] = tuple(int(x) for x in d)
+
+
+def su2_sweep(n=1):
+    _check(load().su2_sweep(int(n)))
+
+
+def su2_pass(parity, mu):
+    _check(load().su2_pass(int(parity), int(mu)))
+
+
+def su2_plaquette():
+    v = load().su2_plaquette()
+    if np.isnan(v):
+        raise Su2Error(-1, _lib.su2_last_error().decode())
+    return v
+
+
+def su2_plaquette_st():
+    out = np.zeros(3)
+    _check(load().su2_plaquette_st(_ptr(out, ctypes.c_double)))
+    return out
+
+
+def su2_polyakov():
+    out = ctypes.c_double(np.nan)
+    _check(load().su2_polyakov(ctypes.byref(out)))
+    return out.value
+
+
+def su2_measure_device(dev_out):
+    """Enqueue (P, P_s, P_t, Polyakov) into 4 doubles of device memory:
+    a torch float64 CUDA tensor (its first 4 elements) or a raw address."""
+    ptr = dev_out.data_ptr() if hasattr(dev_out, "data_ptr") else int(dev_out)
+    _check(load().su2_measure_device(ctypes.c_void_p(ptr)))
+
+
+def su2_sweep_measure(n, every=1):
+    m = int(n) // int(every) if every > 0 else 0
+    hist = np.zeros((max(m, 1), 3))
+    _check(load().su2_sweep_measure(int(n), int(every), _ptr(hist, ctypes.c_double)))
+    return hist[:m]
+
+
+def su2_links():
+    """Links as float32 [V, 4, 4] (site lex, direction, component)."""
+    dims = _keep.get("dims")
+    if dims is None:
+        raise Su2Error(SU2_ESTATE, "no lattice")
+    V = int(np.prod(dims))
+    out = np.empty((V, 4, 4), dtype=np.float32)
+    _check(load().su2_links(_ptr(out, ctypes.c_float), out.size))
+    return out
+
+
+def su2_set_links(U, sweep_index):
+    U = np.ascontiguousarray(U, dtype=np.float32)
+    _check(load().su2_set_links(_ptr(U, ctypes.c_float), U.size, ctypes.c_uint64(sweep_index)))
+
+
+def su2_sweep_index():
+    out = ctypes.c_uint64(0)
+    _check(load().su2_sweep_index(ctypes.byref(out)))
+    return out.value
+
+
+def su2_counters():
+    out = np.zeros(2, dtype=np.uint64)
+    _check(load().su2_counters(_ptr(out, ctypes.c_uint64)))
+    return int(out[0]), int(out[1])
+
+
+def su2_set_stream(stream=None):
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    ptr = 0
+    if stream is not None:
+        ptr = getattr(stream, "cuda_stream", stream)
+        _keep["stream"] = stream
+    _check(load().su2_set_stream(ctypes.c_void_p(int(ptr)) if ptr else None))
+
+
+def su2_philox(seed, counters):
+    c = np.ascontiguousarray(np.asarray(counters, dtype=np.uint32).reshape(-1, 4))
+    out = np.zeros_like(c)
+    _check(load().su2_philox(ctypes.c_uint64(seed), _ptr(c, ctypes.c_uint32), len(c),
+                             _ptr(out, ctypes.c_uint32)))
+    return out
+
+
+def su2_synchronize():
+    _check(load().su2_synchronize())
+
+
+def su2_last_error():
+    return load().su2_last_error().decode()
+
+
+def su2_finalize():
+    load().su2_finalize()
+    _keep.pop("links", None)
+    _keep.pop("dims", None)

@@ -1,0 +1,106 @@
+"""Statistical checks of configurations produced by the HIP path against what
+the mathematics fixes (independent of the oracle): Haar at beta = 0, strong
+coupling, and the heat-bath equilibrium identity; and long-run plaquettes
+against the oracle's stored histories within 3 sigma."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import su2_np
+from exact_density import haar_cdf, mean_x0
+from parity import UNIT_TOL, unitarity_error
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_0903_3053_amd import su2
+    su2.load()
+    yield su2
+    su2.su2_finalize()
+
+
+def binned(x, nbins=16):
+    """Mean and its standard error from nbins consecutive bins (bins longer
+    than the autocorrelation time make the bin means independent)."""
+    x = np.asarray(x, dtype=np.float64)
+    b = len(x) // nbins
+    m = x[: b * nbins].reshape(nbins, b).mean(axis=1)
+    return float(m.mean()), float(m.std(ddof=1) / np.sqrt(nbins))
+
+
+def test_beta_zero_is_haar(lib):
+    from scipy import stats
+    dims = (8, 8, 8, 8)
+    lib.su2_init(dims, 0.0, 3, lib.COLD)
+    lib.su2_sweep(1)
+    q = lib.su2_links().reshape(-1, 4).astype(np.float64)
+    for c in range(4):
+        assert stats.kstest(q[:, c], haar_cdf).pvalue > 1e-3
+    hist = lib.su2_sweep_measure(50, 1)
+    sigma = 0.5 / np.sqrt(6 * 8**4 * 50)
+    assert abs(hist[:, 0].mean()) < 4 * sigma
+
+
+def test_strong_coupling(lib):
+    """<P> = I2(beta)/I1(beta) + O(beta^5) at beta = 0.1."""
+    lib.su2_init((16, 16, 16, 16), 0.1, 5, lib.HOT)
+    lib.su2_sweep(50)
+    hist = lib.su2_sweep_measure(800, 1)
+    m, se = binned(hist[:, 0])
+    print(f"strong coupling: <P> = {m:.6f} +- {se:.6f}, I2/I1 = {mean_x0(0.1):.6f}")
+    assert abs(m - mean_x0(0.1)) < 4 * se
+
+
+def test_equilibrium_identity(lib):
+    """Heat-bath equilibrium: 6<P> = <mean over links of k I2(beta k)/I1(beta k)>,
+    k = |staple| -- staples computed test-side with 2x2 matrices from the GPU's
+    configurations."""
+    dims, beta = (8, 8, 8, 8), 2.3
+    lib.su2_init(dims, beta, 7, lib.HOT)
+    lib.su2_sweep(100)
+    D = []
+    for _ in range(160):
+        lib.su2_sweep(1)
+        U = lib.su2_links().astype(np.float64)
+        k = np.linalg.norm(su2_np.staples(U, dims), axis=2)
+        D.append(6 * su2_np.plaquette(U, dims)[0] - np.mean(k * mean_x0(beta * k)))
+    m, se = binned(D)
+    print(f"equilibrium identity at beta 2.3: <D> = {m:.2e} +- {se:.2e}")
+    assert abs(m) < 4 * se
+    assert unitarity_error(U) <= UNIT_TOL
+
+
+def test_long_run_32x32x32x32_vs_oracle(lib):
+    """32^4 hot start, beta in {2.2, 2.3, 2.4, 2.5}, 1000 sweeps: the GPU's
+    mean plaquette over sweeps 200-999 agrees with the oracle's stored chain
+    within 3 sigma (binned errors of both)."""
+    path = os.path.join(HERE, "golden", "oracle_su2_32x32x32x32_hot.json")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle histories not generated")
+    ref = json.load(open(path))
+    dims = tuple(ref["dims"])
+    for run in ref["runs"]:
+        h_o = np.asarray(run["history"])
+        n = len(h_o)
+        lib.su2_init(dims, run["beta"], ref["seed"], lib.HOT)
+        h_g = lib.su2_sweep_measure(n, 1)
+        att, fail = lib.su2_counters()
+        cut = n // 5
+        for col, name in ((0, "P"), (1, "P_s"), (2, "P_t")):
+            mg, sg = binned(h_g[cut:, col])
+            mo, so = binned(h_o[cut:, col])
+            z = (mg - mo) / np.hypot(sg, so)
+            print(f"32^4 beta {run['beta']}: {name} gpu {mg:.6f}+-{sg:.6f} oracle {mo:.6f}+-{so:.6f} "
+                  f"z = {z:+.2f}")
+            assert abs(z) < 3.0
+        upd = 4 * int(np.prod(dims)) * n
+        print(f"   KP attempts/update gpu {att / upd:.5f} oracle {run['attempts'] / upd:.5f}")
+        assert abs(att / upd - run["attempts"] / upd) < 2e-3
+        assert np.all(np.isfinite(h_g))

@@ -186,3 +186,16 @@ def test_equilibrium_identity():
     m, se = _binned_mean(D)
     assert abs(m) < 4 * se, (m, se)
     assert se < 0.01
+
+
+def test_update_sites_equals_pass():
+    dims = (4, 6, 4, 2)
+    U = su2_inputs.random_links(dims, 12).astype(np.float64)
+    x = np.array(np.unravel_index(np.arange(U.shape[0]), dims[::-1]))
+    par = x.sum(axis=0) % 2
+    sites = np.flatnonzero(par == 1)[::3]
+    out, tries, _ = oracle.update_sites(dims, U, 2.2, SEED, 4, 3, sites)
+    U2 = U.copy()
+    res = oracle.heatbath_pass(dims, U2, 2.2, SEED, 4, 1, 3)
+    np.testing.assert_array_equal(out, U2[sites, 3])
+    np.testing.assert_array_equal(tries, res.tries[sites])

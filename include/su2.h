@@ -72,6 +72,16 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
  * Philox counters advances by one per sweep.  Asynchronous. */
 int su2_sweep(int32_t n);
 
+/* As su2_sweep (n >= 1), and the last sweep also measures: its even-parity
+ * passes for mu = 1, 2, 3 add dot(U_new, staple_nu) for nu < mu, which over
+ * the three passes is every plaquette (Eq. (3)) of the resulting
+ * configuration exactly once.  The next su2_plaquette / su2_plaquette_st /
+ * su2_measure_device then only reduces those partials instead of re-reading
+ * the lattice (any call that changes the links discards them).  This is the
+ * paper's working sweep with its measuring kernel (Sec. 2.1, Sec. 2.4) with
+ * the measurement folded into the update. */
+int su2_sweep_measured(int32_t n);
+
 /* One pass: the links U_mu(x) with parity(x) == parity (0 or 1), mu in 0..3,
  * at the current sweep index (which does not advance). */
 int su2_pass(int32_t parity, int32_t mu);

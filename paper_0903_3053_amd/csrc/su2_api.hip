@@ -34,11 +34,15 @@ struct Context {
     uint64_t sweep = 0;                 // host mirror
     unsigned long long *d_counters = nullptr;  // per-wave (attempts, failures)
     uint32_t n_waves = 0;
-    double2 *d_partials = nullptr;
+    double2 *d_partials = nullptr;      // per-workgroup partial sums of a measurement
+    double2 *d_meas = nullptr;          // plaquette partials written by a measured sweep
+    double2 *d_scratch = nullptr;       // first-level reduction results
     double *d_out = nullptr;            // 3 doubles for scalar results
+    bool meas_fresh = false;            // d_meas holds the plaquette of the current links
     hipStream_t stream = nullptr;
     hipGraphExec_t graph1 = nullptr;    // one sweep
     hipGraphExec_t graphN = nullptr;    // kGraphSweeps sweeps
+    hipGraphExec_t graphM = nullptr;    // one sweep that also measures the plaquette
 };
 
 Context ctx;
@@ -64,7 +68,8 @@ void release_graphs()
 {
     if (ctx.graph1) hipGraphExecDestroy(ctx.graph1);
     if (ctx.graphN) hipGraphExecDestroy(ctx.graphN);
-    ctx.graph1 = ctx.graphN = nullptr;
+    if (ctx.graphM) hipGraphExecDestroy(ctx.graphM);
+    ctx.graph1 = ctx.graphN = ctx.graphM = nullptr;
 }
 
 void release_all()
@@ -75,6 +80,8 @@ void release_all()
     if (ctx.d_sweep) hipFree(ctx.d_sweep);
     if (ctx.d_counters) hipFree(ctx.d_counters);
     if (ctx.d_partials) hipFree(ctx.d_partials);
+    if (ctx.d_meas) hipFree(ctx.d_meas);
+    if (ctx.d_scratch) hipFree(ctx.d_scratch);
     if (ctx.d_out) hipFree(ctx.d_out);
     hipStream_t keep = ctx.stream;
     ctx = Context{};
@@ -106,6 +113,7 @@ Geo make_geo(const int32_t dims[4], uint64_t V)
     g.st[1] = g.H0;
     g.st[2] = g.H0 * g.L[1];
     g.st[3] = g.H0 * g.L[1] * g.L[2];
+    for (int d = 0; d < 4; ++d) g.wrap[d] = (g.L[d] - 1) * g.st[d];
     g.dH0 = make_fastdiv(g.H0);
     g.dL1 = make_fastdiv(g.L[1]);
     g.dL2 = make_fastdiv(g.L[2]);
@@ -113,7 +121,7 @@ Geo make_geo(const int32_t dims[4], uint64_t V)
     return g;
 }
 
-int build_graph(int nsweeps, hipGraphExec_t *out)
+int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
 {
     hipGraph_t graph;
     HIP_TRY(hipGraphCreate(&graph, 0));
@@ -123,9 +131,10 @@ int build_graph(int nsweeps, hipGraphExec_t *out)
         // Sec. 2.4: odd sites for every direction, then even sites
         for (int p = 1; p >= 0 && rc == SU2_OK; --p) {
             for (int mu = 0; mu < 4; ++mu) {
+                const bool measure = measure_last && s == nsweeps - 1;
                 PassLaunch pl = pass_launch(ctx.links, ctx.g, ctx.key, (float)ctx.beta,
                                             (uint32_t)p, (uint32_t)mu, ctx.d_sweep,
-                                            ctx.d_counters);
+                                            ctx.d_counters, measure ? ctx.d_meas : nullptr);
                 pl.bind();
                 hipKernelNodeParams kp{};
                 kp.func = const_cast<void *>(pl.func);
@@ -171,24 +180,42 @@ int require_ready()
     return SU2_OK;
 }
 
-int run_sweeps(int32_t n)
+// n sweeps; with measured, the last one also leaves the plaquette partials of
+// its result in d_meas (the even passes mu >= 1 accumulate them)
+int run_sweeps(int32_t n, bool measured = false)
 {
+    if (n <= 0) return SU2_OK;
     if (!ctx.graph1) {
-        int rc = build_graph(1, &ctx.graph1);
+        int rc = build_graph(1, false, &ctx.graph1);
         if (rc) return rc;
     }
-    if (n >= kGraphSweeps && !ctx.graphN) {
-        int rc = build_graph(kGraphSweeps, &ctx.graphN);
+    if (measured && !ctx.graphM) {
+        int rc = build_graph(1, true, &ctx.graphM);
         if (rc) return rc;
     }
-    int32_t left = n;
+    int32_t left = measured ? n - 1 : n;
+    if (left >= kGraphSweeps && !ctx.graphN) {
+        int rc = build_graph(kGraphSweeps, false, &ctx.graphN);
+        if (rc) return rc;
+    }
     while (left >= kGraphSweeps) {
         HIP_TRY(hipGraphLaunch(ctx.graphN, ctx.stream));
         left -= kGraphSweeps;
     }
     while (left-- > 0) HIP_TRY(hipGraphLaunch(ctx.graph1, ctx.stream));
+    if (measured) HIP_TRY(hipGraphLaunch(ctx.graphM, ctx.stream));
     ctx.sweep += (uint64_t)n;
+    ctx.meas_fresh = measured;
     return SU2_OK;
+}
+
+// (P, P_s, P_t) of the current links into device out[0..2]: from the partials
+// of the last measured sweep when they are current, else by k_plaquette
+hipError_t enqueue_plaquette(double *out)
+{
+    if (ctx.meas_fresh)
+        return launch_measure_reduce(ctx.d_meas, ctx.g, ctx.d_scratch, out, ctx.stream);
+    return launch_plaquette(ctx.links, ctx.g, ctx.d_partials, ctx.d_scratch, out, ctx.stream);
 }
 
 }  // namespace
@@ -217,6 +244,7 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
     ctx.key = Key{ (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
     ctx.n_waves = counter_waves(ctx.g);
     const uint32_t nb = std::max(plaquette_blocks(ctx.g), polyakov_blocks(ctx.g));
+    const size_t n_meas = (size_t)3 * pass_blocks(ctx.g);
     if (dev_links) {
         ctx.links = static_cast<float4 *>(dev_links);
         ctx.owns_links = false;
@@ -232,6 +260,8 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
     if (hipMalloc(&ctx.d_sweep, sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&ctx.d_counters, (size_t)ctx.n_waves * 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx.d_partials, (size_t)nb * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&ctx.d_meas, n_meas * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&ctx.d_scratch, (size_t)reduce_scratch() * sizeof(double2)) != hipSuccess ||
         hipMalloc(&ctx.d_out, 3 * sizeof(double)) != hipSuccess) {
         hipGetLastError();
         release_all();
@@ -242,6 +272,7 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
                            ctx.stream));
     HIP_TRY(launch_init(ctx.links, ctx.g, ctx.key, start == SU2_HOT, ctx.stream));
     ctx.sweep = 0;
+    ctx.meas_fresh = false;
     ctx.ready = true;
     return SU2_OK;
 }
@@ -261,14 +292,26 @@ int su2_sweep(int32_t n)
     return run_sweeps(n);
 }
 
+int su2_sweep_measured(int32_t n)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (n < 1) return fail(SU2_EINVAL, "n must be >= 1");
+    if (ctx.sweep + (uint64_t)n > 0xffffffffull)
+        return fail(SU2_EINVAL, "sweep index would pass 2^32 - 1");
+    return run_sweeps(n, true);
+}
+
 int su2_pass(int32_t parity, int32_t mu)
 {
     int rc = require_ready();
     if (rc) return rc;
     if (parity < 0 || parity > 1 || mu < 0 || mu > 3)
         return fail(SU2_EINVAL, "parity must be 0/1 and mu 0..3");
-    HIP_TRY(launch_pass(ctx.links, ctx.g, ctx.key, (float)ctx.beta, (uint32_t)parity,
-                        (uint32_t)mu, ctx.d_sweep, ctx.d_counters, ctx.stream));
+    PassLaunch pl = pass_launch(ctx.links, ctx.g, ctx.key, (float)ctx.beta, (uint32_t)parity,
+                                (uint32_t)mu, ctx.d_sweep, ctx.d_counters, nullptr);
+    HIP_TRY(launch(pl, ctx.stream));
+    ctx.meas_fresh = false;
     return SU2_OK;
 }
 
@@ -277,7 +320,7 @@ int su2_plaquette_st(double out[3])
     int rc = require_ready();
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
-    HIP_TRY(launch_plaquette(ctx.links, ctx.g, ctx.d_partials, ctx.d_out, ctx.stream));
+    HIP_TRY(enqueue_plaquette(ctx.d_out));
     HIP_TRY(hipMemcpyAsync(out, ctx.d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
     HIP_TRY(hipStreamSynchronize(ctx.stream));
     return SU2_OK;
@@ -296,7 +339,7 @@ int su2_polyakov(double *out)
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
     double o[3];
-    HIP_TRY(launch_polyakov(ctx.links, ctx.g, ctx.d_partials, ctx.d_out, ctx.stream));
+    HIP_TRY(launch_polyakov(ctx.links, ctx.g, ctx.d_partials, ctx.d_scratch, ctx.d_out, ctx.stream));
     HIP_TRY(hipMemcpyAsync(o, ctx.d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
     HIP_TRY(hipStreamSynchronize(ctx.stream));
     *out = o[0];
@@ -308,8 +351,8 @@ int su2_measure_device(double *dev_out)
     int rc = require_ready();
     if (rc) return rc;
     if (!dev_out || (uintptr_t)dev_out % 8) return fail(SU2_EINVAL, "dev_out must be 8-byte aligned device memory");
-    HIP_TRY(launch_plaquette(ctx.links, ctx.g, ctx.d_partials, dev_out, ctx.stream));
-    HIP_TRY(launch_polyakov(ctx.links, ctx.g, ctx.d_partials, dev_out + 3, ctx.stream));
+    HIP_TRY(enqueue_plaquette(dev_out));
+    HIP_TRY(launch_polyakov(ctx.links, ctx.g, ctx.d_partials, ctx.d_scratch, dev_out + 3, ctx.stream));
     return SU2_OK;
 }
 
@@ -329,9 +372,9 @@ int su2_sweep_measure(int32_t n, int32_t every, double *host_hist)
         return fail(SU2_ENOMEM, "cannot allocate the measurement history");
     }
     for (int32_t i = 0; i < m && rc == SU2_OK; ++i) {
-        rc = run_sweeps(every);
+        rc = run_sweeps(every, true);
         if (rc == SU2_OK) {
-            hipError_t e = launch_plaquette(ctx.links, ctx.g, ctx.d_partials, d_hist + 3 * i, ctx.stream);
+            hipError_t e = enqueue_plaquette(d_hist + 3 * i);
             if (e != hipSuccess) rc = fail(SU2_EDEVICE, "plaquette launch: %s", hipGetErrorString(e));
         }
     }
@@ -385,6 +428,7 @@ int su2_set_links(const float *host_in, size_t n_floats, uint64_t sweep_index)
     hipError_t e = hipMemcpyAsync(stage, host_in, n_floats * sizeof(float), hipMemcpyHostToDevice,
                                   ctx.stream);
     if (e == hipSuccess) e = launch_unpack(ctx.links, ctx.g, stage, ctx.stream);
+    ctx.meas_fresh = false;
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx.d_sweep, &s32, sizeof s32, hipMemcpyHostToDevice, ctx.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);

@@ -133,6 +133,7 @@ struct Geo {
     uint32_t H0;       // L0 / 2
     uint32_t half;     // V / 2
     uint32_t st[4];    // half-index strides of x0 (pairs), x1, x2, x3: 1, H0, H0*L1, H0*L1*L2
+    uint32_t wrap[4];  // (L_d - 1) * st[d]: the jump back across the periodic boundary
     FastDiv dH0, dL1, dL2, dL0;
 };
 
@@ -176,6 +177,52 @@ __device__ __forceinline__ Site step(const Geo &g, Site s, int d, int dir)
 __device__ __forceinline__ size_t arr(const Geo &g, uint32_t mu, uint32_t p)
 {
     return (size_t)(2u * mu + p) * g.half;
+}
+
+// Half index of the neighbour x + e_D (plus) or x - e_D (minus) of a site with
+// half index h and coordinate xd along D, by additions only.  Along x0 the
+// half index changes only when the step crosses a pair boundary.
+template <int D>
+__device__ __forceinline__ uint32_t h_plus(const Geo &g, uint32_t h, uint32_t xd)
+{
+    if constexpr (D == 0)
+        return (xd & 1u) ? ((xd + 1u == g.L[0]) ? h - (g.H0 - 1u) : h + 1u) : h;
+    else
+        return (xd + 1u == g.L[D]) ? h - g.wrap[D] : h + g.st[D];
+}
+
+template <int D>
+__device__ __forceinline__ uint32_t h_minus(const Geo &g, uint32_t h, uint32_t xd)
+{
+    if constexpr (D == 0)
+        return (xd & 1u) ? h : ((xd == 0u) ? h + (g.H0 - 1u) : h - 1u);
+    else
+        return (xd == 0u) ? h + g.wrap[D] : h - g.st[D];
+}
+
+// 16-byte load of element idx of an array: with OFF32 the byte offset is
+// formed in 32 bits (valid while an array is below 4 GiB), which lets the
+// load use a scalar base address plus a 32-bit lane offset.
+template <bool OFF32>
+__device__ __forceinline__ float4 ld4(const float4 *base, uint32_t idx)
+{
+    if constexpr (OFF32)
+        return *reinterpret_cast<const float4 *>(reinterpret_cast<const char *>(base) + idx * 16u);
+    else
+        return base[idx];
+}
+
+template <bool OFF32>
+__device__ __forceinline__ void st4_stream(float4 *base, uint32_t idx, float4 v)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    f4 *ptr;
+    if constexpr (OFF32)
+        ptr = reinterpret_cast<f4 *>(reinterpret_cast<char *>(base) + idx * 16u);
+    else
+        ptr = reinterpret_cast<f4 *>(base + idx);
+    const f4 val = { v.x, v.y, v.z, v.w };
+    __builtin_nontemporal_store(val, ptr);  // written links are not re-read in this pass
 }
 
 }  // namespace su2

@@ -12,6 +12,8 @@
 //   k_reduce     fixed-order FP64 reduction of the partials (deterministic)
 //   k_pack / k_unpack   device checkerboard layout <-> host [V][4][4]
 //   k_philox     raw generator blocks, for bit-exact checks
+#include <algorithm>
+
 #include "su2_kernels.hpp"
 
 namespace su2 {
@@ -35,31 +37,42 @@ __global__ __launch_bounds__(kBlock) void k_init(float4 *__restrict__ links, Geo
 }
 
 // ---------------------------------------------------------------------------
-// Staple sum of Eq. (6) for U_mu(x), x of parity p, over the six plaquettes
-// that contain the link (all nu != mu).
-__device__ __forceinline__ float4 staple(const float4 *__restrict__ L, const Geo &g,
-                                         const Site &x, uint32_t h, uint32_t p, uint32_t mu)
+// The three directions nu != mu, as compile-time constants.
+template <uint32_t MU, int I>
+constexpr uint32_t other_dir()
+{
+    return (uint32_t)(I < (int)MU ? I : I + 1);
+}
+
+// The six gathered links of the two staples of U_mu(x) in the plane (mu, nu)
+// (Eq. (6)): forward U_nu(x) U_mu(x+nu) U_nu(x+mu)^dag and backward
+// U_nu(x-nu)^dag U_mu(x-nu) U_nu(x+mu-nu).
+struct StapleLinks {
+    float4 a, b, c, d, e, f;
+};
+
+template <uint32_t MU, uint32_t NU, bool OFF32>
+__device__ __forceinline__ StapleLinks gather(const float4 *L, const Geo &g, uint32_t p,
+                                              uint32_t h, uint32_t h_pm, const Site &x)
 {
     const uint32_t q = p ^ 1u;
-    const Site xpm = step(g, x, mu, +1);
-    const uint32_t h_pm = half_of(g, xpm);
-    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll
-    for (uint32_t nu = 0; nu < 4; ++nu) {
-        if (nu == mu) continue;
-        const uint32_t h_pn = half_of(g, step(g, x, nu, +1));
-        const uint32_t h_mn = half_of(g, step(g, x, nu, -1));
-        const uint32_t h_pm_mn = half_of(g, step(g, xpm, nu, -1));
-        const float4 a = L[arr(g, nu, p) + h];        // U_nu(x)
-        const float4 b = L[arr(g, mu, q) + h_pn];     // U_mu(x+nu)
-        const float4 c = L[arr(g, nu, q) + h_pm];     // U_nu(x+mu)
-        const float4 d = L[arr(g, nu, q) + h_mn];     // U_nu(x-nu)
-        const float4 e = L[arr(g, mu, q) + h_mn];     // U_mu(x-nu)
-        const float4 f = L[arr(g, nu, p) + h_pm_mn];  // U_nu(x+mu-nu)
-        w = qadd(w, qmul(qmul(a, b), qdag(c)));
-        w = qadd(w, qmul(qmul(qdag(d), e), f));
-    }
-    return w;
+    const uint32_t h_pn = h_plus<NU>(g, h, x.x[NU]);
+    const uint32_t h_mn = h_minus<NU>(g, h, x.x[NU]);
+    const uint32_t h_pm_mn = h_minus<NU>(g, h_pm, x.x[NU]);  // x+mu has the same x_nu
+    const float4 *Lnp = L + arr(g, NU, p), *Lnq = L + arr(g, NU, q), *Lmq = L + arr(g, MU, q);
+    StapleLinks s;
+    s.a = ld4<OFF32>(Lnp, h);         // U_nu(x)
+    s.b = ld4<OFF32>(Lmq, h_pn);      // U_mu(x+nu)
+    s.c = ld4<OFF32>(Lnq, h_pm);      // U_nu(x+mu)
+    s.d = ld4<OFF32>(Lnq, h_mn);      // U_nu(x-nu)
+    s.e = ld4<OFF32>(Lmq, h_mn);      // U_mu(x-nu)
+    s.f = ld4<OFF32>(Lnp, h_pm_mn);   // U_nu(x+mu-nu)
+    return s;
+}
+
+__device__ __forceinline__ float4 staple_sum(const StapleLinks &s)
+{
+    return qadd(qmul(qmul(s.a, s.b), qdag(s.c)), qmul(qmul(qdag(s.d), s.e), s.f));
 }
 
 // lambda^2 of one Kennedy-Pendleton attempt; evaluated without contraction so
@@ -78,76 +91,8 @@ __device__ __forceinline__ bool kp_accept(float u3, float lam2)
     return u3 * u3 <= 1.0f - lam2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, Key key,
-                                                 float beta, uint32_t p, uint32_t mu,
-                                                 const uint32_t *__restrict__ sweep_ptr,
-                                                 unsigned long long *__restrict__ counters)
-{
-    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
-    const bool valid = h < g.half;
-    const uint32_t s = *sweep_ptr;  // wave-uniform scalar load
-    Site x{};
-    uint32_t lex = 0;
-    float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (valid) {
-        x = site_of(g, h, p);
-        lex = lex_of(g, x);
-        w = staple(L, g, x, h, p, mu);
-    }
-    const float k = sqrtf(qdot(w, w));
-    const float alpha = beta * k;
-    const bool haar_branch = valid && alpha == 0.0f;
-    bool done = !valid || haar_branch;
-    float lam2 = 0.0f;
-    unsigned long long attempts = 0;
-    for (uint32_t t = 0; t < 8u; ++t) {
-        const unsigned long long pending = __ballot(!done);
-        if (pending == 0ull) break;
-        attempts += __popcll(pending);
-        if (!done) {
-            const uint4 r = draw(key, lex, mu, kPurposeUpdate, s, t);
-            const float l = kp_lambda2(unit24(r.x), unit24(r.y), unit24(r.z), alpha);
-            if (kp_accept(unit24(r.w), l)) {
-                done = true;
-                lam2 = l;
-            }
-        }
-    }
-    const bool failed = valid && !done;
-    const unsigned long long failures = __popcll(__ballot(failed));
-    if (valid && !failed) {
-        float4 un;
-        if (haar_branch) {
-            un = unitize(haar(draw(key, lex, mu, kPurposeUpdate, s, kSlotHaar)));
-        } else {
-            const uint4 r = draw(key, lex, mu, kPurposeUpdate, s, kSlotDirection);
-            const float cz = 2.0f * unit24(r.x) - 1.0f;
-            float sphi, cphi;
-            sincospif(2.0f * unit24(r.y), &sphi, &cphi);
-            const float sn = sqrtf(1.0f - cz * cz);
-            const float a0 = 1.0f - 2.0f * lam2;
-            const float am = 2.0f * sqrtf(lam2 * (1.0f - lam2));
-            const float4 X = make_float4(a0, am * sn * cphi, am * sn * sphi, am * cz);
-            const float ik = 1.0f / k;
-            const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
-            un = unitize(qmul(X, V));
-        }
-        L[arr(g, mu, p) + h] = un;
-    }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
-        const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
-        counters[2 * wave] += attempts;
-        counters[2 * wave + 1] += failures;
-    }
-}
-
-__global__ void k_tick(uint32_t *sweep_ptr)
-{
-    if (threadIdx.x == 0) *sweep_ptr += 1u;
-}
-
-// ---------------------------------------------------------------------------
-// Block-level FP64 sum of two values: wave butterflies, then waves in order.
+// Block-level FP64 sum of two values: wave butterflies, then waves in order
+// (fixed structure, so the result does not depend on scheduling).
 __device__ __forceinline__ double2 block_sum2(double a, double b)
 {
     __shared__ double sh[2][kBlock / kWave];
@@ -172,6 +117,101 @@ __device__ __forceinline__ double2 block_sum2(double a, double b)
     return r;
 }
 
+// One heat-bath pass over the links U_MU(x), parity(x) = p.  All 18 gathers
+// are issued before any arithmetic (MU is a template parameter so the three
+// staple directions unroll).  With MEASURE (even passes MU >= 1 of a measured
+// sweep), each lane also adds dot(U_new, staple_nu) for nu < MU: over the
+// three even passes this counts every plaquette of the final configuration
+// exactly once (planes (nu, MU), nu < MU), so the plaquette of the sweep's
+// result comes out of the sweep itself.  meas_out receives one FP64 partial
+// per workgroup.
+template <uint32_t MU, bool OFF32, bool MEASURE>
+__global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, Key key,
+                                                 float beta, uint32_t p,
+                                                 const uint32_t *__restrict__ sweep_ptr,
+                                                 unsigned long long *__restrict__ counters,
+                                                 double2 *__restrict__ meas_out)
+{
+    constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
+    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = h < g.half;
+    const uint32_t s = *sweep_ptr;  // wave-uniform scalar load
+    const uint32_t hh = valid ? h : 0u;
+    const Site x = site_of(g, hh, p);
+    const uint32_t lex = 2u * hh + (x.x[0] & 1u);  // L0 = 2*H0, so lex = 2h + (x0 mod 2)
+    const uint32_t h_pm = h_plus<MU>(g, hh, x.x[MU]);
+    const StapleLinks s0 = gather<MU, N0, OFF32>(L, g, p, hh, h_pm, x);
+    const StapleLinks s1 = gather<MU, N1, OFF32>(L, g, p, hh, h_pm, x);
+    const StapleLinks s2 = gather<MU, N2, OFF32>(L, g, p, hh, h_pm, x);
+    const float4 w0 = staple_sum(s0), w1 = staple_sum(s1), w2 = staple_sum(s2);
+    const float4 w = qadd(qadd(w0, w1), w2);
+    const float k = sqrtf(qdot(w, w));
+    const float alpha = beta * k;
+    const bool haar_branch = valid && alpha == 0.0f;
+    bool done = !valid || haar_branch;
+    float lam2 = 0.0f;
+    unsigned long long attempts = 0;
+    for (uint32_t t = 0; t < 8u; ++t) {
+        const unsigned long long pending = __ballot(!done);
+        if (pending == 0ull) break;
+        attempts += __popcll(pending);
+        if (!done) {
+            const uint4 r = draw(key, lex, MU, kPurposeUpdate, s, t);
+            const float l = kp_lambda2(unit24(r.x), unit24(r.y), unit24(r.z), alpha);
+            if (kp_accept(unit24(r.w), l)) {
+                done = true;
+                lam2 = l;
+            }
+        }
+    }
+    const bool failed = valid && !done;
+    const unsigned long long failures = __popcll(__ballot(failed));
+    float4 *Lout = L + arr(g, MU, p);
+    float4 un = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid && !failed) {
+        if (haar_branch) {
+            un = unitize(haar(draw(key, lex, MU, kPurposeUpdate, s, kSlotHaar)));
+        } else {
+            const uint4 r = draw(key, lex, MU, kPurposeUpdate, s, kSlotDirection);
+            const float cz = 2.0f * unit24(r.x) - 1.0f;
+            float sphi, cphi;
+            sincospif(2.0f * unit24(r.y), &sphi, &cphi);
+            const float sn = sqrtf(1.0f - cz * cz);
+            const float a0 = 1.0f - 2.0f * lam2;
+            const float am = 2.0f * sqrtf(lam2 * (1.0f - lam2));
+            const float4 X = make_float4(a0, am * sn * cphi, am * sn * sphi, am * cz);
+            const float ik = 1.0f / k;
+            const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
+            un = unitize(qmul(X, V));
+        }
+        st4_stream<OFF32>(Lout, h, un);
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+        counters[2 * wave] += attempts;
+        counters[2 * wave + 1] += failures;
+    }
+    if constexpr (MEASURE) {
+        if (failed) un = ld4<OFF32>(Lout, h);  // the link kept its value
+        double acc = 0.0;
+        if (valid) {
+            if (N0 < MU) acc += (double)qdot(un, w0);
+            if (N1 < MU) acc += (double)qdot(un, w1);
+            if (N2 < MU) acc += (double)qdot(un, w2);
+        }
+        const double2 r = block_sum2(acc, 0.0);
+        // spatial planes (MU = 1, 2) in .x, temporal planes (MU = 3) in .y
+        if (threadIdx.x == 0)
+            meas_out[blockIdx.x] = MU == 3u ? make_double2(0.0, r.x) : make_double2(r.x, 0.0);
+    }
+}
+
+__global__ void k_tick(uint32_t *sweep_ptr)
+{
+    if (threadIdx.x == 0) *sweep_ptr += 1u;
+}
+
+// ---------------------------------------------------------------------------
 // One site per lane (index over both parities); the six plaquettes whose
 // corner is x, split spatial (nu < 3) / temporal (nu == 3).
 __global__ __launch_bounds__(kBlock) void k_plaquette(const float4 *__restrict__ L, Geo g,
@@ -184,20 +224,23 @@ __global__ __launch_bounds__(kBlock) void k_plaquette(const float4 *__restrict__
         const uint32_t h = i - p * g.half;
         const uint32_t q = p ^ 1u;
         const Site x = site_of(g, h, p);
-        float4 u[4];
-        uint32_t hn[4];
+        const uint32_t hn[4] = { h_plus<0>(g, h, x.x[0]), h_plus<1>(g, h, x.x[1]),
+                                 h_plus<2>(g, h, x.x[2]), h_plus<3>(g, h, x.x[3]) };
+        float4 u[4], nb[4][4];
 #pragma unroll
-        for (uint32_t mu = 0; mu < 4; ++mu) {
-            u[mu] = L[arr(g, mu, p) + h];
-            hn[mu] = half_of(g, step(g, x, mu, +1));
-        }
+        for (uint32_t mu = 0; mu < 4; ++mu) u[mu] = L[arr(g, mu, p) + h];
+#pragma unroll
+        for (uint32_t mu = 0; mu < 4; ++mu)
+#pragma unroll
+            for (uint32_t nu = 0; nu < 4; ++nu)
+                if (nu != mu) nb[mu][nu] = L[arr(g, nu, q) + hn[mu]];  // U_nu(x + mu)
 #pragma unroll
         for (uint32_t mu = 0; mu < 4; ++mu) {
 #pragma unroll
             for (uint32_t nu = mu + 1; nu < 4; ++nu) {
                 // U_mu(x) U_nu(x+mu) . [U_nu(x) U_mu(x+nu)]^dag
-                const float4 a = qmul(u[mu], L[arr(g, nu, q) + hn[mu]]);
-                const float4 b = qmul(u[nu], L[arr(g, mu, q) + hn[nu]]);
+                const float4 a = qmul(u[mu], nb[mu][nu]);
+                const float4 b = qmul(u[nu], nb[nu][mu]);
                 const double v = (double)qdot(a, b);
                 if (nu == 3) pt += v; else ps += v;
             }
@@ -230,7 +273,25 @@ __global__ __launch_bounds__(kBlock) void k_polyakov(const float4 *__restrict__ 
     if (threadIdx.x == 0) partials[blockIdx.x] = r;
 }
 
-// Single workgroup: thread j sums partials j, j+256, ... in order, then a
+// First level of the deterministic reduction: workgroup b sums the partials
+// [b*chunk, (b+1)*chunk) -- thread j takes j, j+256, ... in order, then the
+// fixed block tree.
+__global__ __launch_bounds__(kBlock) void k_reduce_chunks(const double2 *__restrict__ in,
+                                                          uint32_t n, uint32_t chunk,
+                                                          double2 *__restrict__ out)
+{
+    const uint32_t lo = blockIdx.x * chunk;
+    const uint32_t hi = min(n, lo + chunk);
+    double a = 0.0, b = 0.0;
+    for (uint32_t j = lo + threadIdx.x; j < hi; j += kBlock) {
+        a += in[j].x;
+        b += in[j].y;
+    }
+    const double2 r = block_sum2(a, b);
+    if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+// Final level, one workgroup: thread j sums j, j+256, ... in order, then a
 // fixed tree.  Mode 0 (plaquette): out[0] = (a*sa + b*sb)/2, out[1] = a*sa,
 // out[2] = b*sb.  Mode 1 (single value): out[0] = a*sa.
 __global__ __launch_bounds__(kBlock) void k_reduce(const double2 *__restrict__ partials,
@@ -319,34 +380,58 @@ hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_
     return hipGetLastError();
 }
 
+bool use_off32(const Geo &g) { return (uint64_t)g.half * 16u <= 0xffffffffull; }
+
+template <uint32_t MU>
+static const void *pass_func_mu(bool off32, bool measure)
+{
+    if (off32)
+        return measure ? reinterpret_cast<const void *>(&k_pass<MU, true, true>)
+                       : reinterpret_cast<const void *>(&k_pass<MU, true, false>);
+    return measure ? reinterpret_cast<const void *>(&k_pass<MU, false, true>)
+                   : reinterpret_cast<const void *>(&k_pass<MU, false, false>);
+}
+
+const void *pass_func(uint32_t mu, bool off32, bool measure)
+{
+    switch (mu) {
+    case 0: return pass_func_mu<0>(off32, false);  // no plaquette plane has nu < 0
+    case 1: return pass_func_mu<1>(off32, measure);
+    case 2: return pass_func_mu<2>(off32, measure);
+    default: return pass_func_mu<3>(off32, measure);
+    }
+}
+
+uint32_t pass_blocks(const Geo &g) { return blocks_for(g.half); }
+
 PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
-                       const uint32_t *sweep_ptr, unsigned long long *counters)
+                       const uint32_t *sweep_ptr, unsigned long long *counters,
+                       double2 *meas_out)
 {
     PassLaunch pl;
-    pl.func = reinterpret_cast<const void *>(&k_pass);
-    pl.grid = dim3(blocks_for(g.half));
+    const bool measure = meas_out != nullptr && p == 0u && mu >= 1u;
+    pl.func = pass_func(mu, use_off32(g), measure);
+    pl.grid = dim3(pass_blocks(g));
     pl.block = dim3(kBlock);
     pl.links = links;
     pl.g = g;
     pl.key = key;
     pl.beta = beta;
     pl.p = p;
-    pl.mu = mu;
     pl.sweep_ptr = sweep_ptr;
     pl.counters = counters;
+    pl.meas_out = measure ? meas_out + (size_t)(mu - 1u) * pass_blocks(g) : nullptr;
     pl.bind();
     return pl;
 }
 
-const void *tick_func() { return reinterpret_cast<const void *>(&k_tick); }
-
-hipError_t launch_pass(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
-                       const uint32_t *sweep_ptr, unsigned long long *counters, hipStream_t st)
+hipError_t launch(PassLaunch &pl, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_pass, dim3(blocks_for(g.half)), dim3(kBlock), 0, st, links, g, key, beta,
-                       p, mu, sweep_ptr, counters);
-    return hipGetLastError();
+    pl.bind();
+    return hipLaunchKernel(pl.func, pl.grid, pl.block, pl.args, 0, st);
 }
+
+const void *tick_func() { return reinterpret_cast<const void *>(&k_tick); }
 
 hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st)
 {
@@ -360,26 +445,44 @@ uint32_t polyakov_blocks(const Geo &g)
     return blocks_for((size_t)g.L[0] * g.L[1] * g.L[2]);
 }
 uint32_t counter_waves(const Geo &g) { return blocks_for(g.half) * (kBlock / kWave); }
+uint32_t reduce_scratch() { return kBlock; }
 
-hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials, double *out,
-                            hipStream_t st)
+// Two-level deterministic sum of n double2 partials into out (mode as k_reduce).
+static hipError_t reduce2(const double2 *partials, uint32_t n, double2 *scratch, double sa,
+                          double sb, int mode, double *out, hipStream_t st)
+{
+    const uint32_t nb1 = std::min<uint32_t>(kBlock, std::max<uint32_t>(1u, (n + 1023u) / 1024u));
+    const uint32_t chunk = (n + nb1 - 1) / nb1;
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(nb1), dim3(kBlock), 0, st, partials, n, chunk,
+                       scratch);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, scratch, nb1, sa, sb, mode, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials,
+                            double2 *scratch, double *out, hipStream_t st)
 {
     const uint32_t nb = plaquette_blocks(g);
     hipLaunchKernelGGL(k_plaquette, dim3(nb), dim3(kBlock), 0, st, links, g, partials);
     const double scale = 1.0 / (3.0 * 2.0 * (double)g.half);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nb, scale, scale, 0, out);
-    return hipGetLastError();
+    return reduce2(partials, nb, scratch, scale, scale, 0, out, st);
 }
 
-hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials, double *out,
-                           hipStream_t st)
+hipError_t launch_measure_reduce(const double2 *meas_partials, const Geo &g, double2 *scratch,
+                                 double *out, hipStream_t st)
+{
+    // spatial planes from the mu = 1, 2 passes (x), temporal from mu = 3 (y)
+    const double scale = 1.0 / (3.0 * 2.0 * (double)g.half);
+    return reduce2(meas_partials, 3u * pass_blocks(g), scratch, scale, scale, 0, out, st);
+}
+
+hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials,
+                           double2 *scratch, double *out, hipStream_t st)
 {
     const uint32_t vs = g.L[0] * g.L[1] * g.L[2];
     const uint32_t nb = polyakov_blocks(g);
     hipLaunchKernelGGL(k_polyakov, dim3(nb), dim3(kBlock), 0, st, links, g, vs, partials);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, nb, 1.0 / (double)vs, 0.0,
-                       1, out);
-    return hipGetLastError();
+    return reduce2(partials, nb, scratch, 1.0 / (double)vs, 0.0, 1, out, st);
 }
 
 hipError_t launch_pack(const float4 *links, const Geo &g, float4 *stage, hipStream_t st)

@@ -13,9 +13,10 @@ struct PassLaunch {
     Geo g;
     Key key;
     float beta;
-    uint32_t p, mu;
+    uint32_t p;
     const uint32_t *sweep_ptr;
     unsigned long long *counters;
+    double2 *meas_out;
     void *args[8];
     // point args at this object's own fields (call after every copy)
     void bind()
@@ -25,27 +26,34 @@ struct PassLaunch {
         args[2] = &key;
         args[3] = &beta;
         args[4] = &p;
-        args[5] = &mu;
-        args[6] = &sweep_ptr;
-        args[7] = &counters;
+        args[5] = &sweep_ptr;
+        args[6] = &counters;
+        args[7] = &meas_out;
     }
 };
 
-hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st);
-hipError_t launch_pass(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
-                       const uint32_t *sweep_ptr, unsigned long long *counters, hipStream_t st);
-hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st);
+bool use_off32(const Geo &g);
+uint32_t pass_blocks(const Geo &g);
+// meas_out != nullptr: the even passes mu >= 1 add their plaquette partials
+// (one double2 per workgroup) to meas_out + (mu - 1) * pass_blocks(g)
 PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
-                       const uint32_t *sweep_ptr, unsigned long long *counters);
+                       const uint32_t *sweep_ptr, unsigned long long *counters,
+                       double2 *meas_out);
+hipError_t launch(PassLaunch &pl, hipStream_t st);
+hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st);
+hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st);
 const void *tick_func();
 
 uint32_t plaquette_blocks(const Geo &g);
 uint32_t polyakov_blocks(const Geo &g);
 uint32_t counter_waves(const Geo &g);
-hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials, double *out,
-                            hipStream_t st);
-hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials, double *out,
-                           hipStream_t st);
+uint32_t reduce_scratch();
+hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials,
+                            double2 *scratch, double *out, hipStream_t st);
+hipError_t launch_measure_reduce(const double2 *meas_partials, const Geo &g, double2 *scratch,
+                                 double *out, hipStream_t st);
+hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials,
+                           double2 *scratch, double *out, hipStream_t st);
 hipError_t launch_pack(const float4 *links, const Geo &g, float4 *stage, hipStream_t st);
 hipError_t launch_unpack(float4 *links, const Geo &g, const float4 *stage, hipStream_t st);
 hipError_t launch_philox(const uint4 *ctr, uint32_t n, Key key, uint4 *out, hipStream_t st);

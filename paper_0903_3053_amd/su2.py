@@ -19,7 +19,7 @@ COLD, HOT = 0, 1
 
 # every symbol include/su2.h declares
 EXPORTS = (
-    "su2_init", "su2_init_ex", "su2_sweep", "su2_pass", "su2_plaquette", "su2_plaquette_st",
+    "su2_init", "su2_init_ex", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_plaquette", "su2_plaquette_st",
     "su2_polyakov", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
     "su2_counters", "su2_set_stream", "su2_philox", "su2_synchronize", "su2_last_error",
     "su2_finalize",
@@ -58,6 +58,7 @@ def load():
         "su2_init_ex": ([i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                          ctypes.c_size_t], ctypes.c_int),
         "su2_sweep": ([ctypes.c_int32], ctypes.c_int),
+        "su2_sweep_measured": ([ctypes.c_int32], ctypes.c_int),
         "su2_pass": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "su2_plaquette": ([], ctypes.c_double),
         "su2_plaquette_st": ([dp], ctypes.c_int),
@@ -128,6 +129,10 @@ def su2_init_ex(dims, beta, seed, start, dev_ptr, nbytes):
 
 def su2_sweep(n=1):
     _check(load().su2_sweep(int(n)))
+
+
+def su2_sweep_measured(n=1):
+    _check(load().su2_sweep_measured(int(n)))
 
 
 def su2_pass(parity, mu):

@@ -272,3 +272,38 @@ def test_measure_device_matches_host_calls(lib):
     np.testing.assert_array_equal(got[:3], lib.su2_plaquette_st())
     assert got[3] == lib.su2_polyakov()
     assert np.all(np.isnan(out.cpu().numpy()[0]))
+
+
+@pytest.mark.parametrize("dims,beta", [((8, 6, 10, 4), 2.3), ((12, 12, 12, 12), 2.5),
+                                       ((4, 4, 4, 4), 0.05), ((2, 4, 2, 6), 1.0)])
+def test_fused_measurement_equals_plaquette_kernel(lib, dims, beta):
+    """A measured sweep's plaquette (accumulated by its even passes) equals the
+    plaquette kernel's value on the same resulting links; at beta = 0.05 many
+    updates exhaust the 8 attempts, so kept links enter the fused sum."""
+    lib.su2_init(dims, beta, 13, lib.HOT)
+    lib.su2_sweep(2)
+    lib.su2_sweep_measured(3)
+    fused = lib.su2_plaquette_st()
+    U = lib.su2_links()
+    lib.su2_set_links(U, lib.su2_sweep_index())  # discards the fused partials
+    direct = lib.su2_plaquette_st()
+    ref = oracle.plaquette(dims, U.astype(np.float64))
+    assert np.max(np.abs(fused - direct)) <= 2e-6
+    assert np.max(np.abs(fused - ref)) <= 2e-6
+    # a plain sweep afterwards must not reuse stale partials
+    lib.su2_sweep_measured(1)
+    lib.su2_sweep(1)
+    stale_check = lib.su2_plaquette_st()
+    U2 = lib.su2_links()
+    assert np.max(np.abs(stale_check - oracle.plaquette(dims, U2.astype(np.float64)))) <= 2e-6
+
+
+def test_measured_sweep_same_links_as_plain_sweep(lib):
+    dims = (8, 6, 10, 4)
+    lib.su2_init(dims, 2.2, 3, lib.HOT)
+    lib.su2_sweep(5)
+    a = lib.su2_links()
+    lib.su2_init(dims, 2.2, 3, lib.HOT)
+    lib.su2_sweep_measured(2)
+    lib.su2_sweep_measured(3)
+    assert np.array_equal(lib.su2_links(), a)

@@ -83,6 +83,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--lattice", type=int, default=64, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--plan", type=int, nargs=2, metavar=("ORDER", "LDS"), default=None,
+                    help="use this pass-kernel launch plan instead of tuning")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device copy (torch), so that a counter "
+                         "profile of this command also holds the copy of known size")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -102,6 +108,22 @@ def main():
     su2.su2_set_stream(stream)
     su2.su2_init(dims, w["beta"], w["seed"], w["start"])
     hist = torch.zeros((args.steps, 4), dtype=torch.float64, device="cuda")
+    # pick the pass kernel's launch plan (tile order, LDS reservation) by timing
+    # it on a scratch copy of the lattice; results do not depend on it
+    if args.copy_calibration:
+        a = torch.ones(2**28, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.plan is not None:
+        su2.su2_set_plan(*args.plan)
+        plan = tuple(args.plan)
+    elif args.no_tune:
+        plan = (0, 0)
+    else:
+        plan = su2.su2_tune(2)
 
     # warm-up: sweeps and measurements, graphs built and replayed
     for i in range(args.warmup):
@@ -145,7 +167,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "dims": list(dims), "beta": w["beta"], "seed": w["seed"],
                    "start": "hot", "proposal": "kennedy-pendleton",
-                   "step": "1 sweep (8 passes, plaquette summed in the even passes) + Polyakov loop, on device"},
+                   "step": "1 sweep (8 passes, plaquette summed in the even passes) + Polyakov loop, on device",
+                   "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_pass", "avg_launch_ms": pass_ms,

@@ -132,6 +132,21 @@ int su2_counters(uint64_t out[2]);
  * stream); NULL selects the null stream.  Synchronises the previous stream. */
 int su2_set_stream(void *hip_stream);
 
+/* Launch plan of the pass kernel: order_kind 0 = workgroups in lattice order;
+ * T > 0 = each XCD takes a band of x1 rows of every (x2, x3) plane and walks
+ * the planes in T x T squares (only where a plane holds a multiple of 8
+ * tiles of 256 half-sites and T divides L2 and L3, else SU2_EINVAL);
+ * lds_bytes (0..65536) of local memory reserved per workgroup to cap the
+ * workgroups resident on a compute unit.  Results are bit-identical for every
+ * plan; only the speed changes. */
+int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
+
+/* Time each plan in {order 0, 4, 8, 16} x {LDS 0, 16, 24, 32, 40 KiB} on a
+ * scratch copy of the links (reps sweeps' worth of passes each; the lattice,
+ * sweep index and counters are untouched) and install the fastest; out
+ * (nullable) receives {order_kind, lds_bytes}.  Synchronises. */
+int su2_tune(int32_t reps, int32_t out[2]);
+
 /* Device Philox-4x32-10 blocks for n host counters ctr[n][4] and key = (seed
  * mod 2^32, seed >> 32), written to host out[n][4]; for bit-exact checks of
  * the generator the sweep uses. */

@@ -43,6 +43,9 @@ struct Context {
     hipGraphExec_t graph1 = nullptr;    // one sweep
     hipGraphExec_t graphN = nullptr;    // kGraphSweeps sweeps
     hipGraphExec_t graphM = nullptr;    // one sweep that also measures the plaquette
+    PassPlan plan;                      // launch plan of k_pass (tile order, LDS reservation)
+    uint32_t *d_order = nullptr;        // device tile-order table of the plan
+    int32_t order_kind = 0;
 };
 
 Context ctx;
@@ -82,6 +85,7 @@ void release_all()
     if (ctx.d_partials) hipFree(ctx.d_partials);
     if (ctx.d_meas) hipFree(ctx.d_meas);
     if (ctx.d_scratch) hipFree(ctx.d_scratch);
+    if (ctx.d_order) hipFree(ctx.d_order);
     if (ctx.d_out) hipFree(ctx.d_out);
     hipStream_t keep = ctx.stream;
     ctx = Context{};
@@ -134,13 +138,14 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
                 const bool measure = measure_last && s == nsweeps - 1;
                 PassLaunch pl = pass_launch(ctx.links, ctx.g, ctx.key, (float)ctx.beta,
                                             (uint32_t)p, (uint32_t)mu, ctx.d_sweep,
-                                            ctx.d_counters, measure ? ctx.d_meas : nullptr);
+                                            ctx.d_counters, measure ? ctx.d_meas : nullptr,
+                                            ctx.plan);
                 pl.bind();
                 hipKernelNodeParams kp{};
                 kp.func = const_cast<void *>(pl.func);
                 kp.gridDim = pl.grid;
                 kp.blockDim = pl.block;
-                kp.sharedMemBytes = 0;
+                kp.sharedMemBytes = pl.lds;
                 kp.kernelParams = pl.args;
                 kp.extra = nullptr;
                 hipGraphNode_t node;
@@ -172,6 +177,34 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
     }
     hipGraphDestroy(graph);
     return rc;
+}
+
+// Install a k_pass launch plan: tile order kind (0 = identity) and LDS bytes
+// reserved per workgroup.  Graphs are rebuilt on next use.
+int set_plan(int32_t kind, uint32_t lds)
+{
+    std::vector<uint32_t> order;
+    if (!make_order(ctx.g, kind, order))
+        return fail(SU2_EINVAL, "tile order %d does not fit this lattice", kind);
+    if (lds > 65536u) return fail(SU2_EINVAL, "LDS reservation must be <= 65536 bytes");
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    if (ctx.d_order) {
+        hipFree(ctx.d_order);
+        ctx.d_order = nullptr;
+    }
+    if (kind > 0) {
+        if (hipMalloc(&ctx.d_order, order.size() * sizeof(uint32_t)) != hipSuccess) {
+            hipGetLastError();
+            return fail(SU2_ENOMEM, "cannot allocate the tile order");
+        }
+        HIP_TRY(hipMemcpy(ctx.d_order, order.data(), order.size() * sizeof(uint32_t),
+                          hipMemcpyHostToDevice));
+    }
+    ctx.plan.order = ctx.d_order;
+    ctx.plan.lds_bytes = lds;
+    ctx.order_kind = kind;
+    release_graphs();
+    return SU2_OK;
 }
 
 int require_ready()
@@ -309,7 +342,7 @@ int su2_pass(int32_t parity, int32_t mu)
     if (parity < 0 || parity > 1 || mu < 0 || mu > 3)
         return fail(SU2_EINVAL, "parity must be 0/1 and mu 0..3");
     PassLaunch pl = pass_launch(ctx.links, ctx.g, ctx.key, (float)ctx.beta, (uint32_t)parity,
-                                (uint32_t)mu, ctx.d_sweep, ctx.d_counters, nullptr);
+                                (uint32_t)mu, ctx.d_sweep, ctx.d_counters, nullptr, ctx.plan);
     HIP_TRY(launch(pl, ctx.stream));
     ctx.meas_fresh = false;
     return SU2_OK;
@@ -491,6 +524,84 @@ int su2_philox(uint64_t seed, const uint32_t *ctr, size_t n, uint32_t *out)
     hipStreamSynchronize(ctx.stream);
     hipFree(d);
     if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_philox: %s", hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int su2_set_plan(int32_t order_kind, int32_t lds_bytes)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (order_kind < 0 || lds_bytes < 0) return fail(SU2_EINVAL, "negative plan parameter");
+    return set_plan(order_kind, (uint32_t)lds_bytes);
+}
+
+int su2_tune(int32_t reps, int32_t out[2])
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (reps < 1) return fail(SU2_EINVAL, "reps must be >= 1");
+    const size_t link_bytes = (size_t)ctx.V * 4 * sizeof(float4);
+    const size_t ctr_bytes = (size_t)ctx.n_waves * 2 * sizeof(unsigned long long);
+    float4 *tl = nullptr;
+    unsigned long long *tc = nullptr;
+    if (hipMalloc(&tl, link_bytes) != hipSuccess || hipMalloc(&tc, ctr_bytes) != hipSuccess) {
+        hipGetLastError();
+        if (tl) hipFree(tl);
+        return fail(SU2_ENOMEM, "cannot allocate the tuning copy of the links");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    if (e == hipSuccess) e = hipMemcpyAsync(tl, ctx.links, link_bytes, hipMemcpyDeviceToDevice, ctx.stream);
+    if (e == hipSuccess) e = hipMemsetAsync(tc, 0, ctr_bytes, ctx.stream);
+    const int32_t kinds[] = { 0, 4, 8, 16 };
+    const uint32_t ldss[] = { 0u, 16384u, 24576u, 32768u, 40960u };
+    float best = 1e30f;
+    int32_t best_kind = 0;
+    uint32_t best_lds = 0;
+    for (int32_t kind : kinds) {
+        if (e != hipSuccess) break;
+        std::vector<uint32_t> order;
+        if (!make_order(ctx.g, kind, order)) continue;
+        rc = set_plan(kind, 0);
+        if (rc) break;
+        for (uint32_t lds : ldss) {
+            ctx.plan.lds_bytes = lds;
+            for (int warm = 0; warm < 2 && e == hipSuccess; ++warm) {
+                if (warm == 1) e = hipEventRecord(e0, ctx.stream);
+                for (int32_t r = 0; r < (warm ? reps : 1) && e == hipSuccess; ++r)
+                    for (int p = 1; p >= 0 && e == hipSuccess; --p)
+                        for (uint32_t mu = 0; mu < 4 && e == hipSuccess; ++mu) {
+                            PassLaunch pl = pass_launch(tl, ctx.g, ctx.key, (float)ctx.beta,
+                                                        (uint32_t)p, mu, ctx.d_sweep, tc, nullptr,
+                                                        ctx.plan);
+                            e = launch(pl, ctx.stream);
+                        }
+            }
+            if (e == hipSuccess) e = hipEventRecord(e1, ctx.stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess && ms < best) {
+                best = ms;
+                best_kind = kind;
+                best_lds = lds;
+            }
+        }
+    }
+    hipStreamSynchronize(ctx.stream);
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(tl);
+    hipFree(tc);
+    if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_tune: %s", hipGetErrorString(e));
+    if (rc) return rc;
+    rc = set_plan(best_kind, best_lds);
+    if (rc) return rc;
+    if (out) {
+        out[0] = best_kind;
+        out[1] = (int32_t)best_lds;
+    }
     return SU2_OK;
 }
 

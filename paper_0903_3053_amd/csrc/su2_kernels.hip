@@ -130,10 +130,14 @@ __global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, 
                                                  float beta, uint32_t p,
                                                  const uint32_t *__restrict__ sweep_ptr,
                                                  unsigned long long *__restrict__ counters,
-                                                 double2 *__restrict__ meas_out)
+                                                 double2 *__restrict__ meas_out,
+                                                 const uint32_t *__restrict__ order)
 {
     constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
-    const uint32_t h = blockIdx.x * kBlock + threadIdx.x;
+    // workgroup -> tile of 256 half-sites; a table can reorder tiles so that the
+    // workgroups the hardware sends to one XCD share their neighbour data in L2
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
+    const uint32_t h = tile * kBlock + threadIdx.x;
     const bool valid = h < g.half;
     const uint32_t s = *sweep_ptr;  // wave-uniform scalar load
     const uint32_t hh = valid ? h : 0u;
@@ -187,7 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, 
         st4_stream<OFF32>(Lout, h, un);
     }
     if ((threadIdx.x & (kWave - 1)) == 0) {
-        const uint32_t wave = (blockIdx.x * kBlock + threadIdx.x) / kWave;
+        const uint32_t wave = h / kWave;
         counters[2 * wave] += attempts;
         counters[2 * wave + 1] += failures;
     }
@@ -202,7 +206,7 @@ __global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, 
         const double2 r = block_sum2(acc, 0.0);
         // spatial planes (MU = 1, 2) in .x, temporal planes (MU = 3) in .y
         if (threadIdx.x == 0)
-            meas_out[blockIdx.x] = MU == 3u ? make_double2(0.0, r.x) : make_double2(r.x, 0.0);
+            meas_out[tile] = MU == 3u ? make_double2(0.0, r.x) : make_double2(r.x, 0.0);
     }
 }
 
@@ -404,11 +408,43 @@ const void *pass_func(uint32_t mu, bool off32, bool measure)
 
 uint32_t pass_blocks(const Geo &g) { return blocks_for(g.half); }
 
+// Tile orders (workgroup w runs tile order[w]; the hardware deals workgroups
+// to the 8 XCDs round-robin, w mod 8).  kind 0: identity.  kind T > 0: when a
+// (x2, x3) plane holds a multiple of 8 tiles, XCD k takes the k-th eighth of
+// every plane (a band of x1 rows) and walks the planes in T x T squares of
+// (x2, x3), so that the planes whose rows a tile's staples read were fetched
+// into the same L2 shortly before.  Returns false if the geometry does not fit
+// the scheme (the identity is then used).
+bool make_order(const Geo &g, int kind, std::vector<uint32_t> &order)
+{
+    const uint32_t n = pass_blocks(g);
+    order.resize(n);
+    for (uint32_t w = 0; w < n; ++w) order[w] = w;
+    if (kind <= 0) return true;
+    const uint32_t T = (uint32_t)kind;
+    const uint64_t per_plane = (uint64_t)g.H0 * g.L[1];
+    if (per_plane % (8u * kBlock) || g.L[2] % T || g.L[3] % T || n % 8u) return false;
+    const uint32_t bpp = (uint32_t)(per_plane / kBlock);  // tiles per plane
+    const uint32_t band = bpp / 8u;                       // tiles per plane per XCD
+    const uint32_t nt2 = g.L[2] / T;
+    for (uint32_t w = 0; w < n; ++w) {
+        const uint32_t k = w % 8u, j = w / 8u;
+        const uint32_t in_band = j % band, pj = j / band;  // pj-th plane of this XCD
+        const uint32_t sq = pj / (T * T), in_sq = pj % (T * T);
+        const uint32_t x2 = (sq % nt2) * T + in_sq % T;
+        const uint32_t x3 = (sq / nt2) * T + in_sq / T;
+        order[w] = (x2 + g.L[2] * x3) * bpp + k * band + in_band;
+    }
+    return true;
+}
+
 PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
                        const uint32_t *sweep_ptr, unsigned long long *counters,
-                       double2 *meas_out)
+                       double2 *meas_out, const PassPlan &plan)
 {
     PassLaunch pl;
+    pl.lds = plan.lds_bytes;
+    pl.order = plan.order;
     const bool measure = meas_out != nullptr && p == 0u && mu >= 1u;
     pl.func = pass_func(mu, use_off32(g), measure);
     pl.grid = dim3(pass_blocks(g));
@@ -428,7 +464,7 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
 hipError_t launch(PassLaunch &pl, hipStream_t st)
 {
     pl.bind();
-    return hipLaunchKernel(pl.func, pl.grid, pl.block, pl.args, 0, st);
+    return hipLaunchKernel(pl.func, pl.grid, pl.block, pl.args, pl.lds, st);
 }
 
 const void *tick_func() { return reinterpret_cast<const void *>(&k_tick); }

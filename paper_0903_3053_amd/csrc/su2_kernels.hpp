@@ -1,9 +1,20 @@
 // su2_kernels.hpp -- host-side launchers of the lattice kernels.
 #pragma once
 
+#include <vector>
+
 #include "su2_device.hpp"
 
 namespace su2 {
+
+// How k_pass is launched: tile order table (device, nullptr = identity) and
+// LDS bytes reserved per workgroup (caps resident workgroups per CU; 0 = none).
+// Neither changes any result: every update is a pure function of the links it
+// reads and of its Philox counter.
+struct PassPlan {
+    const uint32_t *order = nullptr;
+    uint32_t lds_bytes = 0;
+};
 
 // Arguments of one k_pass launch, kept together so a graph node can point at them.
 struct PassLaunch {
@@ -17,7 +28,9 @@ struct PassLaunch {
     const uint32_t *sweep_ptr;
     unsigned long long *counters;
     double2 *meas_out;
-    void *args[8];
+    const uint32_t *order;
+    uint32_t lds;
+    void *args[9];
     // point args at this object's own fields (call after every copy)
     void bind()
     {
@@ -29,6 +42,7 @@ struct PassLaunch {
         args[5] = &sweep_ptr;
         args[6] = &counters;
         args[7] = &meas_out;
+        args[8] = &order;
     }
 };
 
@@ -38,7 +52,8 @@ uint32_t pass_blocks(const Geo &g);
 // (one double2 per workgroup) to meas_out + (mu - 1) * pass_blocks(g)
 PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_t p, uint32_t mu,
                        const uint32_t *sweep_ptr, unsigned long long *counters,
-                       double2 *meas_out);
+                       double2 *meas_out, const PassPlan &plan);
+bool make_order(const Geo &g, int kind, std::vector<uint32_t> &order);
 hipError_t launch(PassLaunch &pl, hipStream_t st);
 hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st);
 hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st);

@@ -21,7 +21,7 @@ COLD, HOT = 0, 1
 EXPORTS = (
     "su2_init", "su2_init_ex", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_plaquette", "su2_plaquette_st",
     "su2_polyakov", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
-    "su2_counters", "su2_set_stream", "su2_philox", "su2_synchronize", "su2_last_error",
+    "su2_counters", "su2_set_stream", "su2_set_plan", "su2_tune", "su2_philox", "su2_synchronize", "su2_last_error",
     "su2_finalize",
 )
 
@@ -70,6 +70,8 @@ def load():
         "su2_sweep_index": ([u64p], ctypes.c_int),
         "su2_counters": ([u64p], ctypes.c_int),
         "su2_set_stream": ([ctypes.c_void_p], ctypes.c_int),
+        "su2_set_plan": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "su2_tune": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
         "su2_philox": ([ctypes.c_uint64, u32p, ctypes.c_size_t, u32p], ctypes.c_int),
         "su2_synchronize": ([], ctypes.c_int),
         "su2_last_error": ([], ctypes.c_char_p),
@@ -207,6 +209,18 @@ def su2_set_stream(stream=None):
         ptr = getattr(stream, "cuda_stream", stream)
         _keep["stream"] = stream
     _check(load().su2_set_stream(ctypes.c_void_p(int(ptr)) if ptr else None))
+
+
+def su2_set_plan(order_kind, lds_bytes):
+    _check(load().su2_set_plan(int(order_kind), int(lds_bytes)))
+
+
+def su2_tune(reps=2):
+    """Time the pass-kernel launch plans and install the fastest; returns
+    (order_kind, lds_bytes)."""
+    out = (ctypes.c_int32 * 2)()
+    _check(load().su2_tune(int(reps), out))
+    return int(out[0]), int(out[1])
 
 
 def su2_philox(seed, counters):

@@ -44,16 +44,17 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload, bytes_per_launch):
+def measured_traffic(workload, plan):
     """HBM bytes per k_pass launch from the committed rocprofv3 counter runs,
-    or None if they were taken on another version of the kernel."""
+    or None if they were taken on another version of the kernel or with
+    another launch plan."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     rec = t.get(workload)
-    if not rec or rec.get("kernel_hash") != kernel_hash():
+    if not rec or rec.get("kernel_hash") != kernel_hash() or list(rec.get("plan", [])) != list(plan):
         return None
     return rec.get("bytes_per_launch")
 
@@ -158,7 +159,7 @@ def main():
     pass_ms = sweep_ms / (8 * args.steps)
     bytes_per_launch = (V // 2) * BYTES_PER_UPDATE
     achieved = bytes_per_launch / (pass_ms * 1e-3) / 1e9
-    traffic = measured_traffic(w["name"], bytes_per_launch)
+    traffic = measured_traffic(w["name"], plan)
 
     rec = {
         "metric": METRIC, "value": value, "unit": "link updates/s", "n_gpus": 1,

@@ -33,7 +33,7 @@ WORKLOADS = {
 }
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0903_3053_amd", "csrc", f)
-                  for f in ("su2_kernels.hip", "su2_device.hpp")]
+                  for f in ("su2_kernels.hip", "su2_device.hpp", "su2_pass.hpp")]
 
 
 def kernel_hash():

@@ -147,6 +147,60 @@ int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
  * (nullable) receives {order_kind, lds_bytes}.  Synchronises. */
 int su2_tune(int32_t reps, int32_t out[2]);
 
+/* ---- Batched replicas ---------------------------------------------------
+ * A second, independent context: n lattices, each with its own extents
+ * dims[4*r .. 4*r+3] (even, >= 2, V/2 * 16 bytes below 4 GiB), coupling
+ * betas[r] and seed seeds[r], all started cold or hot.  Every replica evolves
+ * exactly as a single lattice with the same (dims, beta, seed, start) would
+ * under su2_init + su2_sweep: the same Philox counters, the same sweep order
+ * (Sec. 2.4), bit-identical links.  The paper runs one parameter point per GPU
+ * (Sec. 3); here many share one device.  Replaces any previous batch. */
+int su2_batch_init(int32_t n, const int32_t *dims, const double *betas, const uint64_t *seeds,
+                   int32_t start);
+
+/* n >= 0 sweeps of every replica (synchronises in persistent mode). */
+int su2_batch_sweep(int32_t n);
+
+/* How su2_batch_sweep runs: mode 0 = one launch per (parity, mu) pass over
+ * the tiles of all replicas, replayed from a hipGraph; mode 1 = one
+ * persistent launch per call (graph-captured with a counter reset), in which
+ * workgroups take (sweep, pass, replica, tiles) items in order and an item
+ * waits for its replica's previous pass (per-replica completion counters).
+ * tiles_per_item (1..64) tiles of 256 half-sites form one work item;
+ * lds_bytes (0..65536) caps resident workgroups.  Results do not depend on
+ * any of these. */
+int su2_batch_set_mode(int32_t mode, int32_t tiles_per_item, int32_t lds_bytes);
+
+/* Time every {mode 0, 1} x {1, 2, 4 tiles per item} x {0, 24 KiB LDS} over
+ * `sweeps` sweeps on a saved copy of the state (restored afterwards) and
+ * install the fastest; out (nullable) receives {mode, tiles_per_item,
+ * lds_bytes}. */
+int su2_batch_tune(int32_t sweeps, int32_t out[3]);
+
+/* Bound, in wall-clock ticks, on any single dependency wait of the
+ * persistent kernel (default: 2 s).  A wait that exceeds it makes the launch
+ * stop early and su2_batch_sweep return SU2_EDEVICE; the replicas are then in
+ * an undefined intermediate state and must be re-initialised. */
+int su2_batch_set_spin_limit(uint64_t ticks);
+
+/* out[3*r .. 3*r+2] = (P, P_s, P_t) of replica r (as su2_plaquette_st). */
+int su2_batch_plaquette(double *out);
+
+/* Links of replica r, float32 [V][4][4] (n_floats = 16*V). */
+int su2_batch_links(int32_t r, float *host_out, size_t n_floats);
+
+/* KP attempts and cap failures of replica r since su2_batch_init. */
+int su2_batch_counters(int32_t r, uint64_t out[2]);
+
+/* Sweeps done since su2_batch_init (the same for every replica). */
+int su2_batch_sweep_index(uint64_t *out);
+
+/* Message for the last error of a su2_batch_* call. */
+const char *su2_batch_last_error(void);
+
+/* Release the batch; safe to call twice. */
+void su2_batch_finalize(void);
+
 /* Device Philox-4x32-10 blocks for n host counters ctr[n][4] and key = (seed
  * mod 2^32, seed >> 32), written to host out[n][4]; for bit-exact checks of
  * the generator the sweep uses. */

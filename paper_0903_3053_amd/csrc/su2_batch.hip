@@ -1,0 +1,747 @@
+// su2_batch.hip -- many independent replicas (each its own lattice, coupling
+// and seed) swept together on one GPU.  The paper runs one parameter point per
+// GPU (Sec. 3); here replicas of uneven size share the device.
+//
+// Two ways to run n sweeps of every replica, with identical results (each link
+// update is a pure function of the links it reads and its Philox counter):
+//   grouped     one launch per (parity, mu) pass covering the tiles of all
+//               replicas, eight per sweep, replayed from a hipGraph;
+//   persistent  one launch for all n sweeps: workgroups take work items
+//               (sweep, pass, replica, k tiles) in a fixed order, item i going
+//               to workgroup i mod G with G workgroups co-resident; an item
+//               waits until its replica's previous pass is complete
+//               (per-replica counters with agent-scope release/acquire).
+//               Waits only reach back to earlier items, so the queue drains;
+//               every wait is also bounded by a wall-clock limit after which
+//               the workgroup raises an error flag and leaves, so the kernel
+//               always ends.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "su2.h"
+#include "su2_pass.hpp"
+
+namespace su2 {
+
+struct Rep {
+    Geo g;
+    Key key;
+    float beta;
+    uint32_t tiles;      // tiles of 256 half-sites per pass
+    uint32_t items;      // work items per pass (tiles grouped k at a time)
+    uint64_t link_off;   // float4 offset of the replica's 8 link arrays
+    uint64_t ctr_off;    // offset of its per-wave (attempts, failures) counters
+};
+
+struct BatchDev {
+    const Rep *reps;
+    const uint32_t *prefix;  // prefix[r] = items of replicas < r in one pass; prefix[n] = total
+    uint32_t n;
+    float4 *links;
+    unsigned long long *counters;
+};
+
+// replica r with prefix[r] <= i < prefix[r + 1] (wave-uniform binary search)
+__device__ __forceinline__ uint32_t find_rep(const BatchDev &b, uint32_t i)
+{
+    uint32_t lo = 0, hi = b.n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (b.prefix[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Run item `it` (tiles it*k .. it*k+k-1) of pass (p, mu) of replica rep.
+__device__ __forceinline__ void run_item(const BatchDev &b, const Rep &rep, uint32_t p,
+                                         uint32_t mu, uint32_t s, uint32_t it, uint32_t k)
+{
+    float4 *L = b.links + rep.link_off;
+    unsigned long long *ctr = b.counters + rep.ctr_off;
+    for (uint32_t j = 0; j < k; ++j) {
+        const uint32_t tile = it * k + j;
+        if (tile >= rep.tiles) break;  // uniform: the whole workgroup leaves together
+        switch (mu) {
+        case 0: pass_tile<0, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr); break;
+        case 1: pass_tile<1, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr); break;
+        case 2: pass_tile<2, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr); break;
+        default: pass_tile<3, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr); break;
+        }
+    }
+}
+
+// One (parity, mu) pass of every replica; workgroup w runs work item w.
+__global__ __launch_bounds__(kBlock) void k_batch_pass(BatchDev b, uint32_t p, uint32_t mu,
+                                                       const uint32_t *__restrict__ sweep_ptr,
+                                                       uint32_t k)
+{
+    extern __shared__ float reserve[];  // LDS reservation only (caps resident workgroups)
+    (void)reserve;
+    const uint32_t r = find_rep(b, blockIdx.x);
+    const Rep rep = b.reps[r];
+    run_item(b, rep, p, mu, *sweep_ptr, blockIdx.x - b.prefix[r], k);
+}
+
+__global__ void k_batch_tick(uint32_t *sweep_ptr, uint32_t n)
+{
+    if (threadIdx.x == 0) *sweep_ptr += n;
+}
+
+// Zero the persistent kernel's completion counters and error flag (a kernel,
+// not a memset, so the graph that holds it replays correctly).
+__global__ void k_batch_reset(unsigned int *done, uint32_t n, unsigned int *err)
+{
+    for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+    if (threadIdx.x == 0) *err = 0u;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchDev b,
+                                                             const uint32_t *__restrict__ sweep_ptr,
+                                                             uint32_t nsweeps, uint32_t k,
+                                                             unsigned int *done, unsigned int *err,
+                                                             unsigned long long spin_limit)
+{
+    extern __shared__ float reserve[];
+    (void)reserve;
+    __shared__ uint32_t ok_sh;
+    const uint32_t per_pass = b.prefix[b.n];
+    const uint64_t total = (uint64_t)nsweeps * 8u * per_pass;
+    const uint32_t s0 = *sweep_ptr;
+    for (uint64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const uint32_t sk = (uint32_t)(item / per_pass);  // sweep * 8 + pass
+        const uint32_t rem = (uint32_t)(item - (uint64_t)sk * per_pass);
+        const uint32_t r = find_rep(b, rem);
+        const Rep rep = b.reps[r];
+        const uint32_t it = rem - b.prefix[r];
+        const uint32_t pass = sk & 7u;
+        // Sec. 2.4 order: odd sites for mu = 0..3, then even sites
+        const uint32_t p = pass < 4u ? 1u : 0u, mu = pass & 3u;
+        if (threadIdx.x == 0) {
+            // every item of this replica's previous passes must be complete
+            const unsigned int target = sk * rep.items;
+            unsigned int ok = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
+            if (ok && __hip_atomic_load(&done[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                const unsigned long long t0 = wall_clock64();
+                while (__hip_atomic_load(&done[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                    if (wall_clock64() - t0 > spin_limit ||
+                        __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                        ok = 0u;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+            }
+            if (!ok) __hip_atomic_fetch_or(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            ok_sh = ok;
+        }
+        __syncthreads();
+        if (!ok_sh) break;  // workgroup-uniform: every wave leaves
+        // make the previous pass's links, written by other workgroups, visible
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        run_item(b, rep, p, mu, s0 + (sk >> 3), it, k);
+        // publish this item's links before counting it done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0)
+            __hip_atomic_fetch_add(&done[r], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Per-replica plaquette: workgroup w of replica r (tiles of 256 sites over both
+// parities) writes a partial; k_batch_plaq_reduce sums each replica's
+// partials in order.
+__global__ __launch_bounds__(kBlock) void k_batch_plaquette(BatchDev b,
+                                                            const uint32_t *__restrict__ site_prefix,
+                                                            double2 *__restrict__ partials)
+{
+    // find the replica of this workgroup among the site tiles
+    uint32_t lo = 0, hi = b.n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (site_prefix[mid] <= blockIdx.x) lo = mid; else hi = mid;
+    }
+    const Rep rep = b.reps[lo];
+    const Geo &g = rep.g;
+    const float4 *L = b.links + rep.link_off;
+    const uint32_t i = (blockIdx.x - site_prefix[lo]) * kBlock + threadIdx.x;
+    double ps = 0.0, pt = 0.0;
+    if (i < 2u * g.half) {
+        const uint32_t p = i >= g.half ? 1u : 0u;
+        const uint32_t h = i - p * g.half;
+        const uint32_t q = p ^ 1u;
+        const Site x = site_of(g, h, p);
+        const uint32_t hn[4] = { h_plus<0>(g, h, x.x[0]), h_plus<1>(g, h, x.x[1]),
+                                 h_plus<2>(g, h, x.x[2]), h_plus<3>(g, h, x.x[3]) };
+        float4 u[4];
+#pragma unroll
+        for (uint32_t mu = 0; mu < 4; ++mu) u[mu] = L[arr(g, mu, p) + h];
+#pragma unroll
+        for (uint32_t mu = 0; mu < 4; ++mu) {
+#pragma unroll
+            for (uint32_t nu = mu + 1; nu < 4; ++nu) {
+                const float4 a = qmul(u[mu], L[arr(g, nu, q) + hn[mu]]);
+                const float4 c = qmul(u[nu], L[arr(g, mu, q) + hn[nu]]);
+                const double v = (double)qdot(a, c);
+                if (nu == 3) pt += v; else ps += v;
+            }
+        }
+    }
+    const double2 r = block_sum2(ps, pt);
+    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_plaq_reduce(const Rep *__restrict__ reps,
+                                                              const uint32_t *__restrict__ site_prefix,
+                                                              const double2 *__restrict__ partials,
+                                                              double *__restrict__ out)
+{
+    const uint32_t r = blockIdx.x;
+    const uint32_t lo = site_prefix[r], hi = site_prefix[r + 1];
+    double a = 0.0, c = 0.0;
+    for (uint32_t j = lo + threadIdx.x; j < hi; j += kBlock) {
+        a += partials[j].x;
+        c += partials[j].y;
+    }
+    const double2 t = block_sum2(a, c);
+    if (threadIdx.x == 0) {
+        const double scale = 1.0 / (3.0 * 2.0 * (double)reps[r].g.half);
+        out[3 * r + 0] = 0.5 * (t.x + t.y) * scale;
+        out[3 * r + 1] = t.x * scale;
+        out[3 * r + 2] = t.y * scale;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_init(BatchDev b, int hot)
+{
+    const uint32_t r = blockIdx.y;
+    const Rep rep = b.reps[r];
+    const Geo &g = rep.g;
+    float4 *L = b.links + rep.link_off;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < 8u * g.half; i += gridDim.x * kBlock) {
+        const uint32_t a = i / g.half, h = i - a * g.half;  // array a = 2 mu + p
+        const uint32_t mu = a >> 1, p = a & 1u;
+        float4 q = make_float4(1.f, 0.f, 0.f, 0.f);
+        if (hot) {
+            const Site s = site_of(g, h, p);
+            q = haar(draw(rep.key, lex_of(g, s), mu, kPurposeHot, 0u, 0u));
+        }
+        L[(size_t)a * g.half + h] = q;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_batch_pack(BatchDev b, uint32_t r,
+                                                       float4 *__restrict__ out)
+{
+    const Rep rep = b.reps[r];
+    const Geo &g = rep.g;
+    const float4 *L = b.links + rep.link_off;
+    const uint32_t lex = blockIdx.x * kBlock + threadIdx.x;
+    if (lex >= 2u * g.half) return;
+    Site s;
+    uint32_t t = lex;
+    s.x[0] = t % g.L[0]; t /= g.L[0];
+    s.x[1] = t % g.L[1]; t /= g.L[1];
+    s.x[2] = t % g.L[2];
+    s.x[3] = t / g.L[2];
+    const uint32_t p = (s.x[0] + s.x[1] + s.x[2] + s.x[3]) & 1u;
+    const uint32_t h = half_of(g, s);
+#pragma unroll
+    for (uint32_t mu = 0; mu < 4; ++mu) out[(size_t)lex * 4 + mu] = L[arr(g, mu, p) + h];
+}
+
+}  // namespace su2
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+using namespace su2;
+
+namespace {
+
+struct Batch {
+    bool ready = false;
+    std::vector<Rep> reps;          // host copy
+    Rep *d_reps = nullptr;
+    uint32_t *d_prefix = nullptr;       // item prefix (current k)
+    uint32_t *d_site_prefix = nullptr;  // plaquette workgroup prefix
+    std::vector<uint32_t> site_prefix;
+    float4 *links = nullptr;
+    size_t link_floats4 = 0;
+    unsigned long long *counters = nullptr;
+    size_t n_counters = 0;             // u64 entries
+    uint32_t *d_sweep = nullptr;
+    uint64_t sweep = 0;
+    unsigned int *d_done = nullptr;
+    unsigned int *d_err = nullptr;
+    double2 *d_partials = nullptr;
+    double *d_out = nullptr;
+    int32_t mode = 0;                  // 0 grouped, 1 persistent
+    uint32_t k = 1;                    // tiles per work item
+    uint32_t lds = 0;
+    uint32_t grid_persistent = 0;
+    unsigned long long spin_limit = 0;
+    uint32_t per_pass = 0;
+    hipGraphExec_t graph = nullptr;     // grouped: one sweep
+    hipGraphExec_t pgraph = nullptr;    // persistent: reset + kernel + tick for pgraph_n sweeps
+    int32_t pgraph_n = 0;
+};
+
+Batch B;
+char berr[512] = "no error";
+
+int bfail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(berr, sizeof berr, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define BTRY(expr)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return bfail(SU2_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+void drop_graphs()
+{
+    if (B.graph) hipGraphExecDestroy(B.graph);
+    if (B.pgraph) hipGraphExecDestroy(B.pgraph);
+    B.graph = B.pgraph = nullptr;
+    B.pgraph_n = 0;
+}
+
+void batch_release()
+{
+    if (B.ready) hipDeviceSynchronize();
+    drop_graphs();
+    void *ptrs[] = { B.d_reps, B.d_prefix, B.d_site_prefix, B.links, B.counters, B.d_sweep,
+                     B.d_done, B.d_err, B.d_partials, B.d_out };
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    B = Batch{};
+}
+
+BatchDev dev()
+{
+    BatchDev d;
+    d.reps = B.d_reps;
+    d.prefix = B.d_prefix;
+    d.n = (uint32_t)B.reps.size();
+    d.links = B.links;
+    d.counters = B.counters;
+    return d;
+}
+
+// item prefix for k tiles per item; uploads reps (items field) and prefix
+int set_items(uint32_t k)
+{
+    std::vector<uint32_t> prefix(B.reps.size() + 1, 0);
+    for (size_t r = 0; r < B.reps.size(); ++r) {
+        B.reps[r].items = (B.reps[r].tiles + k - 1) / k;
+        prefix[r + 1] = prefix[r] + B.reps[r].items;
+    }
+    BTRY(hipDeviceSynchronize());
+    BTRY(hipMemcpy(B.d_reps, B.reps.data(), B.reps.size() * sizeof(Rep), hipMemcpyHostToDevice));
+    BTRY(hipMemcpy(B.d_prefix, prefix.data(), prefix.size() * sizeof(uint32_t),
+                   hipMemcpyHostToDevice));
+    B.per_pass = prefix.back();
+    B.k = k;
+    drop_graphs();
+    return SU2_OK;
+}
+
+int add_node(hipGraph_t g, hipGraphNode_t *prev, const void *func, dim3 grid, dim3 block,
+             unsigned lds, void **args)
+{
+    hipKernelNodeParams kp{};
+    kp.func = const_cast<void *>(func);
+    kp.gridDim = grid;
+    kp.blockDim = block;
+    kp.sharedMemBytes = lds;
+    kp.kernelParams = args;
+    hipGraphNode_t node;
+    hipError_t e = hipGraphAddKernelNode(&node, g, *prev ? prev : nullptr, *prev ? 1 : 0, &kp);
+    if (e != hipSuccess) return bfail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+    *prev = node;
+    return SU2_OK;
+}
+
+int build_grouped_graph()
+{
+    hipGraph_t g;
+    BTRY(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    int rc = SU2_OK;
+    BatchDev d = dev();
+    const uint32_t *sp = B.d_sweep;
+    uint32_t k = B.k;
+    uint32_t pp[8], mm[8];
+    for (int i = 0; i < 8 && rc == SU2_OK; ++i) {
+        pp[i] = i < 4 ? 1u : 0u;  // odd sites first (Sec. 2.4)
+        mm[i] = (uint32_t)(i & 3);
+        void *args[] = { &d, &pp[i], &mm[i], &sp, &k };
+        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_pass), dim3(B.per_pass),
+                      dim3(kBlock), B.lds, args);
+    }
+    uint32_t one = 1;
+    uint32_t *spw = B.d_sweep;
+    if (rc == SU2_OK) {
+        void *args[] = { &spw, &one };
+        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_tick), dim3(1), dim3(1), 0, args);
+    }
+    if (rc == SU2_OK) {
+        hipError_t e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = bfail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    hipGraphDestroy(g);
+    return rc;
+}
+
+int build_persistent_graph(int32_t n)
+{
+    if (B.pgraph) hipGraphExecDestroy(B.pgraph);
+    B.pgraph = nullptr;
+    hipGraph_t g;
+    BTRY(hipGraphCreate(&g, 0));
+    hipGraphNode_t prev = nullptr;
+    BatchDev d = dev();
+    unsigned int *done = B.d_done, *err = B.d_err;
+    uint32_t nrep = (uint32_t)B.reps.size();
+    void *a0[] = { &done, &nrep, &err };
+    int rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_reset), dim3(1), dim3(kBlock),
+                      0, a0);
+    const uint32_t *sp = B.d_sweep;
+    uint32_t ns = (uint32_t)n, k = B.k;
+    unsigned long long lim = B.spin_limit;
+    if (rc == SU2_OK) {
+        void *a1[] = { &d, &sp, &ns, &k, &done, &err, &lim };
+        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_persistent),
+                      dim3(B.grid_persistent), dim3(kBlock), B.lds, a1);
+    }
+    uint32_t *spw = B.d_sweep;
+    if (rc == SU2_OK) {
+        void *a2[] = { &spw, &ns };
+        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_tick), dim3(1), dim3(1), 0, a2);
+    }
+    if (rc == SU2_OK) {
+        hipError_t e = hipGraphInstantiate(&B.pgraph, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = bfail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    hipGraphDestroy(g);
+    if (rc == SU2_OK) B.pgraph_n = n;
+    return rc;
+}
+
+// co-resident workgroups of the persistent kernel at the current LDS reservation
+int size_persistent_grid()
+{
+    int dev_id = 0, ncu = 0, per_cu = 0, clk_khz = 0;
+    BTRY(hipGetDevice(&dev_id));
+    BTRY(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev_id));
+    BTRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &per_cu, reinterpret_cast<const void *>(&k_batch_persistent), kBlock, B.lds));
+    BTRY(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, dev_id));
+    if (per_cu < 1) return bfail(SU2_EDEVICE, "persistent kernel does not fit on a compute unit");
+    B.grid_persistent = (uint32_t)(ncu * per_cu);
+    if (B.spin_limit == 0) B.spin_limit = (unsigned long long)clk_khz * 1000ull * 2ull;  // 2 s
+    return SU2_OK;
+}
+
+int check_error_flag()
+{
+    unsigned int err = 0;
+    BTRY(hipMemcpy(&err, B.d_err, sizeof err, hipMemcpyDeviceToHost));
+    if (err) return bfail(SU2_EDEVICE, "a persistent-kernel dependency wait exceeded its time limit");
+    return SU2_OK;
+}
+
+int run_batch(int32_t n)
+{
+    if (n <= 0) return SU2_OK;
+    if (B.mode == 0) {
+        if (!B.graph) {
+            int rc = build_grouped_graph();
+            if (rc) return rc;
+        }
+        for (int32_t i = 0; i < n; ++i) BTRY(hipGraphLaunch(B.graph, nullptr));
+    } else {
+        // items of one launch must stay below 2^32
+        const uint64_t per_sweep = 8ull * B.per_pass;
+        const int32_t chunk = (int32_t)std::min<uint64_t>((uint64_t)n, 0xffffffffull / per_sweep);
+        if (chunk < 1) return bfail(SU2_EINVAL, "batch too large for one persistent launch");
+        int32_t left = n;
+        while (left > 0) {
+            const int32_t m = std::min(left, chunk);
+            if (!B.pgraph || B.pgraph_n != m) {
+                int rc = build_persistent_graph(m);
+                if (rc) return rc;
+            }
+            BTRY(hipGraphLaunch(B.pgraph, nullptr));
+            left -= m;
+        }
+        BTRY(hipDeviceSynchronize());
+        int rc = check_error_flag();
+        if (rc) return rc;
+    }
+    B.sweep += (uint64_t)n;
+    return SU2_OK;
+}
+
+int batch_ready()
+{
+    if (!B.ready) return bfail(SU2_ESTATE, "no batch: call su2_batch_init first");
+    return SU2_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int su2_batch_init(int32_t n, const int32_t *dims, const double *betas, const uint64_t *seeds,
+                   int32_t start)
+{
+    if (n < 1 || n > 4096) return bfail(SU2_EINVAL, "n must be in 1..4096");
+    if (!dims || !betas || !seeds) return bfail(SU2_EINVAL, "NULL argument");
+    if (start != SU2_COLD && start != SU2_HOT) return bfail(SU2_EINVAL, "start must be 0 or 1");
+    std::vector<Rep> reps((size_t)n);
+    uint64_t off = 0, coff = 0;
+    std::vector<uint32_t> site_prefix((size_t)n + 1, 0);
+    for (int32_t r = 0; r < n; ++r) {
+        uint64_t V = 1;
+        for (int d = 0; d < 4; ++d) {
+            const int32_t L = dims[4 * r + d];
+            if (L < 2 || (L & 1)) return bfail(SU2_EINVAL, "replica %d: extents must be even and >= 2", r);
+            V *= (uint64_t)L;
+        }
+        if (V / 2 * 16 > 0xffffffffull) return bfail(SU2_EINVAL, "replica %d too large for a batch", r);
+        if (!std::isfinite(betas[r]) || betas[r] < 0.0) return bfail(SU2_EINVAL, "replica %d: bad beta", r);
+        Rep &R = reps[(size_t)r];
+        Geo &g = R.g;
+        for (int d = 0; d < 4; ++d) g.L[d] = (uint32_t)dims[4 * r + d];
+        g.H0 = g.L[0] / 2;
+        g.half = (uint32_t)(V / 2);
+        g.st[0] = 1;
+        g.st[1] = g.H0;
+        g.st[2] = g.H0 * g.L[1];
+        g.st[3] = g.H0 * g.L[1] * g.L[2];
+        for (int d = 0; d < 4; ++d) g.wrap[d] = (g.L[d] - 1) * g.st[d];
+        g.dH0 = make_fastdiv(g.H0);
+        g.dL1 = make_fastdiv(g.L[1]);
+        g.dL2 = make_fastdiv(g.L[2]);
+        g.dL0 = make_fastdiv(g.L[0]);
+        R.key = Key{ (uint32_t)(seeds[r] & 0xffffffffu), (uint32_t)(seeds[r] >> 32) };
+        R.beta = (float)betas[r];
+        R.tiles = (g.half + kBlock - 1) / kBlock;
+        R.items = R.tiles;
+        R.link_off = off;
+        R.ctr_off = coff;
+        off += 4 * V;
+        coff += (uint64_t)R.tiles * (kBlock / kWave) * 2;
+        site_prefix[(size_t)r + 1] = site_prefix[(size_t)r] + (uint32_t)((V + kBlock - 1) / kBlock);
+    }
+    batch_release();
+    B.reps = reps;
+    B.site_prefix = site_prefix;
+    B.link_floats4 = off;
+    B.n_counters = coff;
+    const size_t np = site_prefix.back();
+    if (hipMalloc(&B.d_reps, reps.size() * sizeof(Rep)) != hipSuccess ||
+        hipMalloc(&B.d_prefix, (reps.size() + 1) * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&B.d_site_prefix, site_prefix.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&B.links, off * sizeof(float4)) != hipSuccess ||
+        hipMalloc(&B.counters, coff * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&B.d_sweep, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&B.d_done, reps.size() * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&B.d_err, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&B.d_partials, np * sizeof(double2)) != hipSuccess ||
+        hipMalloc(&B.d_out, reps.size() * 3 * sizeof(double)) != hipSuccess) {
+        hipGetLastError();
+        batch_release();
+        return bfail(SU2_ENOMEM, "cannot allocate the batch");
+    }
+    B.ready = true;
+    BTRY(hipMemcpy(B.d_site_prefix, site_prefix.data(), site_prefix.size() * sizeof(uint32_t),
+                   hipMemcpyHostToDevice));
+    BTRY(hipMemset(B.counters, 0, coff * sizeof(unsigned long long)));
+    BTRY(hipMemset(B.d_sweep, 0, sizeof(uint32_t)));
+    BTRY(hipMemset(B.d_err, 0, sizeof(unsigned int)));
+    int rc = set_items(1);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_batch_init, dim3(256, (uint32_t)n), dim3(kBlock), 0, nullptr, dev(),
+                       start == SU2_HOT);
+    BTRY(hipGetLastError());
+    BTRY(hipDeviceSynchronize());
+    return size_persistent_grid();
+}
+
+int su2_batch_sweep(int32_t n)
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    if (n < 0) return bfail(SU2_EINVAL, "n must be >= 0");
+    if (B.sweep + (uint64_t)n > 0xffffffffull) return bfail(SU2_EINVAL, "sweep index would pass 2^32 - 1");
+    return run_batch(n);
+}
+
+int su2_batch_set_mode(int32_t mode, int32_t tiles_per_item, int32_t lds_bytes)
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    if (mode < 0 || mode > 1 || tiles_per_item < 1 || tiles_per_item > 64 || lds_bytes < 0 ||
+        lds_bytes > 65536)
+        return bfail(SU2_EINVAL, "mode 0/1, tiles_per_item 1..64, lds_bytes 0..65536");
+    B.mode = mode;
+    B.lds = (uint32_t)lds_bytes;
+    rc = set_items((uint32_t)tiles_per_item);
+    if (rc) return rc;
+    return size_persistent_grid();
+}
+
+int su2_batch_set_spin_limit(uint64_t ticks)
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    B.spin_limit = ticks ? ticks : 1;
+    drop_graphs();
+    return SU2_OK;
+}
+
+int su2_batch_tune(int32_t sweeps, int32_t out[3])
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    if (sweeps < 1) return bfail(SU2_EINVAL, "sweeps must be >= 1");
+    // time on a scratch copy: save links, counters and sweep index, restore after
+    float4 *save_l = nullptr;
+    unsigned long long *save_c = nullptr;
+    if (hipMalloc(&save_l, B.link_floats4 * sizeof(float4)) != hipSuccess ||
+        hipMalloc(&save_c, B.n_counters * sizeof(unsigned long long)) != hipSuccess) {
+        hipGetLastError();
+        if (save_l) hipFree(save_l);
+        return bfail(SU2_ENOMEM, "cannot allocate the tuning copy");
+    }
+    BTRY(hipMemcpy(save_l, B.links, B.link_floats4 * sizeof(float4), hipMemcpyDeviceToDevice));
+    BTRY(hipMemcpy(save_c, B.counters, B.n_counters * sizeof(unsigned long long), hipMemcpyDeviceToDevice));
+    const uint64_t sweep0 = B.sweep;
+    struct Cand { int32_t mode, k, lds; };
+    std::vector<Cand> cands;
+    for (int32_t mode : { 0, 1 })
+        for (int32_t k : { 1, 2, 4 })
+            for (int32_t lds : { 0, 24576 }) cands.push_back({ mode, k, lds });
+    float best = 1e30f;
+    Cand bc{ 0, 1, 0 };
+    hipEvent_t e0, e1;
+    BTRY(hipEventCreate(&e0));
+    BTRY(hipEventCreate(&e1));
+    for (const Cand &c : cands) {
+        rc = su2_batch_set_mode(c.mode, c.k, c.lds);
+        if (rc) break;
+        rc = run_batch(1);  // build graphs, warm up
+        if (rc) break;
+        BTRY(hipDeviceSynchronize());
+        BTRY(hipEventRecord(e0, nullptr));
+        rc = run_batch(sweeps);
+        if (rc) break;
+        BTRY(hipEventRecord(e1, nullptr));
+        BTRY(hipEventSynchronize(e1));
+        float ms = 0.f;
+        BTRY(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < best) {
+            best = ms;
+            bc = c;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    BTRY(hipMemcpy(B.links, save_l, B.link_floats4 * sizeof(float4), hipMemcpyDeviceToDevice));
+    BTRY(hipMemcpy(B.counters, save_c, B.n_counters * sizeof(unsigned long long), hipMemcpyDeviceToDevice));
+    const uint32_t s32 = (uint32_t)sweep0;
+    BTRY(hipMemcpy(B.d_sweep, &s32, sizeof s32, hipMemcpyHostToDevice));
+    B.sweep = sweep0;
+    hipFree(save_l);
+    hipFree(save_c);
+    if (rc) return rc;
+    rc = su2_batch_set_mode(bc.mode, bc.k, bc.lds);
+    if (rc) return rc;
+    if (out) {
+        out[0] = bc.mode;
+        out[1] = bc.k;
+        out[2] = bc.lds;
+    }
+    return SU2_OK;
+}
+
+int su2_batch_plaquette(double *out)
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    if (!out) return bfail(SU2_EINVAL, "out is NULL");
+    const uint32_t n = (uint32_t)B.reps.size();
+    hipLaunchKernelGGL(k_batch_plaquette, dim3(B.site_prefix.back()), dim3(kBlock), 0, nullptr,
+                       dev(), B.d_site_prefix, B.d_partials);
+    hipLaunchKernelGGL(k_batch_plaq_reduce, dim3(n), dim3(kBlock), 0, nullptr, B.d_reps,
+                       B.d_site_prefix, B.d_partials, B.d_out);
+    BTRY(hipGetLastError());
+    BTRY(hipMemcpy(out, B.d_out, (size_t)n * 3 * sizeof(double), hipMemcpyDeviceToHost));
+    return SU2_OK;
+}
+
+int su2_batch_links(int32_t r, float *host_out, size_t n_floats)
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    if (r < 0 || r >= (int32_t)B.reps.size()) return bfail(SU2_EINVAL, "no replica %d", r);
+    const uint64_t V = 2ull * B.reps[(size_t)r].g.half;
+    if (!host_out || n_floats != V * 16) return bfail(SU2_EINVAL, "n_floats must be 16*V");
+    float4 *stage = nullptr;
+    if (hipMalloc(&stage, n_floats * sizeof(float)) != hipSuccess) {
+        hipGetLastError();
+        return bfail(SU2_ENOMEM, "cannot allocate the staging buffer");
+    }
+    hipLaunchKernelGGL(k_batch_pack, dim3((uint32_t)((V + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       nullptr, dev(), (uint32_t)r, stage);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(host_out, stage, n_floats * sizeof(float), hipMemcpyDeviceToHost);
+    hipFree(stage);
+    if (e != hipSuccess) return bfail(SU2_EDEVICE, "su2_batch_links: %s", hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int su2_batch_counters(int32_t r, uint64_t out[2])
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    if (r < 0 || r >= (int32_t)B.reps.size() || !out) return bfail(SU2_EINVAL, "bad replica or out");
+    const Rep &R = B.reps[(size_t)r];
+    const size_t m = (size_t)R.tiles * (kBlock / kWave) * 2;
+    std::vector<unsigned long long> h(m);
+    BTRY(hipMemcpy(h.data(), B.counters + R.ctr_off, m * sizeof(unsigned long long),
+                   hipMemcpyDeviceToHost));
+    out[0] = out[1] = 0;
+    for (size_t i = 0; i < m; i += 2) {
+        out[0] += h[i];
+        out[1] += h[i + 1];
+    }
+    return SU2_OK;
+}
+
+int su2_batch_sweep_index(uint64_t *out)
+{
+    int rc = batch_ready();
+    if (rc) return rc;
+    if (!out) return bfail(SU2_EINVAL, "out is NULL");
+    *out = B.sweep;
+    return SU2_OK;
+}
+
+const char *su2_batch_last_error(void) { return berr; }
+
+void su2_batch_finalize(void) { batch_release(); }
+
+}  // extern "C"

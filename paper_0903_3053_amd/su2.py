@@ -22,7 +22,9 @@ EXPORTS = (
     "su2_init", "su2_init_ex", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_plaquette", "su2_plaquette_st",
     "su2_polyakov", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
     "su2_counters", "su2_set_stream", "su2_set_plan", "su2_tune", "su2_philox", "su2_synchronize", "su2_last_error",
-    "su2_finalize",
+    "su2_finalize", "su2_batch_init", "su2_batch_sweep", "su2_batch_set_mode", "su2_batch_tune",
+    "su2_batch_set_spin_limit", "su2_batch_plaquette", "su2_batch_links", "su2_batch_counters",
+    "su2_batch_sweep_index", "su2_batch_last_error", "su2_batch_finalize",
 )
 
 
@@ -76,6 +78,17 @@ def load():
         "su2_synchronize": ([], ctypes.c_int),
         "su2_last_error": ([], ctypes.c_char_p),
         "su2_finalize": ([], None),
+        "su2_batch_init": ([ctypes.c_int32, i32p, dp, u64p, ctypes.c_int32], ctypes.c_int),
+        "su2_batch_sweep": ([ctypes.c_int32], ctypes.c_int),
+        "su2_batch_set_mode": ([ctypes.c_int32, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "su2_batch_tune": ([ctypes.c_int32, i32p], ctypes.c_int),
+        "su2_batch_set_spin_limit": ([ctypes.c_uint64], ctypes.c_int),
+        "su2_batch_plaquette": ([dp], ctypes.c_int),
+        "su2_batch_links": ([ctypes.c_int32, fp, ctypes.c_size_t], ctypes.c_int),
+        "su2_batch_counters": ([ctypes.c_int32, u64p], ctypes.c_int),
+        "su2_batch_sweep_index": ([u64p], ctypes.c_int),
+        "su2_batch_last_error": ([], ctypes.c_char_p),
+        "su2_batch_finalize": ([], None),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -243,3 +256,77 @@ def su2_finalize():
     load().su2_finalize()
     _keep.pop("links", None)
     _keep.pop("dims", None)
+
+
+# ---- batched replicas --------------------------------------------------------
+_batch = {}
+
+
+def _bcheck(rc):
+    if rc != SU2_OK:
+        raise Su2Error(rc, _lib.su2_batch_last_error().decode())
+    return rc
+
+
+def su2_batch_init(dims_list, betas, seeds, start):
+    lib = load()
+    d = np.ascontiguousarray(np.asarray(dims_list, dtype=np.int32).reshape(-1, 4))
+    b = np.ascontiguousarray(np.asarray(betas, dtype=np.float64))
+    sd = np.ascontiguousarray(np.asarray(seeds, dtype=np.uint64))
+    if not (len(d) == len(b) == len(sd)):
+        raise ValueError("dims, betas and seeds must have one entry per replica")
+    _bcheck(lib.su2_batch_init(len(d), _ptr(d, ctypes.c_int32), _ptr(b, ctypes.c_double),
+                               _ptr(sd, ctypes.c_uint64), int(start)))
+    _batch["dims"] = [tuple(int(v) for v in row) for row in d]
+
+
+def su2_batch_sweep(n=1):
+    _bcheck(load().su2_batch_sweep(int(n)))
+
+
+def su2_batch_set_mode(mode, tiles_per_item=1, lds_bytes=0):
+    _bcheck(load().su2_batch_set_mode(int(mode), int(tiles_per_item), int(lds_bytes)))
+
+
+def su2_batch_tune(sweeps=2):
+    out = (ctypes.c_int32 * 3)()
+    _bcheck(load().su2_batch_tune(int(sweeps), out))
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def su2_batch_set_spin_limit(ticks):
+    _bcheck(load().su2_batch_set_spin_limit(ctypes.c_uint64(int(ticks))))
+
+
+def su2_batch_plaquette():
+    n = len(_batch.get("dims", []))
+    out = np.zeros((max(n, 1), 3))
+    _bcheck(load().su2_batch_plaquette(_ptr(out, ctypes.c_double)))
+    return out[:n]
+
+
+def su2_batch_links(r):
+    if not 0 <= int(r) < len(_batch.get("dims", [])):
+        raise Su2Error(SU2_EINVAL, f"no replica {r}")
+    dims = _batch["dims"][r]
+    V = int(np.prod(dims))
+    out = np.empty((V, 4, 4), dtype=np.float32)
+    _bcheck(load().su2_batch_links(int(r), _ptr(out, ctypes.c_float), out.size))
+    return out
+
+
+def su2_batch_counters(r):
+    out = np.zeros(2, dtype=np.uint64)
+    _bcheck(load().su2_batch_counters(int(r), _ptr(out, ctypes.c_uint64)))
+    return int(out[0]), int(out[1])
+
+
+def su2_batch_sweep_index():
+    out = ctypes.c_uint64(0)
+    _bcheck(load().su2_batch_sweep_index(ctypes.byref(out)))
+    return out.value
+
+
+def su2_batch_finalize():
+    load().su2_batch_finalize()
+    _batch.clear()

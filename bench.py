@@ -77,6 +77,46 @@ def cpu_baseline(w, sweeps=8):
                       f"lattice from the same hot start, {dt:.2f} s wall"}
 
 
+def batched_replicas(su2, sweeps=500, compare_sweeps=50):
+    """The batched-replica workload: 64 lattices, L uniform on {8, 12, 16, 20,
+    24}, beta uniform on [1.8, 2.8], hot starts from per-replica seeds, `sweeps`
+    sweeps of every replica in the tuned launch mode; also the grouped and the
+    persistent mode timed side by side."""
+    import numpy as np
+    import torch
+    import su2_inputs
+    table = su2_inputs.replica_table(64, 1)
+    dims = [t["dims"] for t in table]
+    V = sum(int(np.prod(d)) for d in dims)
+    su2.su2_batch_init(dims, [t["beta"] for t in table], [t["seed"] for t in table], 1)
+    modes = {}
+    for name, mode in (("grouped", (0, 1, 0)), ("persistent", (1, 1, 0))):
+        su2.su2_batch_set_mode(*mode)
+        su2.su2_batch_sweep(2)  # build the graph, warm up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su2.su2_batch_sweep(compare_sweeps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        modes[name] = 4 * V * compare_sweeps / dt
+    su2.su2_batch_init(dims, [t["beta"] for t in table], [t["seed"] for t in table], 1)
+    chosen = su2.su2_batch_tune(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    su2.su2_batch_sweep(sweeps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    P = su2.su2_batch_plaquette()
+    su2.su2_batch_finalize()
+    upd = 4 * V * sweeps
+    return {"workload": "64 replicas, L uniform on {8,12,16,20,24}, beta uniform on [1.8,2.8], hot, "
+                        f"{sweeps} sweeps", "sites": V, "value": upd / dt, "unit": "link updates/s",
+            "seconds": dt, "algorithmic_GBps": upd * BYTES_PER_UPDATE / dt / 1e9,
+            "mode": {"persistent": bool(chosen[0]), "tiles_per_item": chosen[1], "lds_bytes": chosen[2]},
+            "updates_per_s_by_mode": modes,
+            "plaquette_range": [float(P[:, 0].min()), float(P[:, 0].max())]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +124,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--lattice", type=int, default=64, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched-replica and learned-proposal workloads")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--plan", type=int, nargs=2, metavar=("ORDER", "LDS"), default=None,
                     help="use this pass-kernel launch plan instead of tuning")
@@ -179,6 +221,9 @@ def main():
     }
     att, fail = su2.su2_counters()
     rec["observables"]["kp_attempts_per_update"] = att / max(1, 4 * V * (args.steps + args.warmup))
+    su2.su2_finalize()
+    if not args.no_extras:
+        rec["batched_replicas"] = batched_replicas(su2)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     su2.su2_finalize()

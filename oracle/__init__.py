@@ -65,6 +65,13 @@ def _load():
     lib.oracle_polyakov.restype = ctypes.c_int
     lib.oracle_staple_action.argtypes = [i32p, dp, dp]
     lib.oracle_staple_action.restype = ctypes.c_int
+    lib.oracle_pass_imh.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                    ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int,
+                                    ctypes.c_double, i8p, dp, u64p]
+    lib.oracle_pass_imh.restype = ctypes.c_int
+    lib.oracle_sweep_imh.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
+                                     ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, u64p]
+    lib.oracle_sweep_imh.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -201,6 +208,50 @@ def update_sites(dims, U, beta, seed, sweep_index, mu, sites, prec32=True):
     if rc:
         raise ValueError("oracle_update_sites rejected its arguments")
     return out, tries, margin
+
+
+def _table(table):
+    t = np.ascontiguousarray(np.asarray(table, dtype=np.float64))
+    if t.ndim != 2 or t.shape[1] != 33 or t.shape[0] < 2:
+        raise ValueError("knot table must have shape [G >= 2, 33]")
+    return t
+
+
+def imh_pass(dims, U, beta, seed, sweep_index, parity, mu, table, alpha_max=40.0, prec32=True):
+    """In-place pass with the learned independence-Metropolis proposal.
+    Returns (result codes per site, margins, proposals, accepts); codes 10 =
+    accepted, 11 = rejected, 0..9 = plain heat-bath codes."""
+    lib = _load()
+    d = _dims(dims)
+    if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
+        raise ValueError("U must be a C-contiguous float64 array")
+    t = _table(table)
+    V = volume(dims)
+    res = np.full(V, -1, dtype=np.int8)
+    margin = np.full(V, np.nan)
+    stats = np.zeros(2, dtype=np.uint64)
+    rc = lib.oracle_pass_imh(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
+                             int(sweep_index), int(parity), int(mu), int(bool(prec32)),
+                             _ptr(U, ctypes.c_double), _ptr(t, ctypes.c_double), len(t),
+                             float(alpha_max), _ptr(res, ctypes.c_int8),
+                             _ptr(margin, ctypes.c_double), _ptr(stats, ctypes.c_uint64))
+    if rc:
+        raise ValueError("oracle_pass_imh rejected its arguments")
+    return res, margin, int(stats[0]), int(stats[1])
+
+
+def imh_sweep(dims, U, beta, seed, sweep_index, table, alpha_max=40.0, prec32=True):
+    lib = _load()
+    d = _dims(dims)
+    t = _table(table)
+    stats = np.zeros(2, dtype=np.uint64)
+    rc = lib.oracle_sweep_imh(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
+                              int(sweep_index), int(bool(prec32)), _ptr(U, ctypes.c_double),
+                              _ptr(t, ctypes.c_double), len(t), float(alpha_max),
+                              _ptr(stats, ctypes.c_uint64))
+    if rc:
+        raise ValueError("oracle_sweep_imh rejected its arguments")
+    return int(stats[0]), int(stats[1])
 
 
 def sweep(dims, U, beta, seed, sweep_index, prec32=True):

@@ -394,6 +394,147 @@ int oracle_update_sites(const int dims[4], double beta, uint64_t seed, uint32_t 
     return 0;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Learned-proposal variant: an independence-Metropolis step for x0.          */
+/* The proposal q(x0 | alpha) is a monotone piecewise-linear inverse CDF with */
+/* 32 equal-probability segments between knots y_0 = -1 < ... < y_32 = 1; the */
+/* knots at alpha come from `table` (G rows of 33 knots at alpha_g = g *      */
+/* alpha_max / (G - 1)) by linear interpolation in alpha.  One Philox call    */
+/* (purpose 2, slot 0): u0 -> proposal, u1 -> accept, (u2, u3) -> direction.  */
+/* The target for x0 is pi(x) ~ sqrt(1 - x^2) exp(alpha x) (the same local     */
+/* conditional the heat-bath samples); the step accepts with probability      */
+/* min(1, [pi(x') / q(x')] / [pi(x) / q(x)]), x = dot(U_old, V), so it leaves */
+/* that conditional invariant.  alpha = 0 takes the Haar draw and alpha above */
+/* alpha_max the capped Kennedy-Pendleton draw, as in the plain pass.         */
+/* ------------------------------------------------------------------------- */
+static void knots_at(const double *table, int G, double alpha_max, double alpha, double y[33])
+{
+    double t = alpha / (alpha_max / (double)(G - 1));
+    int g0 = (int)floor(t);
+    if (g0 > G - 2) g0 = G - 2;
+    if (g0 < 0) g0 = 0;
+    double f = t - (double)g0;
+    for (int j = 0; j < 33; ++j)
+        y[j] = (1.0 - f) * table[g0 * 33 + j] + f * table[(g0 + 1) * 33 + j];
+}
+
+static int segment_of(const double y[33], double x)
+{
+    int j = 0;
+    while (j < 31 && x >= y[j + 1]) ++j;
+    return j;
+}
+
+/* *res: 10 = proposal accepted, 11 = rejected (link kept), or the plain-pass
+ * codes (0..9) when the plain heat-bath handled the update. */
+static void update_one_imh(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int mu,
+                           int prec32, const double *U, long lex, const double *table, int G,
+                           double alpha_max, double out[4], int *res, double *margin)
+{
+    double w[4];
+    oracle_staple(dims, U, lex, mu, w);
+    double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+    double alpha = beta * k;
+    if (alpha == 0.0 || alpha > alpha_max) {
+        update_one(dims, beta, seed, sweep, mu, prec32, U, lex, out, res, margin);
+        return;
+    }
+    double y[33];
+    knots_at(table, G, alpha_max, alpha, y);
+    double u[4];
+    draw4(seed, (uint32_t)lex, mu, PURPOSE_IMH, sweep, 0u, u);
+    int jp = (int)floor(32.0 * u[0]);
+    if (jp > 31) jp = 31;
+    double xp = y[jp] + (32.0 * u[0] - (double)jp) * (y[jp + 1] - y[jp]);
+    double V[4] = { w[0] / k, w[1] / k, w[2] / k, w[3] / k };
+    const double *uo = link(U, lex, mu);
+    double xc = uo[0] * V[0] + uo[1] * V[1] + uo[2] * V[2] + uo[3] * V[3];
+    if (xc > 1.0) xc = 1.0;
+    if (xc < -1.0) xc = -1.0;
+    int jc = segment_of(y, xc);
+    /* log of the acceptance ratio: pi ratio times the inverse q ratio (q is
+     * (1/32) / width on each segment) */
+    double lr_terms[3];
+    double num = 1.0 - xp * xp, den = 1.0 - xc * xc;
+    int accept_always = 0, reject_always = 0;
+    if (num <= 0.0) reject_always = 1;
+    else if (den <= 0.0) accept_always = 1;
+    lr_terms[0] = (num > 0.0 && den > 0.0) ? 0.5 * log(num / den) : 0.0;
+    lr_terms[1] = alpha * (xp - xc);
+    lr_terms[2] = log((y[jp + 1] - y[jp]) / (y[jc + 1] - y[jc]));
+    int acc;
+    double m;
+    if (reject_always) { acc = 0; m = INFINITY; }
+    else if (accept_always) { acc = 1; m = INFINITY; }
+    else if (prec32) {
+        float lr = (float)lr_terms[0] + (float)lr_terms[1] + (float)lr_terms[2];
+        float lu = (float)log(u[1]);
+        acc = lu <= lr;
+        m = fabs((double)lu - (double)lr);
+    } else {
+        double lr = lr_terms[0] + lr_terms[1] + lr_terms[2];
+        double lu = log(u[1]);
+        acc = lu <= lr;
+        m = fabs(lu - lr);
+    }
+    *margin = m;
+    if (!acc) {
+        memcpy(out, uo, 4 * sizeof(double));
+        *res = 11;
+        return;
+    }
+    double c = 2.0 * u[2] - 1.0, phi = 2.0 * M_PI * u[3];
+    double sn = sqrt(1.0 - c * c), am = sqrt(1.0 - xp * xp);
+    double X[4] = { xp, am * sn * cos(phi), am * sn * sin(phi), am * c };
+    double Un[4];
+    oracle_qmul(X, V, Un);
+    store_unit(out, Un, prec32);
+    *res = 10;
+}
+
+/* One pass with the learned proposal; stats[0] += independence-Metropolis
+ * proposals, stats[1] += accepted ones (updates outside the table's alpha
+ * range go to the plain heat-bath and are not counted). */
+int oracle_pass_imh(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int parity,
+                    int mu, int prec32, double *U, const double *table, int G, double alpha_max,
+                    int8_t *res_out, double *margin, uint64_t stats[2])
+{
+    geom_t g;
+    if (geom_init(&g, dims)) return -1;
+    if (parity < 0 || parity > 1 || mu < 0 || mu > 3 || !(beta >= 0.0) || G < 2 ||
+        !(alpha_max > 0.0))
+        return -1;
+    uint64_t prop = 0, acc = 0;
+#pragma omp parallel for schedule(static) reduction(+ : prop, acc)
+    for (long lex = 0; lex < g.V; ++lex) {
+        int x[4];
+        coords(&g, lex, x);
+        if (((x[0] + x[1] + x[2] + x[3]) & 1) != parity) continue;
+        double out[4], m = NAN;
+        int r;
+        update_one_imh(dims, beta, seed, sweep, mu, prec32, U, lex, table, G, alpha_max, out, &r, &m);
+        memcpy(U + (lex * 4 + mu) * 4, out, sizeof out);
+        if (res_out) res_out[lex] = (int8_t)r;
+        if (margin) margin[lex] = m;
+        if (r >= 10) prop += 1;
+        if (r == 10) acc += 1;
+    }
+    if (stats) { stats[0] += prop; stats[1] += acc; }
+    return 0;
+}
+
+/* A sweep with the learned proposal (same pass order as oracle_sweep). */
+int oracle_sweep_imh(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int prec32,
+                     double *U, const double *table, int G, double alpha_max, uint64_t stats[2])
+{
+    for (int parity = 1; parity >= 0; --parity)
+        for (int mu = 0; mu < 4; ++mu)
+            if (oracle_pass_imh(dims, beta, seed, sweep, parity, mu, prec32, U, table, G,
+                                alpha_max, NULL, NULL, stats))
+                return -1;
+    return 0;
+}
+
 /* One sweep (Sec. 2.4): odd sites for mu = 0..3, then even sites for
  * mu = 0..3; the Philox sweep index is `sweep` for all eight passes. */
 int oracle_sweep(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int prec32,

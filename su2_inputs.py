@@ -68,3 +68,22 @@ def alpha_grid(n=4096, alpha_max=40.0):
 def random_alphas(n, seed, alpha_max=40.0):
     rng = np.random.default_rng(seed)
     return rng.uniform(0.0, alpha_max, size=n)
+
+
+# The learned proposal's network 1 -> 64 -> 64 -> 33 has 6433 parameters in the
+# order W1 (64x1), b1 (64), W2 (64x64), b2 (64), W3 (33x64), b3 (33).
+MLP_SHAPES = ((64, 1), (64,), (64, 64), (64,), (33, 64), (33,))
+
+
+def mlp_init(seed):
+    """Initial parameters (float32, flat): weights uniform in
+    [-1/sqrt(fan_in), 1/sqrt(fan_in)], biases zero."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            bound = 1.0 / np.sqrt(shape[1])
+            parts.append(rng.uniform(-bound, bound, size=shape).ravel())
+        else:
+            parts.append(np.zeros(shape))
+    return np.concatenate(parts).astype(np.float32)

@@ -1,0 +1,144 @@
+"""Pins the learned-proposal pieces of the oracle: the CDF/quantile integrator,
+the network's analytic gradient, BF16 rounding, and the exactness of the
+independence-Metropolis step."""
+import numpy as np
+import pytest
+from scipy import optimize, special, stats
+
+import oracle
+import su2_inputs
+from exact_density import X0Cdf, haar_cdf
+from oracle import cdf, mlp
+
+
+@pytest.mark.parametrize("alpha", [0.5, 2.3, 13.8, 40.0])
+def test_normaliser_closed_form(alpha):
+    # int sqrt(1-t^2) e^{alpha (t-1)} dt = pi I1(alpha) e^{-alpha} / alpha
+    ref = np.pi * special.ive(1, alpha) / alpha
+    assert abs(cdf.normaliser(alpha) / ref - 1) < 1e-12
+
+
+def test_alpha_zero_closed_form():
+    assert abs(cdf.normaliser(0.0) - np.pi / 2) < 1e-13
+    for x in np.linspace(-0.99, 0.99, 13):
+        assert abs(cdf.cdf(x, 0.0) - haar_cdf(x)) < 1e-12
+    y = cdf.knots(0.0)
+    for j in range(1, 32):
+        xj = optimize.brentq(lambda x: haar_cdf(x) - j / 32, -1, 1, xtol=1e-15)
+        assert abs(y[j] - xj) < 1e-11
+
+
+@pytest.mark.parametrize("alpha", [0.7, 8.0, 31.0])
+def test_knots_consistent_and_match_tabulation(alpha):
+    y = cdf.knots(alpha)
+    assert y[0] == -1 and y[32] == 1 and np.all(np.diff(y) > 0)
+    for j in range(1, 32):
+        assert abs(cdf.cdf(y[j], alpha) - j / 32) < 1e-11
+    tab = X0Cdf(alpha)
+    np.testing.assert_allclose(y[1:-1], tab.inverse(np.arange(1, 32) / 32), atol=2e-6)
+
+
+def test_bf16_rounding_matches_library():
+    import torch
+    rng = np.random.default_rng(4)
+    x = np.concatenate([rng.standard_normal(5000).astype(np.float32) * 10,
+                        np.float32([0.0, -0.0, 1.0, 1.00390625, 1.005859375, 3.0e-39])])
+    ref = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    np.testing.assert_array_equal(mlp.bf16_round(x), ref)
+
+
+def test_forward_gives_monotone_knots():
+    th = mlp.bf16_round(su2_inputs.mlp_init(1))
+    y, logw, _ = mlp.forward(th, su2_inputs.alpha_grid(50))
+    assert y.shape == (50, 33)
+    assert np.all(y[:, 0] == -1) and np.all(y[:, -1] == 1)
+    assert np.all(np.diff(y, axis=1) > 0)
+    np.testing.assert_allclose(np.exp(logw).sum(axis=1), 2.0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("rounded", [False, True])
+def test_gradient_matches_finite_differences(rounded):
+    rng = np.random.default_rng(9)
+    th = su2_inputs.mlp_init(2).astype(np.float64) + 0.1 * rng.standard_normal(mlp.NPARAM)
+    if rounded:
+        th = mlp.bf16_round(th)
+    alphas = su2_inputs.random_alphas(7, 3)
+    target = np.log(np.full((7, 32), 2.0 / 32)) + 0.3 * rng.standard_normal((7, 32))
+    L, g = mlp.loss_and_grad(th, alphas, target)
+    idx = np.concatenate([rng.choice(mlp.NPARAM, 60, replace=False),
+                          [0, 64, 128, 4160, 4224, mlp.NPARAM - 34, mlp.NPARAM - 1]])
+    h = 1e-6
+    for i in idx:
+        e = np.zeros(mlp.NPARAM)
+        e[i] = h
+        fd = (mlp.loss_and_grad(th + e, alphas, target)[0]
+              - mlp.loss_and_grad(th - e, alphas, target)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-7 + 1e-6 * abs(g[i]), (i, fd, g[i])
+    # the reserved output 32 never receives gradient
+    W3 = mlp.unpack(g)["W3"]
+    assert np.all(W3[32] == 0) and mlp.unpack(g)["b3"][32] == 0
+
+
+def _imh_chain_samples(table, beta, passes, thin=10, burn=40):
+    """All links equal to g: every (parity 0, mu 1) link has staple 6 g and keeps
+    it while that pass is repeated, so each link runs its own chain at alpha = 6
+    beta.  Returns thinned x0 = dot(U, g) samples and the acceptance rate."""
+    dims = (4, 4, 4, 4)
+    g = np.array([0.5, 0.5, -0.5, 0.5])
+    U = np.tile(g, (256, 4, 1)).copy()
+    par = np.array([sum(np.unravel_index(i, dims)) % 2 for i in range(256)])
+    xs, prop, acc = [], 0, 0
+    for s in range(passes):
+        _, _, p, a = oracle.imh_pass(dims, U, beta, 7, s, 0, 1, table)
+        prop += p
+        acc += a
+        if s >= burn and s % thin == 0:
+            xs.append(U[par == 0, 1] @ g)
+    return np.concatenate(xs), acc / prop
+
+
+def _table_with_row(alpha_exact_row, knots_row):
+    t = np.tile(np.linspace(-1, 1, 33), (41, 1))
+    t[alpha_exact_row] = knots_row
+    return t
+
+
+def test_imh_step_leaves_the_conditional_invariant():
+    beta = 1.0  # alpha = 6: row 6 of a 41-row table on [0, 40]
+    exact = cdf.knots(6.0)
+    x, rate = _imh_chain_samples(_table_with_row(6, exact), beta, 400)
+    assert rate > 0.9
+    assert stats.kstest(x, X0Cdf(6.0)).pvalue > 1e-3
+    # a poor proposal (uniform knots) is slower but still exact
+    x2, rate2 = _imh_chain_samples(np.tile(np.linspace(-1, 1, 33), (41, 1)), beta, 1200, thin=30,
+                                   burn=120)
+    assert rate2 < rate
+    assert stats.kstest(x2, X0Cdf(6.0)).pvalue > 1e-3
+
+
+def test_imh_fallbacks_by_alpha():
+    """Updates whose alpha lies above the table's range use the plain heat-bath
+    (identical links and codes); those inside use the proposal; alpha = 0 takes
+    the Haar branch."""
+    import su2_np
+    dims = (4, 4, 4, 4)
+    beta, amax, mu, parity = 1.2, 3.0, 2, 1
+    U0 = su2_inputs.random_links(dims, 5).astype(np.float64)
+    alpha = beta * np.linalg.norm(su2_np.staples(U0, dims)[:, mu], axis=1)
+    par = np.array([sum(np.unravel_index(i, dims)) % 2 for i in range(256)])
+    sel = par == parity
+    assert np.any(alpha[sel] > amax) and np.any(alpha[sel] <= amax)
+    tab = np.tile(np.linspace(-1, 1, 33), (5, 1))
+    U = U0.copy()
+    res, _, p, a = oracle.imh_pass(dims, U, beta, 1, 0, parity, mu, tab, alpha_max=amax)
+    U2 = U0.copy()
+    plain = oracle.heatbath_pass(dims, U2, beta, 1, 0, parity, mu)
+    hi = sel & (alpha > amax)
+    lo = sel & (alpha <= amax)
+    assert np.all(res[hi] <= 9) and np.all(res[lo] >= 10)
+    np.testing.assert_array_equal(res[hi], plain.tries[hi])
+    np.testing.assert_array_equal(U[hi], U2[hi])
+    assert p == int(lo.sum())
+    U3 = U0.copy()
+    res, _, p, a = oracle.imh_pass(dims, U3, 0.0, 1, 0, parity, mu, tab)
+    assert np.all(res[sel] == 9) and p == 0

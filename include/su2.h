@@ -147,6 +147,67 @@ int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
  * (nullable) receives {order_kind, lds_bytes}.  Synchronises. */
 int su2_tune(int32_t reps, int32_t out[2]);
 
+/* ---- Learned proposal ---------------------------------------------------
+ * The heat-bath's x0 has density ~ sqrt(1 - x^2) exp(alpha x), alpha = beta |W|
+ * (the local conditional of Eqs. (2), (3), (6)).  A small network maps alpha to
+ * a 32-segment monotone piecewise-linear inverse CDF of x0; used as an
+ * independence-Metropolis proposal with the exact acceptance ratio it leaves
+ * that conditional invariant, with the Kennedy-Pendleton draw as the fallback
+ * outside the network's range.  Network: 1 -> 64 -> 64 -> 33 on alpha / 40,
+ * SiLU, BF16 weights with FP32 accumulation; outputs 0..31 give segment widths
+ * 2 softmax(z), output 32 is reserved.  Parameters: 6433 float32 in the order
+ * W1 (64x1), b1 (64), W2 (64x64), b2 (64), W3 (33x64), b3 (33), row-major.
+ * The network and its knot table are one global state, independent of the
+ * lattice context; su2_mlp_last_error() explains a failed su2_mlp_* /
+ * su2_cdf_knots call. */
+
+/* knots[33*i + j] = F^{-1}(j / 32) for alpha = alphas[i] >= 0, the CDF of the
+ * x0 density integrated numerically on the device (FP64). */
+int su2_cdf_knots(const double *alphas, int32_t n, double *knots);
+
+/* Load the FP32 master parameters (n = 6433); the BF16 copy is their
+ * round-to-nearest-even rounding.  Resets the optimiser state. */
+int su2_mlp_set_params(const float *params, size_t n);
+
+/* Read back the FP32 master (nullable) and BF16 (nullable) parameters. */
+int su2_mlp_get_params(float *master, uint16_t *bf16, size_t n);
+
+/* knots[33*i + j] from the network at alphas[i] (BF16 weights). */
+int su2_mlp_forward(const float *alphas, int32_t n, float *knots);
+
+/* Loss (mean over samples and 32 segments of (log w_j - target_logw_j)^2)
+ * and its gradient with respect to the 6433 parameters (at the BF16 values),
+ * from the device's forward and backward kernels. */
+int su2_mlp_loss_grad(const float *alphas, const float *target_logw, int32_t n, float *loss,
+                      float *grad);
+
+/* Train on the device: targets are the CDF knots of the n alphas (in
+ * [0, 40]) integrated by su2_cdf_knots' kernel, then `steps` full-batch Adam
+ * steps with a cosine learning rate from lr0 to lr_min; loss_hist
+ * (nullable) receives the loss before each step. */
+int su2_mlp_train(const double *alphas, int32_t n, int32_t steps, float lr0, float lr_min,
+                  float *loss_hist);
+
+/* Evaluate the network on `points` alphas evenly spaced on [0, 40] into the
+ * knot table the sweep uses (knots at other alphas: linear in alpha between
+ * rows -- the same table serves proposal and correction, so the step stays
+ * exact). */
+int su2_mlp_tabulate(int32_t points);
+
+/* Copy the current knot table (n_floats = 33 * points). */
+int su2_mlp_table(float *host_out, size_t n_floats);
+
+const char *su2_mlp_last_error(void);
+
+/* Proposal of the lattice context's passes: 0 = Kennedy-Pendleton heat-bath;
+ * 1 = the learned independence-Metropolis step (Philox purpose 2, one call per
+ * update) with the heat-bath for alpha = 0 and alpha above 40.  Kind 1 copies
+ * the current knot table into the lattice context.  su2_init resets to 0. */
+int su2_set_proposal(int32_t kind);
+
+/* Learned-proposal updates proposed and accepted since su2_set_proposal(1). */
+int su2_imh_counters(uint64_t out[2]);
+
 /* ---- Batched replicas ---------------------------------------------------
  * A second, independent context: n lattices, each with its own extents
  * dims[4*r .. 4*r+3] (even, >= 2, V/2 * 16 bytes below 4 GiB), coupling

@@ -15,6 +15,7 @@
 
 #include "su2.h"
 #include "su2_kernels.hpp"
+#include "su2_learned.hpp"
 
 using namespace su2;
 
@@ -46,6 +47,10 @@ struct Context {
     PassPlan plan;                      // launch plan of k_pass (tile order, LDS reservation)
     uint32_t *d_order = nullptr;        // device tile-order table of the plan
     int32_t order_kind = 0;
+    int32_t proposal = 0;               // 0 heat-bath, 1 learned independence-Metropolis
+    float *d_table = nullptr;           // this lattice's copy of the knot table
+    ImhTable *d_imh = nullptr;          // device descriptor passed to the pass kernels
+    unsigned long long *d_imh_stats = nullptr;  // per wave: (proposals, accepts)
 };
 
 Context ctx;
@@ -86,6 +91,9 @@ void release_all()
     if (ctx.d_meas) hipFree(ctx.d_meas);
     if (ctx.d_scratch) hipFree(ctx.d_scratch);
     if (ctx.d_order) hipFree(ctx.d_order);
+    if (ctx.d_table) hipFree(ctx.d_table);
+    if (ctx.d_imh) hipFree(ctx.d_imh);
+    if (ctx.d_imh_stats) hipFree(ctx.d_imh_stats);
     if (ctx.d_out) hipFree(ctx.d_out);
     hipStream_t keep = ctx.stream;
     ctx = Context{};
@@ -601,6 +609,74 @@ int su2_tune(int32_t reps, int32_t out[2])
     if (out) {
         out[0] = best_kind;
         out[1] = (int32_t)best_lds;
+    }
+    return SU2_OK;
+}
+
+int su2_set_proposal(int32_t kind)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (kind != 0 && kind != 1) return fail(SU2_EINVAL, "proposal kind must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    if (kind == 0) {
+        ctx.proposal = 0;
+        ctx.plan.imh = nullptr;
+        release_graphs();
+        return SU2_OK;
+    }
+    const float *knots = nullptr;
+    uint32_t G = 0;
+    float amax = 0.f;
+    if (!su2_learned_table(&knots, &G, &amax))
+        return fail(SU2_ESTATE, "no knot table: train or load the network and call su2_mlp_tabulate");
+    if (ctx.d_table) hipFree(ctx.d_table);
+    ctx.d_table = nullptr;
+    if (!ctx.d_imh && hipMalloc(&ctx.d_imh, sizeof(ImhTable)) != hipSuccess) {
+        hipGetLastError();
+        ctx.d_imh = nullptr;
+        return fail(SU2_ENOMEM, "cannot allocate the proposal descriptor");
+    }
+    const size_t stats_bytes = (size_t)ctx.n_waves * 2 * sizeof(unsigned long long);
+    if (!ctx.d_imh_stats && hipMalloc(&ctx.d_imh_stats, stats_bytes) != hipSuccess) {
+        hipGetLastError();
+        ctx.d_imh_stats = nullptr;
+        return fail(SU2_ENOMEM, "cannot allocate proposal counters");
+    }
+    if (hipMalloc(&ctx.d_table, (size_t)G * 33 * sizeof(float)) != hipSuccess) {
+        hipGetLastError();
+        ctx.d_table = nullptr;
+        return fail(SU2_ENOMEM, "cannot allocate the knot table");
+    }
+    HIP_TRY(hipMemcpy(ctx.d_table, knots, (size_t)G * 33 * sizeof(float), hipMemcpyDeviceToDevice));
+    HIP_TRY(hipMemset(ctx.d_imh_stats, 0, stats_bytes));
+    ImhTable t;
+    t.knots = ctx.d_table;
+    t.G = G;
+    t.alpha_max = amax;
+    t.inv_step = (float)((double)(G - 1) / (double)amax);
+    t.stats = ctx.d_imh_stats;
+    HIP_TRY(hipMemcpy(ctx.d_imh, &t, sizeof t, hipMemcpyHostToDevice));
+    ctx.proposal = 1;
+    ctx.plan.imh = ctx.d_imh;
+    release_graphs();
+    return SU2_OK;
+}
+
+int su2_imh_counters(uint64_t out[2])
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    out[0] = out[1] = 0;
+    if (!ctx.d_imh_stats) return SU2_OK;
+    std::vector<unsigned long long> h((size_t)ctx.n_waves * 2);
+    HIP_TRY(hipMemcpyAsync(h.data(), ctx.d_imh_stats, h.size() * sizeof(unsigned long long),
+                           hipMemcpyDeviceToHost, ctx.stream));
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    for (uint32_t w = 0; w < ctx.n_waves; ++w) {
+        out[0] += h[2 * w];
+        out[1] += h[2 * w + 1];
     }
     return SU2_OK;
 }

@@ -38,16 +38,18 @@ __global__ __launch_bounds__(kBlock) void k_init(float4 *__restrict__ links, Geo
 // One heat-bath pass over U_MU(x), parity(x) = p; each workgroup runs one tile.
 // A table can reorder tiles so that the workgroups the hardware sends to one
 // XCD share their neighbour data in L2.
-template <uint32_t MU, bool OFF32, bool MEASURE>
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH>
 __global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, Key key,
                                                  float beta, uint32_t p,
                                                  const uint32_t *__restrict__ sweep_ptr,
                                                  unsigned long long *__restrict__ counters,
                                                  double2 *__restrict__ meas_out,
-                                                 const uint32_t *__restrict__ order)
+                                                 const uint32_t *__restrict__ order,
+                                                 const ImhTable *__restrict__ imh)
 {
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
-    pass_tile<MU, OFF32, MEASURE>(L, g, key, beta, p, *sweep_ptr, tile, counters, meas_out);
+    pass_tile<MU, OFF32, MEASURE, IMH>(L, g, key, beta, p, *sweep_ptr, tile, counters, meas_out,
+                                       imh);
 }
 
 __global__ void k_tick(uint32_t *sweep_ptr)
@@ -226,23 +228,27 @@ hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_
 
 bool use_off32(const Geo &g) { return (uint64_t)g.half * 16u <= 0xffffffffull; }
 
-template <uint32_t MU>
-static const void *pass_func_mu(bool off32, bool measure)
+template <uint32_t MU, bool MEASURE, bool IMH>
+static const void *pass_func_3(bool off32)
 {
-    if (off32)
-        return measure ? reinterpret_cast<const void *>(&k_pass<MU, true, true>)
-                       : reinterpret_cast<const void *>(&k_pass<MU, true, false>);
-    return measure ? reinterpret_cast<const void *>(&k_pass<MU, false, true>)
-                   : reinterpret_cast<const void *>(&k_pass<MU, false, false>);
+    return off32 ? reinterpret_cast<const void *>(&k_pass<MU, true, MEASURE, IMH>)
+                 : reinterpret_cast<const void *>(&k_pass<MU, false, MEASURE, IMH>);
 }
 
-const void *pass_func(uint32_t mu, bool off32, bool measure)
+template <uint32_t MU>
+static const void *pass_func_mu(bool off32, bool measure, bool imh)
+{
+    if (imh) return measure ? pass_func_3<MU, true, true>(off32) : pass_func_3<MU, false, true>(off32);
+    return measure ? pass_func_3<MU, true, false>(off32) : pass_func_3<MU, false, false>(off32);
+}
+
+const void *pass_func(uint32_t mu, bool off32, bool measure, bool imh)
 {
     switch (mu) {
-    case 0: return pass_func_mu<0>(off32, false);  // no plaquette plane has nu < 0
-    case 1: return pass_func_mu<1>(off32, measure);
-    case 2: return pass_func_mu<2>(off32, measure);
-    default: return pass_func_mu<3>(off32, measure);
+    case 0: return pass_func_mu<0>(off32, false, imh);  // no plaquette plane has nu < 0
+    case 1: return pass_func_mu<1>(off32, measure, imh);
+    case 2: return pass_func_mu<2>(off32, measure, imh);
+    default: return pass_func_mu<3>(off32, measure, imh);
     }
 }
 
@@ -286,7 +292,8 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
     pl.lds = plan.lds_bytes;
     pl.order = plan.order;
     const bool measure = meas_out != nullptr && p == 0u && mu >= 1u;
-    pl.func = pass_func(mu, use_off32(g), measure);
+    pl.func = pass_func(mu, use_off32(g), measure, plan.imh != nullptr);
+    pl.imh = plan.imh;
     pl.grid = dim3(pass_blocks(g));
     pl.block = dim3(kBlock);
     pl.links = links;

@@ -3,7 +3,7 @@
 
 #include <vector>
 
-#include "su2_device.hpp"
+#include "su2_pass.hpp"
 
 namespace su2 {
 
@@ -14,6 +14,7 @@ namespace su2 {
 struct PassPlan {
     const uint32_t *order = nullptr;
     uint32_t lds_bytes = 0;
+    const ImhTable *imh = nullptr;  // device table: learned proposal; nullptr: heat-bath only
 };
 
 // Arguments of one k_pass launch, kept together so a graph node can point at them.
@@ -29,8 +30,9 @@ struct PassLaunch {
     unsigned long long *counters;
     double2 *meas_out;
     const uint32_t *order;
+    const ImhTable *imh;
     uint32_t lds;
-    void *args[9];
+    void *args[10];
     // point args at this object's own fields (call after every copy)
     void bind()
     {
@@ -43,6 +45,7 @@ struct PassLaunch {
         args[6] = &counters;
         args[7] = &meas_out;
         args[8] = &order;
+        args[9] = &imh;
     }
 };
 

@@ -11,6 +11,18 @@ namespace su2 {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 
+// Knot table of the learned proposal: rows g = 0..G-1 hold the 33 knots
+// y_0 = -1 < ... < y_32 = +1 of the piecewise-linear inverse CDF of x0 at
+// alpha_g = g * alpha_max / (G - 1).  Knots at other alpha <= alpha_max are the
+// linear mix of the two neighbouring rows (still monotone with the same ends).
+struct ImhTable {
+    const float *knots;          // [G][33]
+    uint32_t G;
+    float alpha_max;
+    float inv_step;              // (G - 1) / alpha_max
+    unsigned long long *stats;   // per wave: (proposals, accepts)
+};
+
 // ---------------------------------------------------------------------------
 // The three directions nu != mu, as compile-time constants.
 template <uint32_t MU, int I>
@@ -101,11 +113,12 @@ __device__ __forceinline__ double2 block_sum2(double a, double b)
 // exactly once (planes (nu, MU), nu < MU), so the plaquette of the sweep's
 // result comes out of the sweep itself.  meas_out receives one FP64 partial
 // per tile.
-template <uint32_t MU, bool OFF32, bool MEASURE>
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH = false>
 __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, Key key,
                                           float beta, uint32_t p, uint32_t s, uint32_t tile,
                                           unsigned long long *__restrict__ counters,
-                                          double2 *__restrict__ meas_out)
+                                          double2 *__restrict__ meas_out,
+                                          const ImhTable *__restrict__ imh = nullptr)
 {
     constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
     const uint32_t h = tile * kBlock + threadIdx.x;
@@ -122,7 +135,11 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
     const float k = sqrtf(qdot(w, w));
     const float alpha = beta * k;
     const bool haar_branch = valid && alpha == 0.0f;
-    bool done = !valid || haar_branch;
+    // learned proposal: one independence-Metropolis step for alpha in the
+    // table's range; the plain heat-bath stays the fallback outside it
+    bool imh_lane = false;
+    if constexpr (IMH) imh_lane = valid && !haar_branch && alpha <= imh->alpha_max;
+    bool done = !valid || haar_branch || imh_lane;
     float lam2 = 0.0f;
     unsigned long long attempts = 0;
     for (uint32_t t = 0; t < 8u; ++t) {
@@ -142,7 +159,63 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
     const unsigned long long failures = __popcll(__ballot(failed));
     float4 *Lout = L + arr(g, MU, p);
     float4 un = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (valid && !failed) {
+    bool rejected = false;
+    if constexpr (IMH) {
+        if (imh_lane) {
+            const float tpos = alpha * imh->inv_step;
+            const uint32_t g0 = min((uint32_t)tpos, imh->G - 2u);
+            const float f = tpos - (float)g0;
+            const float *r0 = imh->knots + 33u * g0;
+            const float *r1 = r0 + 33;
+            auto knot = [&](uint32_t j) { return r0[j] + f * (r1[j] - r0[j]); };
+            const uint4 r = draw(key, lex, MU, kPurposeImh, s, 0u);
+            const float u0 = unit24(r.x);
+            const uint32_t jp = min((uint32_t)(32.0f * u0), 31u);
+            const float ya = knot(jp), yb = knot(jp + 1u);
+            const float xp = ya + (32.0f * u0 - (float)jp) * (yb - ya);
+            const float4 uold = ld4<OFF32>(Lout, h);
+            const float ik = 1.0f / k;
+            const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
+            const float xc = fminf(1.0f, fmaxf(-1.0f, qdot(uold, V)));
+            uint32_t lo = 0u, hi = 32u;  // y_lo <= xc < y_hi
+            while (hi - lo > 1u) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (xc >= knot(mid)) lo = mid; else hi = mid;
+            }
+            const float wc = knot(lo + 1u) - knot(lo);
+            const float num = 1.0f - xp * xp, den = 1.0f - xc * xc;
+            bool acc;
+            if (num <= 0.0f) {
+                acc = false;  // target density vanishes at the proposal
+            } else if (den <= 0.0f) {
+                acc = true;   // ... or at the current value
+            } else {
+                // log of [pi(x') / q(x')] / [pi(x) / q(x)], q = (1/32) / width
+                const float lr = 0.5f * logf(num / den) + alpha * (xp - xc) + logf((yb - ya) / wc);
+                acc = logf(unit24(r.y)) <= lr;
+            }
+            if (acc) {
+                const float cz = 2.0f * unit24(r.z) - 1.0f;
+                float sphi, cphi;
+                sincospif(2.0f * unit24(r.w), &sphi, &cphi);
+                const float sn = sqrtf(1.0f - cz * cz), am = sqrtf(num);
+                const float4 X = make_float4(xp, am * sn * cphi, am * sn * sphi, am * cz);
+                un = unitize(qmul(X, V));
+                st4_stream<OFF32>(Lout, h, un);
+            } else {
+                un = uold;
+                rejected = true;
+            }
+        }
+        const unsigned long long nprop = __popcll(__ballot(imh_lane));
+        const unsigned long long nacc = __popcll(__ballot(imh_lane && !rejected));
+        if ((threadIdx.x & (kWave - 1)) == 0) {
+            const uint32_t wave = h / kWave;
+            imh->stats[2 * wave] += nprop;
+            imh->stats[2 * wave + 1] += nacc;
+        }
+    }
+    if (valid && !failed && !imh_lane) {
         if (haar_branch) {
             un = unitize(haar(draw(key, lex, MU, kPurposeUpdate, s, kSlotHaar)));
         } else {

@@ -25,6 +25,9 @@ EXPORTS = (
     "su2_finalize", "su2_batch_init", "su2_batch_sweep", "su2_batch_set_mode", "su2_batch_tune",
     "su2_batch_set_spin_limit", "su2_batch_plaquette", "su2_batch_links", "su2_batch_counters",
     "su2_batch_sweep_index", "su2_batch_last_error", "su2_batch_finalize",
+    "su2_cdf_knots", "su2_mlp_set_params", "su2_mlp_get_params", "su2_mlp_forward",
+    "su2_mlp_loss_grad", "su2_mlp_train", "su2_mlp_tabulate", "su2_mlp_table",
+    "su2_mlp_last_error", "su2_set_proposal", "su2_imh_counters",
 )
 
 
@@ -89,6 +92,18 @@ def load():
         "su2_batch_sweep_index": ([u64p], ctypes.c_int),
         "su2_batch_last_error": ([], ctypes.c_char_p),
         "su2_batch_finalize": ([], None),
+        "su2_cdf_knots": ([dp, ctypes.c_int32, dp], ctypes.c_int),
+        "su2_mlp_set_params": ([fp, ctypes.c_size_t], ctypes.c_int),
+        "su2_mlp_get_params": ([fp, ctypes.POINTER(ctypes.c_uint16), ctypes.c_size_t], ctypes.c_int),
+        "su2_mlp_forward": ([fp, ctypes.c_int32, fp], ctypes.c_int),
+        "su2_mlp_loss_grad": ([fp, fp, ctypes.c_int32, fp, fp], ctypes.c_int),
+        "su2_mlp_train": ([dp, ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_float, fp],
+                          ctypes.c_int),
+        "su2_mlp_tabulate": ([ctypes.c_int32], ctypes.c_int),
+        "su2_mlp_table": ([fp, ctypes.c_size_t], ctypes.c_int),
+        "su2_mlp_last_error": ([], ctypes.c_char_p),
+        "su2_set_proposal": ([ctypes.c_int32], ctypes.c_int),
+        "su2_imh_counters": ([u64p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -330,3 +345,79 @@ def su2_batch_sweep_index():
 def su2_batch_finalize():
     load().su2_batch_finalize()
     _batch.clear()
+
+
+# ---- learned proposal ---------------------------------------------------------
+NPARAM = 6433
+
+
+def _mcheck(rc):
+    if rc != SU2_OK:
+        raise Su2Error(rc, _lib.su2_mlp_last_error().decode())
+    return rc
+
+
+def su2_cdf_knots(alphas):
+    a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64))
+    out = np.zeros((len(a), 33))
+    _mcheck(load().su2_cdf_knots(_ptr(a, ctypes.c_double), len(a), _ptr(out, ctypes.c_double)))
+    return out
+
+
+def su2_mlp_set_params(params):
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32))
+    _mcheck(load().su2_mlp_set_params(_ptr(p, ctypes.c_float), p.size))
+
+
+def su2_mlp_get_params():
+    m = np.zeros(NPARAM, dtype=np.float32)
+    b = np.zeros(NPARAM, dtype=np.uint16)
+    _mcheck(load().su2_mlp_get_params(_ptr(m, ctypes.c_float), _ptr(b, ctypes.c_uint16), NPARAM))
+    return m, b
+
+
+def su2_mlp_forward(alphas):
+    a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float32))
+    out = np.zeros((len(a), 33), dtype=np.float32)
+    _mcheck(load().su2_mlp_forward(_ptr(a, ctypes.c_float), len(a), _ptr(out, ctypes.c_float)))
+    return out
+
+
+def su2_mlp_loss_grad(alphas, target_logw):
+    a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float32))
+    t = np.ascontiguousarray(np.asarray(target_logw, dtype=np.float32))
+    loss = ctypes.c_float(np.nan)
+    g = np.zeros(NPARAM, dtype=np.float32)
+    _mcheck(load().su2_mlp_loss_grad(_ptr(a, ctypes.c_float), _ptr(t, ctypes.c_float), len(a),
+                                     ctypes.byref(loss), _ptr(g, ctypes.c_float)))
+    return loss.value, g
+
+
+def su2_mlp_train(alphas, steps, lr0=3e-3, lr_min=1e-5):
+    a = np.ascontiguousarray(np.asarray(alphas, dtype=np.float64))
+    hist = np.zeros(max(int(steps), 1), dtype=np.float32)
+    _mcheck(load().su2_mlp_train(_ptr(a, ctypes.c_double), len(a), int(steps), float(lr0),
+                                 float(lr_min), _ptr(hist, ctypes.c_float)))
+    return hist[:int(steps)]
+
+
+def su2_mlp_tabulate(points=4096):
+    _mcheck(load().su2_mlp_tabulate(int(points)))
+    _keep["table_points"] = int(points)
+
+
+def su2_mlp_table():
+    G = _keep["table_points"]
+    out = np.zeros((G, 33), dtype=np.float32)
+    _mcheck(load().su2_mlp_table(_ptr(out, ctypes.c_float), out.size))
+    return out
+
+
+def su2_set_proposal(kind):
+    _check(load().su2_set_proposal(int(kind)))
+
+
+def su2_imh_counters():
+    out = np.zeros(2, dtype=np.uint64)
+    _check(load().su2_imh_counters(_ptr(out, ctypes.c_uint64)))
+    return int(out[0]), int(out[1])

@@ -1,0 +1,174 @@
+"""The learned proposal on the GPU against the oracle: CDF targets, network
+forward and gradient at identical BF16 weights (seeded inputs, never weights
+trained on the GPU), the independence-Metropolis pass, and what training buys.
+
+Tolerances: knots from the FP64 integrators <= 1e-10; network outputs (FP32
+accumulation vs FP64) <= 2e-5; gradient <= 2e-3 of its largest component;
+IMH links <= 1e-5 except flipped accept decisions at links whose oracle
+margin |log u - log r| is below 5e-4 (the log ratio carries alpha * dx0 with
+dx0 ~ 1e-6 between FP32 and FP64 knot tables)."""
+import numpy as np
+import pytest
+
+import oracle
+import su2_inputs
+from oracle import cdf, mlp
+from parity import UNIT_TOL, parity_of, unitarity_error
+
+pytestmark = pytest.mark.gpu
+IMH_FLIP_MARGIN = 5e-4
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_0903_3053_amd import su2
+    su2.load()
+    yield su2
+    su2.su2_finalize()
+
+
+@pytest.fixture(scope="module")
+def trained(lib):
+    """Train on the device from the seeded initial weights; returns the loss history."""
+    lib.su2_mlp_set_params(su2_inputs.mlp_init(1))
+    hist = lib.su2_mlp_train(su2_inputs.alpha_grid(4096), 3000, 3e-3, 1e-5)
+    params, _ = lib.su2_mlp_get_params()
+    return hist, params
+
+
+def _use(lib, params):
+    lib.su2_mlp_set_params(params)
+    lib.su2_mlp_tabulate(4096)
+
+
+def test_cdf_knots_parity(lib):
+    alphas = np.concatenate([[0.0, 1e-3, 0.3, 2.3, 8.0, 13.8, 40.0], su2_inputs.random_alphas(9, 2)])
+    got = lib.su2_cdf_knots(alphas)
+    ref = np.array([cdf.knots(a) for a in alphas])
+    assert np.max(np.abs(got - ref)) <= 1e-10
+    assert np.all(np.diff(got, axis=1) > 0)
+
+
+def test_forward_and_bf16_parity(lib):
+    p = su2_inputs.mlp_init(7) + np.float32(0.05) * np.random.default_rng(3).standard_normal(mlp.NPARAM).astype(np.float32)
+    lib.su2_mlp_set_params(p)
+    master, b16 = lib.su2_mlp_get_params()
+    np.testing.assert_array_equal(master, p)
+    ref16 = mlp.bf16_round(p).astype(np.float32).view(np.uint32) >> 16
+    np.testing.assert_array_equal(b16.astype(np.uint32), ref16)
+    alphas = np.concatenate([su2_inputs.alpha_grid(33), su2_inputs.random_alphas(31, 4)])
+    got = lib.su2_mlp_forward(alphas)
+    ref, _, _ = mlp.forward(mlp.bf16_round(p), alphas.astype(np.float32).astype(np.float64))
+    assert np.max(np.abs(got - ref)) <= 2e-5
+
+
+def test_gradient_parity(lib):
+    p = su2_inputs.mlp_init(11)
+    lib.su2_mlp_set_params(p)
+    alphas = su2_inputs.random_alphas(512, 5).astype(np.float32)
+    target = cdf.log_widths(np.array([cdf.knots(a) for a in alphas[:64]]))
+    target = np.tile(target, (8, 1)).astype(np.float32)
+    loss, grad = lib.su2_mlp_loss_grad(alphas, target)
+    L, g = mlp.loss_and_grad(mlp.bf16_round(p), alphas.astype(np.float64), target.astype(np.float64))
+    print(f"loss gpu {loss:.7g} oracle {L:.7g}; max |dgrad| / max |grad| = "
+          f"{np.max(np.abs(grad - g)) / np.max(np.abs(g)):.2e}")
+    assert abs(loss - L) <= 1e-5 * abs(L)
+    assert np.max(np.abs(grad - g)) <= 2e-3 * np.max(np.abs(g))
+
+
+def test_training_fits_the_integrated_cdfs(lib, trained):
+    """Loss falls during training; on held-out alphas the trained network's
+    knots are far closer to the integrated CDF's than the untrained ones."""
+    hist, params = trained
+    _use(lib, params)
+    assert hist[-1] < 0.05 * hist[0]
+    held = su2_inputs.random_alphas(48, 99)
+    exact = np.array([cdf.knots(a) for a in held])
+    err_trained = np.max(np.abs(lib.su2_mlp_forward(held) - exact))
+    lib.su2_mlp_set_params(su2_inputs.mlp_init(1))
+    err_init = np.max(np.abs(lib.su2_mlp_forward(held) - exact))
+    print(f"training loss {hist[0]:.3e} -> {hist[-1]:.3e}; held-out max knot error: "
+          f"untrained {err_init:.3e}, trained {err_trained:.3e}")
+    # BF16 weights (8-bit mantissas) bound the fit: ~3 % rms in log width
+    assert err_trained < 0.15 and err_trained < 0.1 * err_init
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 10, 4), (12, 12, 12, 12)])
+def test_imh_pass_parity(lib, dims):
+    """Both sides build their own knot table from the same seeded BF16 weights
+    and run one learned-proposal pass from the same links."""
+    p = su2_inputs.mlp_init(5)
+    lib.su2_mlp_set_params(p)
+    lib.su2_mlp_tabulate(4096)
+    table_o, _, _ = mlp.forward(mlp.bf16_round(p), su2_inputs.alpha_grid(4096))
+    assert np.max(np.abs(lib.su2_mlp_table() - table_o)) <= 2e-5
+    U0 = su2_inputs.near_identity_links(dims, 21, 0.35)
+    flips = n = 0
+    for parity, mu in ((1, 0), (0, 3), (1, 2)):
+        lib.su2_init(dims, 2.3, 9, lib.COLD)
+        lib.su2_set_proposal(1)
+        lib.su2_set_links(U0, 4)
+        lib.su2_pass(parity, mu)
+        gpu = lib.su2_links()
+        prop, acc = lib.su2_imh_counters()
+        U = U0.astype(np.float64)
+        res, margin, po, ao = oracle.imh_pass(dims, U, 2.3, 9, 4, parity, mu, table_o)
+        bad = np.max(np.abs(gpu[:, mu] - U[:, mu]), axis=1) > 1e-5
+        assert not np.any(bad & ~(margin < IMH_FLIP_MARGIN)), "unexplained IMH mismatch"
+        flips += int(bad.sum())
+        n += int(np.prod(dims)) // 2
+        other = np.ones((U.shape[0], 4), dtype=bool)
+        other[parity_of(dims) == parity, mu] = False
+        assert np.array_equal(gpu[other], U0[other])
+        assert unitarity_error(gpu) <= UNIT_TOL
+        if not np.any(bad):
+            assert (prop, acc) == (po, ao)
+    print(f"IMH pass parity {dims}: {n} updates, {flips} flipped decisions")
+    assert flips <= max(2, n * 1e-3)
+
+
+def _binned(x, nbins=10):
+    x = np.asarray(x)
+    b = len(x) // nbins
+    m = x[: b * nbins].reshape(nbins, b).mean(axis=1)
+    return m.mean(), m.std(ddof=1) / np.sqrt(nbins)
+
+
+def test_learned_chain_matches_heat_bath(lib, trained):
+    """Same lattice, same start: the plaquette of the learned-proposal chain
+    agrees with the heat-bath chain within 3 sigma, and the trained proposal is
+    accepted far more often than an untrained or a uniform one."""
+    dims, beta = (16, 16, 16, 16), 2.3
+    _use(lib, trained[1])
+    lib.su2_init(dims, beta, 3, lib.HOT)
+    lib.su2_sweep(100)
+    kp = lib.su2_sweep_measure(400, 1)[:, 0]
+    lib.su2_init(dims, beta, 3, lib.HOT)
+    lib.su2_set_proposal(1)
+    lib.su2_sweep(100)
+    lib.su2_imh_counters()
+    im = lib.su2_sweep_measure(400, 1)[:, 0]
+    prop, acc = lib.su2_imh_counters()
+    m1, s1 = _binned(kp)
+    m2, s2 = _binned(im)
+    z = (m2 - m1) / np.hypot(s1, s2)
+    rate_trained = acc / prop
+    print(f"16^4 beta 2.3: <P> heat-bath {m1:.6f}+-{s1:.6f}, learned {m2:.6f}+-{s2:.6f}, z = {z:+.2f}; "
+          f"acceptance {rate_trained:.4f}")
+    assert abs(z) < 3.0
+    assert rate_trained > 0.85
+    rates = {}
+    for name, params in (("untrained", su2_inputs.mlp_init(1)),
+                         ("uniform", np.zeros(mlp.NPARAM, dtype=np.float32))):
+        _use(lib, params)
+        lib.su2_init(dims, beta, 3, lib.HOT)
+        lib.su2_sweep(100)
+        lib.su2_set_proposal(1)
+        lib.su2_sweep(20)
+        prop, acc = lib.su2_imh_counters()
+        rates[name] = acc / prop
+    print(f"acceptance: trained {rate_trained:.4f}, untrained {rates['untrained']:.4f}, "
+          f"uniform {rates['uniform']:.4f}")
+    assert rate_trained > rates["untrained"] + 0.1 and rate_trained > rates["uniform"] + 0.1

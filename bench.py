@@ -117,6 +117,65 @@ def batched_replicas(su2, sweeps=500, compare_sweeps=50):
             "plaquette_range": [float(P[:, 0].min()), float(P[:, 0].max())]}
 
 
+TABLE_ROWS = 31
+
+
+def learned_proposal(su2, sweeps=1000, train_steps=3000):
+    """The learned-proposal workload: the network trained on the device on the
+    integrated CDFs of 4096 alphas, then 32^4 beta = 2.3 from the same hot start
+    for `sweeps` sweeps with the heat-bath and with the learned independence-
+    Metropolis step; plaquette measured every sweep, averages after a 20 %
+    thermalisation cut with binned errors."""
+    import numpy as np
+    import torch
+    import su2_inputs
+    dims, beta, seed = (32, 32, 32, 32), 2.3, 1
+    V = int(np.prod(dims))
+    su2.su2_mlp_set_params(su2_inputs.mlp_init(1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = su2.su2_mlp_train(su2_inputs.alpha_grid(4096), train_steps, 3e-3, 1e-5)
+    # the sweep reads a knot table of TABLE_ROWS alphas on [0, 40] (linear in
+    # alpha between rows); 31 rows fit the pass kernel's LDS copy
+    su2.su2_mlp_tabulate(TABLE_ROWS)
+    t_train = time.perf_counter() - t0
+
+    def binned(x, nb=20):
+        b = len(x) // nb
+        m = np.asarray(x[: b * nb]).reshape(nb, b).mean(axis=1)
+        return float(m.mean()), float(m.std(ddof=1) / np.sqrt(nb))
+
+    out = {}
+    for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
+        su2.su2_init(dims, beta, seed, 1)
+        su2.su2_set_proposal(kind)
+        su2.su2_sweep(5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su2.su2_sweep(200)
+        torch.cuda.synchronize()
+        rate = 4 * V * 200 / (time.perf_counter() - t0)
+        su2.su2_init(dims, beta, seed, 1)
+        su2.su2_set_proposal(kind)
+        if kind:
+            su2.su2_imh_counters()
+        h = su2.su2_sweep_measure(sweeps, 1)[:, 0]
+        m, e = binned(h[sweeps // 5:])
+        rec = {"link_updates_per_s": rate, "plaquette": m, "plaquette_err": e}
+        if kind:
+            prop, acc = su2.su2_imh_counters()
+            rec["acceptance"] = acc / max(prop, 1)
+        out[name] = rec
+    kp, lp = out["kennedy_pendleton"], out["learned_imh"]
+    su2.su2_finalize()
+    return {"workload": f"32^4 beta 2.3 hot seed 1, {sweeps} sweeps, heat-bath vs learned proposal",
+            "training": {"steps": train_steps, "alphas": 4096, "seconds": t_train, "table_rows": TABLE_ROWS,
+                         "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
+            **out,
+            "z_plaquette": (lp["plaquette"] - kp["plaquette"]) / float(np.hypot(kp["plaquette_err"], lp["plaquette_err"])),
+            "speed_ratio": lp["link_updates_per_s"] / kp["link_updates_per_s"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -224,6 +283,7 @@ def main():
     su2.su2_finalize()
     if not args.no_extras:
         rec["batched_replicas"] = batched_replicas(su2)
+        rec["learned_proposal"] = learned_proposal(su2)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     su2.su2_finalize()

@@ -49,7 +49,6 @@ struct Context {
     int32_t order_kind = 0;
     int32_t proposal = 0;               // 0 heat-bath, 1 learned independence-Metropolis
     float *d_table = nullptr;           // this lattice's copy of the knot table
-    ImhTable *d_imh = nullptr;          // device descriptor passed to the pass kernels
     unsigned long long *d_imh_stats = nullptr;  // per wave: (proposals, accepts)
 };
 
@@ -92,7 +91,6 @@ void release_all()
     if (ctx.d_scratch) hipFree(ctx.d_scratch);
     if (ctx.d_order) hipFree(ctx.d_order);
     if (ctx.d_table) hipFree(ctx.d_table);
-    if (ctx.d_imh) hipFree(ctx.d_imh);
     if (ctx.d_imh_stats) hipFree(ctx.d_imh_stats);
     if (ctx.d_out) hipFree(ctx.d_out);
     hipStream_t keep = ctx.stream;
@@ -550,11 +548,15 @@ int su2_tune(int32_t reps, int32_t out[2])
     if (reps < 1) return fail(SU2_EINVAL, "reps must be >= 1");
     const size_t link_bytes = (size_t)ctx.V * 4 * sizeof(float4);
     const size_t ctr_bytes = (size_t)ctx.n_waves * 2 * sizeof(unsigned long long);
+    const size_t part_bytes = (size_t)3 * pass_blocks(ctx.g) * sizeof(double2);
     float4 *tl = nullptr;
     unsigned long long *tc = nullptr;
-    if (hipMalloc(&tl, link_bytes) != hipSuccess || hipMalloc(&tc, ctr_bytes) != hipSuccess) {
+    double2 *tp = nullptr;
+    if (hipMalloc(&tl, link_bytes) != hipSuccess || hipMalloc(&tc, ctr_bytes) != hipSuccess ||
+        hipMalloc(&tp, part_bytes) != hipSuccess) {
         hipGetLastError();
         if (tl) hipFree(tl);
+        if (tc) hipFree(tc);
         return fail(SU2_ENOMEM, "cannot allocate the tuning copy of the links");
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -562,26 +564,38 @@ int su2_tune(int32_t reps, int32_t out[2])
     if (e == hipSuccess) e = hipEventCreate(&e1);
     if (e == hipSuccess) e = hipMemcpyAsync(tl, ctx.links, link_bytes, hipMemcpyDeviceToDevice, ctx.stream);
     if (e == hipSuccess) e = hipMemsetAsync(tc, 0, ctr_bytes, ctx.stream);
+    // candidates: tile order x LDS reservation.  Each is timed on `reps` full
+    // measured sweeps (as su2_sweep_measured runs them) of a copy of the links,
+    // in three rounds over all candidates; the median of its rounds ranks it,
+    // so slow drifts of the clock or of the cache state do not pick the plan.
     const int32_t kinds[] = { 0, 4, 8, 16 };
     const uint32_t ldss[] = { 0u, 16384u, 24576u, 32768u, 40960u };
-    float best = 1e30f;
-    int32_t best_kind = 0;
-    uint32_t best_lds = 0;
+    constexpr int kRounds = 3;
+    std::vector<int32_t> cand_kind;
+    std::vector<uint32_t> cand_lds;
     for (int32_t kind : kinds) {
-        if (e != hipSuccess) break;
         std::vector<uint32_t> order;
         if (!make_order(ctx.g, kind, order)) continue;
-        rc = set_plan(kind, 0);
-        if (rc) break;
         for (uint32_t lds : ldss) {
-            ctx.plan.lds_bytes = lds;
+            cand_kind.push_back(kind);
+            cand_lds.push_back(lds);
+        }
+    }
+    std::vector<float> ms_all(cand_kind.size() * kRounds, 1e30f);
+    for (int round = 0; round < kRounds && e == hipSuccess && !rc; ++round) {
+        for (size_t c = 0; c < cand_kind.size() && e == hipSuccess; ++c) {
+            if (c == 0 || cand_kind[c] != cand_kind[c - 1]) {
+                rc = set_plan(cand_kind[c], 0);
+                if (rc) break;
+            }
+            ctx.plan.lds_bytes = cand_lds[c];
             for (int warm = 0; warm < 2 && e == hipSuccess; ++warm) {
                 if (warm == 1) e = hipEventRecord(e0, ctx.stream);
                 for (int32_t r = 0; r < (warm ? reps : 1) && e == hipSuccess; ++r)
                     for (int p = 1; p >= 0 && e == hipSuccess; --p)
                         for (uint32_t mu = 0; mu < 4 && e == hipSuccess; ++mu) {
                             PassLaunch pl = pass_launch(tl, ctx.g, ctx.key, (float)ctx.beta,
-                                                        (uint32_t)p, mu, ctx.d_sweep, tc, nullptr,
+                                                        (uint32_t)p, mu, ctx.d_sweep, tc, tp,
                                                         ctx.plan);
                             e = launch(pl, ctx.stream);
                         }
@@ -590,11 +604,7 @@ int su2_tune(int32_t reps, int32_t out[2])
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-            if (e == hipSuccess && ms < best) {
-                best = ms;
-                best_kind = kind;
-                best_lds = lds;
-            }
+            if (e == hipSuccess) ms_all[c * kRounds + round] = ms;
         }
     }
     hipStreamSynchronize(ctx.stream);
@@ -602,8 +612,21 @@ int su2_tune(int32_t reps, int32_t out[2])
     if (e1) hipEventDestroy(e1);
     hipFree(tl);
     hipFree(tc);
+    hipFree(tp);
     if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_tune: %s", hipGetErrorString(e));
     if (rc) return rc;
+    float best = 1e30f;
+    int32_t best_kind = 0;
+    uint32_t best_lds = 0;
+    for (size_t c = 0; c < cand_kind.size(); ++c) {
+        float *m = &ms_all[c * kRounds];
+        std::sort(m, m + kRounds);
+        if (m[kRounds / 2] < best) {
+            best = m[kRounds / 2];
+            best_kind = cand_kind[c];
+            best_lds = cand_lds[c];
+        }
+    }
     rc = set_plan(best_kind, best_lds);
     if (rc) return rc;
     if (out) {
@@ -621,7 +644,9 @@ int su2_set_proposal(int32_t kind)
     HIP_TRY(hipStreamSynchronize(ctx.stream));
     if (kind == 0) {
         ctx.proposal = 0;
-        ctx.plan.imh = nullptr;
+        ctx.plan.learned = false;
+        ctx.plan.imh = ImhTable{};
+        ctx.plan.imh_lds_bytes = 0;
         release_graphs();
         return SU2_OK;
     }
@@ -632,22 +657,20 @@ int su2_set_proposal(int32_t kind)
         return fail(SU2_ESTATE, "no knot table: train or load the network and call su2_mlp_tabulate");
     if (ctx.d_table) hipFree(ctx.d_table);
     ctx.d_table = nullptr;
-    if (!ctx.d_imh && hipMalloc(&ctx.d_imh, sizeof(ImhTable)) != hipSuccess) {
-        hipGetLastError();
-        ctx.d_imh = nullptr;
-        return fail(SU2_ENOMEM, "cannot allocate the proposal descriptor");
-    }
     const size_t stats_bytes = (size_t)ctx.n_waves * 2 * sizeof(unsigned long long);
     if (!ctx.d_imh_stats && hipMalloc(&ctx.d_imh_stats, stats_bytes) != hipSuccess) {
         hipGetLastError();
         ctx.d_imh_stats = nullptr;
         return fail(SU2_ENOMEM, "cannot allocate proposal counters");
     }
-    if (hipMalloc(&ctx.d_table, (size_t)G * 33 * sizeof(float)) != hipSuccess) {
+    // padded so that the pass kernels' fixed-size LDS copy stays inside it
+    const uint32_t n_vec4 = std::max((G * 33u + 3u) / 4u, kImhLdsVec4);
+    if (hipMalloc(&ctx.d_table, (size_t)n_vec4 * 4 * sizeof(float)) != hipSuccess) {
         hipGetLastError();
         ctx.d_table = nullptr;
         return fail(SU2_ENOMEM, "cannot allocate the knot table");
     }
+    HIP_TRY(hipMemset(ctx.d_table, 0, (size_t)n_vec4 * 4 * sizeof(float)));
     HIP_TRY(hipMemcpy(ctx.d_table, knots, (size_t)G * 33 * sizeof(float), hipMemcpyDeviceToDevice));
     HIP_TRY(hipMemset(ctx.d_imh_stats, 0, stats_bytes));
     ImhTable t;
@@ -656,9 +679,10 @@ int su2_set_proposal(int32_t kind)
     t.alpha_max = amax;
     t.inv_step = (float)((double)(G - 1) / (double)amax);
     t.stats = ctx.d_imh_stats;
-    HIP_TRY(hipMemcpy(ctx.d_imh, &t, sizeof t, hipMemcpyHostToDevice));
     ctx.proposal = 1;
-    ctx.plan.imh = ctx.d_imh;
+    ctx.plan.learned = true;
+    ctx.plan.imh = t;
+    ctx.plan.imh_lds_bytes = kImhLdsBytes;
     release_graphs();
     return SU2_OK;
 }

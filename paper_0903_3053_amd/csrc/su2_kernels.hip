@@ -39,13 +39,11 @@ __global__ __launch_bounds__(kBlock) void k_init(float4 *__restrict__ links, Geo
 // A table can reorder tiles so that the workgroups the hardware sends to one
 // XCD share their neighbour data in L2.
 template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH>
-__global__ __launch_bounds__(kBlock) void k_pass(float4 *__restrict__ L, Geo g, Key key,
-                                                 float beta, uint32_t p,
-                                                 const uint32_t *__restrict__ sweep_ptr,
-                                                 unsigned long long *__restrict__ counters,
-                                                 double2 *__restrict__ meas_out,
-                                                 const uint32_t *__restrict__ order,
-                                                 const ImhTable *__restrict__ imh)
+__global__ __launch_bounds__(kBlock) void k_pass(
+    float4 *__restrict__ L, Geo g, Key key, float beta, uint32_t p,
+    const uint32_t *__restrict__ sweep_ptr, unsigned long long *__restrict__ counters,
+    double2 *__restrict__ meas_out, const uint32_t *__restrict__ order,
+    ImhTable imh)
 {
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     pass_tile<MU, OFF32, MEASURE, IMH>(L, g, key, beta, p, *sweep_ptr, tile, counters, meas_out,
@@ -289,10 +287,10 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
                        double2 *meas_out, const PassPlan &plan)
 {
     PassLaunch pl;
-    pl.lds = plan.lds_bytes;
+    pl.lds = plan.learned ? std::max(plan.lds_bytes, plan.imh_lds_bytes) : plan.lds_bytes;
     pl.order = plan.order;
     const bool measure = meas_out != nullptr && p == 0u && mu >= 1u;
-    pl.func = pass_func(mu, use_off32(g), measure, plan.imh != nullptr);
+    pl.func = pass_func(mu, use_off32(g), measure, plan.learned);
     pl.imh = plan.imh;
     pl.grid = dim3(pass_blocks(g));
     pl.block = dim3(kBlock);

@@ -14,7 +14,9 @@ namespace su2 {
 struct PassPlan {
     const uint32_t *order = nullptr;
     uint32_t lds_bytes = 0;
-    const ImhTable *imh = nullptr;  // device table: learned proposal; nullptr: heat-bath only
+    bool learned = false;           // learned proposal (imh) or heat-bath only
+    ImhTable imh;                   // the learned proposal's table, passed by value
+    uint32_t imh_lds_bytes = 0;     // LDS the learned-proposal pass stages its table in
 };
 
 // Arguments of one k_pass launch, kept together so a graph node can point at them.
@@ -30,7 +32,7 @@ struct PassLaunch {
     unsigned long long *counters;
     double2 *meas_out;
     const uint32_t *order;
-    const ImhTable *imh;
+    ImhTable imh;
     uint32_t lds;
     void *args[10];
     // point args at this object's own fields (call after every copy)

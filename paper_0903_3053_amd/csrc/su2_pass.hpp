@@ -15,13 +15,25 @@ constexpr int kWave = 64;
 // y_0 = -1 < ... < y_32 = +1 of the piecewise-linear inverse CDF of x0 at
 // alpha_g = g * alpha_max / (G - 1).  Knots at other alpha <= alpha_max are the
 // linear mix of the two neighbouring rows (still monotone with the same ends).
+// The descriptor travels by value as a kernel argument, so its fields are at
+// hand with the other arguments when a wave starts.
 struct ImhTable {
-    const float *knots;          // [G][33]
-    uint32_t G;
-    float alpha_max;
-    float inv_step;              // (G - 1) / alpha_max
-    unsigned long long *stats;   // per wave: (proposals, accepts)
+    const float *knots = nullptr;          // [G][33], zero-padded to >= kImhLdsVec4 float4
+    uint32_t G = 0;
+    float alpha_max = 0.0f;
+    float inv_step = 0.0f;                 // (G - 1) / alpha_max
+    unsigned long long *stats = nullptr;   // per wave: (proposals, accepts)
 };
+
+// Tables of at most kImhLdsRows rows are read from LDS, larger ones from global
+// memory.  Every workgroup copies the first kImhLdsVec4 float4 of the table
+// (31 rows of 33 knots fill 1023 of its 1024 floats) straight from global
+// memory into LDS: one 16-byte copy per lane, issued right behind the staple
+// gathers, with no branch and no register held (the table buffer is padded to
+// at least that size).  The launch provides kImhLdsBytes of dynamic LDS.
+constexpr uint32_t kImhLdsVec4 = kBlock;
+constexpr uint32_t kImhLdsRows = kImhLdsVec4 * 4u / 33u;  // 31
+constexpr uint32_t kImhLdsBytes = kImhLdsVec4 * 16u;
 
 // ---------------------------------------------------------------------------
 // The three directions nu != mu, as compile-time constants.
@@ -104,6 +116,57 @@ __device__ __forceinline__ double2 block_sum2(double a, double b)
     return r;
 }
 
+// Independence-Metropolis decision of the learned proposal at one link.  r0
+// points at row g0 of the knot table (row g0 + 1 follows at r0 + 33); the
+// proposal's knots are the rows' linear mix with weight f (y_0 = -1 and
+// y_32 = +1 in every row).  u0 picks the proposed x0 from the piecewise-linear
+// inverse CDF, u1 decides; xc is the current link's x0.  Returns whether the
+// proposal is accepted and sets xp (the proposed x0) and num = 1 - xp^2.  Ptr
+// is an LDS or a global pointer type, so each table location gets its own
+// load instructions.
+template <typename Ptr>
+__device__ __forceinline__ bool imh_decide(Ptr r0, float f, float u0, float u1, float alpha,
+                                           float xc, float &xp, float &num)
+{
+    auto knot = [&](uint32_t j) { return r0[j] + f * (r0[33u + j] - r0[j]); };
+    // segment [y_lo, y_lo+1) of the current value: lo counts the knots
+    // y_1..y_31 at or below xc (for non-decreasing knots, the largest lo with
+    // y_lo <= xc).  Two rounds of independent reads: knots 8, 16 and 24 pick
+    // the stretch of eight segments, then its seven inner knots are read
+    // together with the proposal's two.
+    const float q1 = knot(8u), q2 = knot(16u), q3 = knot(24u);
+    const uint32_t jp = min((uint32_t)(32.0f * u0), 31u);
+    const float ya = knot(jp), yb = knot(jp + 1u);
+    const uint32_t b = 8u * ((uint32_t)(xc >= q1) + (uint32_t)(xc >= q2) + (uint32_t)(xc >= q3));
+    float ylo = b == 0u ? -1.0f : b == 8u ? q1 : b == 16u ? q2 : q3;
+    float yhi = b == 0u ? q1 : b == 8u ? q2 : b == 16u ? q3 : 1.0f;
+    float v[7];
+#pragma unroll
+    for (uint32_t j = 0; j < 7u; ++j) v[j] = knot(b + 1u + j);
+#pragma unroll
+    for (uint32_t j = 0; j < 7u; ++j)
+        if (xc >= v[j]) ylo = v[j];
+#pragma unroll
+    for (int j = 6; j >= 0; --j)
+        if (xc < v[j]) yhi = v[j];
+    const float wc = yhi - ylo;
+    xp = ya + (32.0f * u0 - (float)jp) * (yb - ya);
+    num = 1.0f - xp * xp;
+    const float den = 1.0f - xc * xc;
+    if (num <= 0.0f) return false;  // target density vanishes at the proposal
+    if (den <= 0.0f) return true;   // ... or at the current value
+    // r = [pi(x') / q(x')] / [pi(x) / q(x)] with pi(x) = sqrt(1 - x^2) e^{alpha x}
+    // and q = (1/32) / width.  alpha <= 40 keeps the exponent within +-80, so
+    // the product cannot overflow to anything but +inf (accept) or underflow to
+    // anything but 0 (reject, as u1 >= 2^-24); hardware exp2, rcp and sqrt
+    // carry relative errors of order 1e-6, far inside the statistical slack of
+    // an accept decision.
+    const float e = __builtin_amdgcn_exp2f(alpha * (xp - xc) * 1.44269504f);
+    const float ratio = __builtin_amdgcn_sqrtf(num * __builtin_amdgcn_rcpf(den)) * (yb - ya) *
+                        __builtin_amdgcn_rcpf(wc) * e;
+    return u1 <= ratio;
+}
+
 // One tile (256 half-sites) of a heat-bath pass over the links U_MU(x),
 // parity(x) = p, at sweep index s.  All 18 gathers
 // are issued before any arithmetic (MU is a template parameter so the three
@@ -118,7 +181,7 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
                                           float beta, uint32_t p, uint32_t s, uint32_t tile,
                                           unsigned long long *__restrict__ counters,
                                           double2 *__restrict__ meas_out,
-                                          const ImhTable *__restrict__ imh = nullptr)
+                                          const ImhTable &imh = ImhTable{})
 {
     constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
     const uint32_t h = tile * kBlock + threadIdx.x;
@@ -127,9 +190,24 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
     const Site x = site_of(g, hh, p);
     const uint32_t lex = 2u * hh + (x.x[0] & 1u);  // L0 = 2*H0, so lex = 2h + (x0 mod 2)
     const uint32_t h_pm = h_plus<MU>(g, hh, x.x[MU]);
+    float4 *Lout = L + arr(g, MU, p);
+    // learned proposal: the old link and the knot table do not depend on the
+    // staple, so their loads go out right behind the gathers
+    [[maybe_unused]] float4 uold = make_float4(0.f, 0.f, 0.f, 0.f);
     const StapleLinks s0 = gather<MU, N0, OFF32>(L, g, p, hh, h_pm, x);
     const StapleLinks s1 = gather<MU, N1, OFF32>(L, g, p, hh, h_pm, x);
     const StapleLinks s2 = gather<MU, N2, OFF32>(L, g, p, hh, h_pm, x);
+    if constexpr (IMH) uold = ld4<OFF32>(Lout, hh);
+    [[maybe_unused]] bool staged = false;
+    if constexpr (IMH) {
+        extern __shared__ float4 imh_lds[];
+        staged = imh.G <= kImhLdsRows;
+        // lane l of wave v copies float4 64 v + l to LDS address 16 (64 v + l)
+        const uint32_t wv = threadIdx.x / kWave;
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(reinterpret_cast<const float4 *>(imh.knots) + threadIdx.x),
+            (__attribute__((address_space(3))) void *)(imh_lds + wv * kWave), 16u, 0, 0);
+    }
     const float4 w0 = staple_sum(s0), w1 = staple_sum(s1), w2 = staple_sum(s2);
     const float4 w = qadd(qadd(w0, w1), w2);
     const float k = sqrtf(qdot(w, w));
@@ -138,7 +216,7 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
     // learned proposal: one independence-Metropolis step for alpha in the
     // table's range; the plain heat-bath stays the fallback outside it
     bool imh_lane = false;
-    if constexpr (IMH) imh_lane = valid && !haar_branch && alpha <= imh->alpha_max;
+    if constexpr (IMH) imh_lane = valid && !haar_branch && alpha <= imh.alpha_max;
     bool done = !valid || haar_branch || imh_lane;
     float lam2 = 0.0f;
     unsigned long long attempts = 0;
@@ -157,51 +235,38 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
     }
     const bool failed = valid && !done;
     const unsigned long long failures = __popcll(__ballot(failed));
-    float4 *Lout = L + arr(g, MU, p);
     float4 un = make_float4(0.f, 0.f, 0.f, 0.f);
-    bool rejected = false;
+    // a new link X V with X = (x0n, amag * direction); the direction comes from
+    // two uniforms (cos theta = 2 u - 1, phi = 2 pi u') of the lane's draw
+    bool rotate = false;
+    float x0n = 0.0f, amag = 0.0f;
+    uint32_t rz = 0u, rphi = 0u;
     if constexpr (IMH) {
+        bool rejected = false;
+        __syncthreads();  // the staged table is complete
         if (imh_lane) {
-            const float tpos = alpha * imh->inv_step;
-            const uint32_t g0 = min((uint32_t)tpos, imh->G - 2u);
+            const float tpos = alpha * imh.inv_step;
+            const uint32_t g0 = min((uint32_t)tpos, imh.G - 2u);
             const float f = tpos - (float)g0;
-            const float *r0 = imh->knots + 33u * g0;
-            const float *r1 = r0 + 33;
-            auto knot = [&](uint32_t j) { return r0[j] + f * (r1[j] - r0[j]); };
             const uint4 r = draw(key, lex, MU, kPurposeImh, s, 0u);
-            const float u0 = unit24(r.x);
-            const uint32_t jp = min((uint32_t)(32.0f * u0), 31u);
-            const float ya = knot(jp), yb = knot(jp + 1u);
-            const float xp = ya + (32.0f * u0 - (float)jp) * (yb - ya);
-            const float4 uold = ld4<OFF32>(Lout, h);
             const float ik = 1.0f / k;
-            const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
-            const float xc = fminf(1.0f, fmaxf(-1.0f, qdot(uold, V)));
-            uint32_t lo = 0u, hi = 32u;  // y_lo <= xc < y_hi
-            while (hi - lo > 1u) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (xc >= knot(mid)) lo = mid; else hi = mid;
-            }
-            const float wc = knot(lo + 1u) - knot(lo);
-            const float num = 1.0f - xp * xp, den = 1.0f - xc * xc;
+            const float xc = fminf(1.0f, fmaxf(-1.0f, qdot(uold, w) * ik));
+            float xp, num;
             bool acc;
-            if (num <= 0.0f) {
-                acc = false;  // target density vanishes at the proposal
-            } else if (den <= 0.0f) {
-                acc = true;   // ... or at the current value
+            if (staged) {
+                extern __shared__ float4 imh_lds[];
+                acc = imh_decide((const __attribute__((address_space(3))) float *)imh_lds + 33u * g0, f,
+                                 unit24(r.x), unit24(r.y), alpha, xc, xp, num);
             } else {
-                // log of [pi(x') / q(x')] / [pi(x) / q(x)], q = (1/32) / width
-                const float lr = 0.5f * logf(num / den) + alpha * (xp - xc) + logf((yb - ya) / wc);
-                acc = logf(unit24(r.y)) <= lr;
+                acc = imh_decide((const __attribute__((address_space(1))) float *)imh.knots + 33u * g0, f,
+                                 unit24(r.x), unit24(r.y), alpha, xc, xp, num);
             }
             if (acc) {
-                const float cz = 2.0f * unit24(r.z) - 1.0f;
-                float sphi, cphi;
-                sincospif(2.0f * unit24(r.w), &sphi, &cphi);
-                const float sn = sqrtf(1.0f - cz * cz), am = sqrtf(num);
-                const float4 X = make_float4(xp, am * sn * cphi, am * sn * sphi, am * cz);
-                un = unitize(qmul(X, V));
-                st4_stream<OFF32>(Lout, h, un);
+                rotate = true;
+                x0n = xp;
+                amag = sqrtf(num);
+                rz = r.z;
+                rphi = r.w;
             } else {
                 un = uold;
                 rejected = true;
@@ -209,34 +274,42 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
         }
         const unsigned long long nprop = __popcll(__ballot(imh_lane));
         const unsigned long long nacc = __popcll(__ballot(imh_lane && !rejected));
-        if ((threadIdx.x & (kWave - 1)) == 0) {
+        if ((threadIdx.x & (kWave - 1)) == 0 && nprop != 0ull) {
             const uint32_t wave = h / kWave;
-            imh->stats[2 * wave] += nprop;
-            imh->stats[2 * wave + 1] += nacc;
+            atomicAdd(&imh.stats[2 * wave], nprop);
+            atomicAdd(&imh.stats[2 * wave + 1], nacc);
         }
     }
     if (valid && !failed && !imh_lane) {
         if (haar_branch) {
             un = unitize(haar(draw(key, lex, MU, kPurposeUpdate, s, kSlotHaar)));
+            st4_stream<OFF32>(Lout, h, un);
         } else {
             const uint4 r = draw(key, lex, MU, kPurposeUpdate, s, kSlotDirection);
-            const float cz = 2.0f * unit24(r.x) - 1.0f;
-            float sphi, cphi;
-            sincospif(2.0f * unit24(r.y), &sphi, &cphi);
-            const float sn = sqrtf(1.0f - cz * cz);
-            const float a0 = 1.0f - 2.0f * lam2;
-            const float am = 2.0f * sqrtf(lam2 * (1.0f - lam2));
-            const float4 X = make_float4(a0, am * sn * cphi, am * sn * sphi, am * cz);
-            const float ik = 1.0f / k;
-            const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
-            un = unitize(qmul(X, V));
+            rotate = true;
+            x0n = 1.0f - 2.0f * lam2;
+            amag = 2.0f * sqrtf(lam2 * (1.0f - lam2));
+            rz = r.x;
+            rphi = r.y;
         }
+    }
+    if (rotate) {
+        const float cz = 2.0f * unit24(rz) - 1.0f;
+        float sphi, cphi;
+        sincospif(2.0f * unit24(rphi), &sphi, &cphi);
+        const float sn = sqrtf(1.0f - cz * cz);
+        const float4 X = make_float4(x0n, amag * sn * cphi, amag * sn * sphi, amag * cz);
+        const float ik = 1.0f / k;
+        const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
+        un = unitize(qmul(X, V));
         st4_stream<OFF32>(Lout, h, un);
     }
-    if ((threadIdx.x & (kWave - 1)) == 0) {
+    // each wave owns its two counters; the adds return nothing, so the wave
+    // does not wait on a read-modify-write before it retires
+    if ((threadIdx.x & (kWave - 1)) == 0 && attempts != 0ull) {
         const uint32_t wave = h / kWave;
-        counters[2 * wave] += attempts;
-        counters[2 * wave + 1] += failures;
+        atomicAdd(&counters[2 * wave], attempts);
+        if (failures != 0ull) atomicAdd(&counters[2 * wave + 1], failures);
     }
     if constexpr (MEASURE) {
         if (failed) un = ld4<OFF32>(Lout, h);  // the link kept its value

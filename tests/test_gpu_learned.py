@@ -95,14 +95,17 @@ def test_training_fits_the_integrated_cdfs(lib, trained):
     assert err_trained < 0.15 and err_trained < 0.1 * err_init
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 10, 4), (12, 12, 12, 12)])
-def test_imh_pass_parity(lib, dims):
+@pytest.mark.parametrize("dims,points", [((8, 6, 10, 4), 4096), ((12, 12, 12, 12), 4096),
+                                         ((8, 6, 10, 4), 31), ((12, 12, 12, 12), 16),
+                                         ((12, 12, 12, 12), 32)])
+def test_imh_pass_parity(lib, dims, points):
     """Both sides build their own knot table from the same seeded BF16 weights
-    and run one learned-proposal pass from the same links."""
+    and run one learned-proposal pass from the same links (tables of up to
+    31 rows are read from the kernel's LDS copy, larger ones from global memory)."""
     p = su2_inputs.mlp_init(5)
     lib.su2_mlp_set_params(p)
-    lib.su2_mlp_tabulate(4096)
-    table_o, _, _ = mlp.forward(mlp.bf16_round(p), su2_inputs.alpha_grid(4096))
+    lib.su2_mlp_tabulate(points)
+    table_o, _, _ = mlp.forward(mlp.bf16_round(p), su2_inputs.alpha_grid(points))
     assert np.max(np.abs(lib.su2_mlp_table() - table_o)) <= 2e-5
     U0 = su2_inputs.near_identity_links(dims, 21, 0.35)
     flips = n = 0
@@ -125,7 +128,7 @@ def test_imh_pass_parity(lib, dims):
         assert unitarity_error(gpu) <= UNIT_TOL
         if not np.any(bad):
             assert (prop, acc) == (po, ao)
-    print(f"IMH pass parity {dims}: {n} updates, {flips} flipped decisions")
+    print(f"IMH pass parity {dims}, {points}-row table: {n} updates, {flips} flipped decisions")
     assert flips <= max(2, n * 1e-3)
 
 

@@ -147,21 +147,23 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
 
     out = {}
     for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
+        # each proposal runs with the launch plan tuned for it
         su2.su2_init(dims, beta, seed, 1)
         su2.su2_set_proposal(kind)
         su2.su2_sweep(5)
+        plan = su2.su2_tune(2)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         su2.su2_sweep(200)
         torch.cuda.synchronize()
         rate = 4 * V * 200 / (time.perf_counter() - t0)
         su2.su2_init(dims, beta, seed, 1)
+        su2.su2_set_plan(*plan)
         su2.su2_set_proposal(kind)
-        if kind:
-            su2.su2_imh_counters()
         h = su2.su2_sweep_measure(sweeps, 1)[:, 0]
         m, e = binned(h[sweeps // 5:])
-        rec = {"link_updates_per_s": rate, "plaquette": m, "plaquette_err": e}
+        rec = {"link_updates_per_s": rate, "plaquette": m, "plaquette_err": e,
+               "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}}
         if kind:
             prop, acc = su2.su2_imh_counters()
             rec["acceptance"] = acc / max(prop, 1)

@@ -143,9 +143,10 @@ int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
 
 /* Time each plan in {order 0, 4, 8, 16} x {LDS 0, 16, 24, 32, 40 KiB} on a
  * scratch copy of the links (reps measured sweeps each, in three rounds over
- * all plans; the lattice, sweep index and counters are untouched) and install
- * the plan with the smallest median; out (nullable) receives
- * {order_kind, lds_bytes}.  Synchronises. */
+ * all plans; the lattice, sweep index and all counters are untouched) and
+ * install the plan with the smallest median; out (nullable) receives
+ * {order_kind, lds_bytes}.  The plan is timed with the proposal installed at
+ * the time of the call.  Synchronises. */
 int su2_tune(int32_t reps, int32_t out[2]);
 
 /* ---- Learned proposal ---------------------------------------------------

@@ -582,6 +582,9 @@ int su2_tune(int32_t reps, int32_t out[2])
         }
     }
     std::vector<float> ms_all(cand_kind.size() * kRounds, 1e30f);
+    // the learned proposal's counters go to the scratch counters meanwhile
+    unsigned long long *imh_stats = ctx.plan.imh.stats;
+    if (ctx.plan.learned) ctx.plan.imh.stats = tc;
     for (int round = 0; round < kRounds && e == hipSuccess && !rc; ++round) {
         for (size_t c = 0; c < cand_kind.size() && e == hipSuccess; ++c) {
             if (c == 0 || cand_kind[c] != cand_kind[c - 1]) {
@@ -608,6 +611,7 @@ int su2_tune(int32_t reps, int32_t out[2])
         }
     }
     hipStreamSynchronize(ctx.stream);
+    ctx.plan.imh.stats = imh_stats;
     if (e0) hipEventDestroy(e0);
     if (e1) hipEventDestroy(e1);
     hipFree(tl);

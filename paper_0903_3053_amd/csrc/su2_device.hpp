@@ -54,12 +54,15 @@ __device__ __forceinline__ uint4 draw(Key k, uint32_t site, uint32_t mu, uint32_
 // ---------------------------------------------------------------------------
 // Quaternions U = u0 I + i sigma.u, Eq. (4), held in a float4 (x = u0).
 // ---------------------------------------------------------------------------
+// The quaternion arithmetic spells out every fused multiply-add, so the
+// rounding is the same in every kernel that inlines it (the compiler may not
+// fuse or split anything here).
 __device__ __forceinline__ float4 qmul(float4 a, float4 b)  // a b
 {
-    return make_float4(a.x * b.x - a.y * b.y - a.z * b.z - a.w * b.w,
-                       a.x * b.y + b.x * a.y - a.z * b.w + a.w * b.z,
-                       a.x * b.z + b.x * a.z - a.w * b.y + a.y * b.w,
-                       a.x * b.w + b.x * a.w - a.y * b.z + a.z * b.y);
+    return make_float4(__builtin_fmaf(a.x, b.x, -__builtin_fmaf(a.y, b.y, __builtin_fmaf(a.z, b.z, a.w * b.w))),
+                       __builtin_fmaf(a.x, b.y, __builtin_fmaf(b.x, a.y, __builtin_fmaf(-a.z, b.w, a.w * b.z))),
+                       __builtin_fmaf(a.x, b.z, __builtin_fmaf(b.x, a.z, __builtin_fmaf(-a.w, b.y, a.y * b.w))),
+                       __builtin_fmaf(a.x, b.w, __builtin_fmaf(b.x, a.w, __builtin_fmaf(-a.y, b.z, a.z * b.y))));
 }
 
 __device__ __forceinline__ float4 qdag(float4 a) { return make_float4(a.x, -a.y, -a.z, -a.w); }
@@ -71,13 +74,14 @@ __device__ __forceinline__ float4 qadd(float4 a, float4 b)
 
 __device__ __forceinline__ float qdot(float4 a, float4 b)  // (1/2) Re Tr(a b^dag)
 {
-    return a.x * b.x + a.y * b.y + a.z * b.z + a.w * b.w;
+    return __builtin_fmaf(a.x, b.x, __builtin_fmaf(a.y, b.y, __builtin_fmaf(a.z, b.z, a.w * b.w)));
 }
 
 // Reunitarisation, Eq. (7): divide by the norm, summed in FP64.
 __device__ __forceinline__ float4 unitize(float4 q)
 {
-    const double n2 = (double)q.x * q.x + (double)q.y * q.y + (double)q.z * q.z + (double)q.w * q.w;
+    const double x = q.x, y = q.y, z = q.z, w = q.w;
+    const double n2 = __builtin_fma(x, x, __builtin_fma(y, y, __builtin_fma(z, z, w * w)));
     const double inv = 1.0 / sqrt(n2);
     return make_float4((float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv),
                        (float)(q.w * inv));

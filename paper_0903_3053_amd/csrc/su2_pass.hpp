@@ -128,6 +128,7 @@ template <typename Ptr>
 __device__ __forceinline__ bool imh_decide(Ptr r0, float f, float u0, float u1, float alpha,
                                            float xc, float &xp, float &num)
 {
+#pragma clang fp contract(off)
     auto knot = [&](uint32_t j) { return r0[j] + f * (r0[33u + j] - r0[j]); };
     // segment [y_lo, y_lo+1) of the current value: lo counts the knots
     // y_1..y_31 at or below xc (for non-decreasing knots, the largest lo with
@@ -167,49 +168,92 @@ __device__ __forceinline__ bool imh_decide(Ptr r0, float f, float u0, float u1, 
     return u1 <= ratio;
 }
 
-// One tile (256 half-sites) of a heat-bath pass over the links U_MU(x),
-// parity(x) = p, at sweep index s.  All 18 gathers
-// are issued before any arithmetic (MU is a template parameter so the three
-// staple directions unroll).  With MEASURE (even passes MU >= 1 of a measured
-// sweep), each lane also adds dot(U_new, staple_nu) for nu < MU: over the
-// three even passes this counts every plaquette of the final configuration
-// exactly once (planes (nu, MU), nu < MU), so the plaquette of the sweep's
-// result comes out of the sweep itself.  meas_out receives one FP64 partial
-// per tile.
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH = false>
-__device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, Key key,
-                                          float beta, uint32_t p, uint32_t s, uint32_t tile,
-                                          unsigned long long *__restrict__ counters,
-                                          double2 *__restrict__ meas_out,
-                                          const ImhTable &imh = ImhTable{})
+// The links one tile's updates read before any arithmetic: the 18 staple
+// links of every lane and, for the learned proposal, the lane's old link; lex
+// is the lane's lexicographic site index (the Philox counter's first word).
+struct TileLoad {
+    StapleLinks s0, s1, s2;
+    float4 uold;
+    uint32_t lex;
+};
+
+template <uint32_t MU, bool OFF32, bool IMH>
+__device__ __forceinline__ TileLoad load_tile(const float4 *__restrict__ L, const Geo &g, uint32_t p,
+                                              uint32_t tile)
 {
     constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
     const uint32_t h = tile * kBlock + threadIdx.x;
-    const bool valid = h < g.half;
-    const uint32_t hh = valid ? h : 0u;
+    const uint32_t hh = h < g.half ? h : 0u;
     const Site x = site_of(g, hh, p);
-    const uint32_t lex = 2u * hh + (x.x[0] & 1u);  // L0 = 2*H0, so lex = 2h + (x0 mod 2)
     const uint32_t h_pm = h_plus<MU>(g, hh, x.x[MU]);
+    TileLoad t;
+    t.lex = 2u * hh + (x.x[0] & 1u);  // L0 = 2*H0, so lex = 2h + (x0 mod 2)
+    t.s0 = gather<MU, N0, OFF32>(L, g, p, hh, h_pm, x);
+    t.s1 = gather<MU, N1, OFF32>(L, g, p, hh, h_pm, x);
+    t.s2 = gather<MU, N2, OFF32>(L, g, p, hh, h_pm, x);
+    // the old link does not depend on the staple, so its load goes out with
+    // the gathers
+    t.uold = IMH ? ld4<OFF32>(L + arr(g, MU, p), hh) : make_float4(0.f, 0.f, 0.f, 0.f);
+    return t;
+}
+
+// Learned proposal: every workgroup copies the first kImhLdsVec4 float4 of the
+// knot table into LDS, one 16-byte global-to-LDS load per lane (lane l of
+// wave v lands at float4 64 v + l); update_tile waits for it at a barrier.
+__device__ __forceinline__ void stage_table(const ImhTable &imh)
+{
+    extern __shared__ float4 imh_lds[];
+    const uint32_t wv = threadIdx.x / kWave;
+    __builtin_amdgcn_global_load_lds(
+        (const __attribute__((address_space(1))) void *)(reinterpret_cast<const float4 *>(imh.knots) + threadIdx.x),
+        (__attribute__((address_space(3))) void *)(imh_lds + wv * kWave), 16u, 0, 0);
+}
+
+// What an update needs of its loads once the staples are formed: the three
+// plane staples (the plaquette measurement uses those with nu < MU), their sum
+// w (Eq. (6)), the old link (learned proposal) and lex.
+struct TileStaples {
+    float4 w0, w1, w2, w;
+    float4 uold;
+    uint32_t lex;
+};
+
+__device__ __forceinline__ TileStaples staples_of(const TileLoad &in)
+{
+    TileStaples t;
+    t.w0 = staple_sum(in.s0);
+    t.w1 = staple_sum(in.s1);
+    t.w2 = staple_sum(in.s2);
+    t.w = qadd(qadd(t.w0, t.w1), t.w2);
+    t.uold = in.uold;
+    t.lex = in.lex;
+    return t;
+}
+
+// The updates of one tile (256 half-sites) of a heat-bath pass over the links
+// U_MU(x), parity(x) = p, at sweep index s, from the staples in `in`.  With
+// MEASURE (even passes MU >= 1 of a measured sweep), each lane also adds
+// dot(U_new, staple_nu) for nu < MU: over the three even passes this counts
+// every plaquette of the final configuration exactly once (planes (nu, MU),
+// nu < MU), so the plaquette of the sweep's result comes out of the sweep
+// itself.  meas_out receives one FP64 partial per tile.
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH>
+__device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g, Key key,
+                                            float beta, uint32_t p, uint32_t s, uint32_t tile,
+                                            const TileStaples &in,
+                                            unsigned long long *__restrict__ counters,
+                                            double2 *__restrict__ meas_out, const ImhTable &imh)
+{
+    // every operation rounds as written, whatever kernel inlines this
+#pragma clang fp contract(off)
+    constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
+    const uint32_t h = tile * kBlock + threadIdx.x;
+    const bool valid = h < g.half;
+    const uint32_t lex = in.lex;
     float4 *Lout = L + arr(g, MU, p);
-    // learned proposal: the old link and the knot table do not depend on the
-    // staple, so their loads go out right behind the gathers
-    [[maybe_unused]] float4 uold = make_float4(0.f, 0.f, 0.f, 0.f);
-    const StapleLinks s0 = gather<MU, N0, OFF32>(L, g, p, hh, h_pm, x);
-    const StapleLinks s1 = gather<MU, N1, OFF32>(L, g, p, hh, h_pm, x);
-    const StapleLinks s2 = gather<MU, N2, OFF32>(L, g, p, hh, h_pm, x);
-    if constexpr (IMH) uold = ld4<OFF32>(Lout, hh);
-    [[maybe_unused]] bool staged = false;
-    if constexpr (IMH) {
-        extern __shared__ float4 imh_lds[];
-        staged = imh.G <= kImhLdsRows;
-        // lane l of wave v copies float4 64 v + l to LDS address 16 (64 v + l)
-        const uint32_t wv = threadIdx.x / kWave;
-        __builtin_amdgcn_global_load_lds(
-            (const __attribute__((address_space(1))) void *)(reinterpret_cast<const float4 *>(imh.knots) + threadIdx.x),
-            (__attribute__((address_space(3))) void *)(imh_lds + wv * kWave), 16u, 0, 0);
-    }
-    const float4 w0 = staple_sum(s0), w1 = staple_sum(s1), w2 = staple_sum(s2);
-    const float4 w = qadd(qadd(w0, w1), w2);
+    [[maybe_unused]] const float4 uold = in.uold;
+    const float4 w0 = in.w0, w1 = in.w1, w2 = in.w2;
+    const float4 w = in.w;
     const float k = sqrtf(qdot(w, w));
     const float alpha = beta * k;
     const bool haar_branch = valid && alpha == 0.0f;
@@ -243,6 +287,7 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
     uint32_t rz = 0u, rphi = 0u;
     if constexpr (IMH) {
         bool rejected = false;
+        const bool staged = imh.G <= kImhLdsRows;
         __syncthreads();  // the staged table is complete
         if (imh_lane) {
             const float tpos = alpha * imh.inv_step;
@@ -324,6 +369,22 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
         if (threadIdx.x == 0)
             meas_out[tile] = MU == 3u ? make_double2(0.0, r.x) : make_double2(r.x, 0.0);
     }
+}
+
+
+// One tile of a pass: its loads, then its updates (the single-tile kernels and
+// the batched-replica kernels).
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH = false>
+__device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, Key key,
+                                          float beta, uint32_t p, uint32_t s, uint32_t tile,
+                                          unsigned long long *__restrict__ counters,
+                                          double2 *__restrict__ meas_out,
+                                          const ImhTable &imh = ImhTable{})
+{
+    const TileLoad in = load_tile<MU, OFF32, IMH>(L, g, p, tile);
+    if constexpr (IMH) stage_table(imh);
+    update_tile<MU, OFF32, MEASURE, IMH>(L, g, key, beta, p, s, tile, staples_of(in), counters,
+                                         meas_out, imh);
 }
 
 }  // namespace su2

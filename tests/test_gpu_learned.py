@@ -132,6 +132,31 @@ def test_imh_pass_parity(lib, dims, points):
     assert flips <= max(2, n * 1e-3)
 
 
+def test_learned_sweeps_identical_across_plans(lib):
+    """The learned pass gives bit-identical links and proposal counts for every
+    launch plan, with the table read from LDS (31 rows) or global memory (64)."""
+    lib.su2_mlp_set_params(su2_inputs.mlp_init(5))
+    dims = (64, 64, 8, 8)
+    for points in (31, 64):
+        lib.su2_mlp_tabulate(points)
+        ref = None
+        for plan in [(0, 0), (8, 16384), (4, 40960)]:
+            lib.su2_init(dims, 2.3, 4, lib.HOT)
+            lib.su2_set_plan(*plan)
+            lib.su2_set_proposal(1)
+            lib.su2_sweep(2)
+            got = (lib.su2_links(), lib.su2_imh_counters())
+            if ref is None:
+                ref = got
+                assert got[1][0] > 0
+            assert np.array_equal(got[0], ref[0]) and got[1] == ref[1], (points, plan)
+        # tuning with the learned proposal installed leaves lattice and counters alone
+        before = (lib.su2_links(), lib.su2_imh_counters(), lib.su2_counters())
+        lib.su2_tune(1)
+        assert np.array_equal(lib.su2_links(), before[0])
+        assert lib.su2_imh_counters() == before[1] and lib.su2_counters() == before[2]
+
+
 def _binned(x, nbins=10):
     x = np.asarray(x)
     b = len(x) // nbins
@@ -151,9 +176,10 @@ def test_learned_chain_matches_heat_bath(lib, trained):
     lib.su2_init(dims, beta, 3, lib.HOT)
     lib.su2_set_proposal(1)
     lib.su2_sweep(100)
-    lib.su2_imh_counters()
+    p0, a0 = lib.su2_imh_counters()  # counts since su2_set_proposal
     im = lib.su2_sweep_measure(400, 1)[:, 0]
     prop, acc = lib.su2_imh_counters()
+    prop, acc = prop - p0, acc - a0
     m1, s1 = _binned(kp)
     m2, s2 = _binned(im)
     z = (m2 - m1) / np.hypot(s1, s2)

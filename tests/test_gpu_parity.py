@@ -310,20 +310,23 @@ def test_measured_sweep_same_links_as_plain_sweep(lib):
 
 
 def test_launch_plans_bit_identical(lib):
-    """Tile order and LDS reservation change only the speed: links after a few
-    sweeps are bit-identical for every plan, and su2_tune leaves the lattice,
-    sweep index and counters untouched."""
+    """Tile order and LDS reservation change only the speed: links, counters
+    and the in-sweep plaquettes after a few sweeps are bit-identical for every
+    plan, and su2_tune leaves the lattice, sweep index and counters
+    untouched."""
     dims = (64, 64, 8, 8)  # an (x2, x3) plane holds 8 tiles of 256 half-sites: one per XCD
     lib.su2_init(dims, 2.3, 5, lib.HOT)
-    lib.su2_sweep(3)
+    lib.su2_sweep(2)
+    m_ref = lib.su2_sweep_measure(1, 1)
     ref = lib.su2_links()
     c_ref = lib.su2_counters()
     for kind, lds in [(0, 0), (4, 0), (8, 32768), (4, 40960), (0, 16384)]:
         lib.su2_init(dims, 2.3, 5, lib.HOT)
         lib.su2_set_plan(kind, lds)
         lib.su2_sweep(2)
-        lib.su2_sweep_measured(1)
+        m = lib.su2_sweep_measure(1, 1)
         assert np.array_equal(lib.su2_links(), ref), (kind, lds)
+        assert np.array_equal(m, m_ref), (kind, lds)
         assert lib.su2_counters() == c_ref
     lib.su2_init(dims, 2.3, 5, lib.HOT)
     lib.su2_sweep(1)

@@ -226,15 +226,18 @@ int su2_batch_sweep(int32_t n);
 
 /* How su2_batch_sweep runs: mode 0 = one launch per (parity, mu) pass over
  * the tiles of all replicas, replayed from a hipGraph; mode 1 = one
- * persistent launch per call (graph-captured with a counter reset), in which
- * workgroups take (sweep, pass, replica, tiles) items in order and an item
- * waits for its replica's previous pass (per-replica completion counters).
- * tiles_per_item (1..64) tiles of 256 half-sites form one work item;
- * lds_bytes (0..65536) caps resident workgroups.  Results do not depend on
- * any of these. */
+ * persistent launch per call (graph-captured with a counter reset and a
+ * completion check), in which each replica is pinned to one XCD (replicas
+ * balanced over the XCDs by size) and the workgroups running on an XCD take
+ * (sweep, pass, replica, tiles) items of its replicas from that XCD's queue in
+ * order; an item waits for its replica's previous pass (per-replica
+ * completion counters).  SU2_EDEVICE if a wait exceeds the spin limit or an
+ * XCD's queue was left unfinished.  tiles_per_item (1..64) tiles of 256
+ * half-sites form one work item; lds_bytes (0..65536) caps resident
+ * workgroups.  Results do not depend on any of these. */
 int su2_batch_set_mode(int32_t mode, int32_t tiles_per_item, int32_t lds_bytes);
 
-/* Time every {mode 0, 1} x {1, 2, 4 tiles per item} x {0, 24 KiB LDS} over
+/* Time every {mode 0, 1} x {1, 2, 4, 8, 16 tiles per item} x {0, 24 KiB LDS} over
  * `sweeps` sweeps on a saved copy of the state (restored afterwards) and
  * install the fastest; out (nullable) receives {mode, tiles_per_item,
  * lds_bytes}. */

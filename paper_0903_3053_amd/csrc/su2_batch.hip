@@ -6,15 +6,22 @@
 // update is a pure function of the links it reads and its Philox counter):
 //   grouped     one launch per (parity, mu) pass covering the tiles of all
 //               replicas, eight per sweep, replayed from a hipGraph;
-//   persistent  one launch for all n sweeps: workgroups take work items
-//               (sweep, pass, replica, k tiles) in a fixed order, item i going
-//               to workgroup i mod G with G workgroups co-resident; an item
-//               waits until its replica's previous pass is complete
-//               (per-replica counters with agent-scope release/acquire).
-//               Waits only reach back to earlier items, so the queue drains;
-//               every wait is also bounded by a wall-clock limit after which
-//               the workgroup raises an error flag and leaves, so the kernel
-//               always ends.
+//   persistent  one launch for all n sweeps.  Each replica belongs to one XCD
+//               (the host balances replicas over the XCDs by their tiles);
+//               a workgroup reads the XCD it runs on from the hardware and
+//               takes work items (sweep, pass, replica, k tiles) of that
+//               XCD's replicas from the XCD's queue, in order.  An item waits
+//               until its replica's previous pass is complete.  Since every
+//               item of a replica runs on the same XCD, the links it reads
+//               were written through that XCD's L2: the handshake needs the
+//               writer's stores to have reached L2 (s_waitcnt before counting
+//               the item done) and the reader's L1 invalidated after the wait,
+//               not the L2 write-back an agent-scope release costs on a
+//               multi-XCD chip.  Waits only reach
+//               back to earlier items, so every queue drains; every wait is
+//               also bounded by a wall-clock limit after which the workgroup
+//               raises an error flag and leaves, so the kernel always ends,
+//               and a check after the kernel flags any queue left unfinished.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -43,6 +50,23 @@ struct BatchDev {
     float4 *links;
     unsigned long long *counters;
 };
+
+// Replicas grouped by XCD for the persistent kernel: group x holds the
+// replicas rep[off[x]] .. rep[off[x + 1] - 1]; pre[j] counts the work items of
+// one pass of the group's replicas before rep[j]; total[x] those of the group.
+constexpr uint32_t kMaxXcd = 16;
+struct XcdMap {
+    const uint32_t *rep;
+    const uint32_t *pre;
+    uint32_t off[kMaxXcd + 1];
+    uint32_t total[kMaxXcd];
+};
+
+__device__ __forceinline__ uint32_t xcc_id()
+{
+    // hwreg(HW_REG_XCC_ID, 0, 4): the XCD this wave runs on
+    return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u;
+}
 
 // replica r with prefix[r] <= i < prefix[r + 1] (wave-uniform binary search)
 __device__ __forceinline__ uint32_t find_rep(const BatchDev &b, uint32_t i)
@@ -90,32 +114,51 @@ __global__ void k_batch_tick(uint32_t *sweep_ptr, uint32_t n)
     if (threadIdx.x == 0) *sweep_ptr += n;
 }
 
-// Zero the persistent kernel's completion counters and error flag (a kernel,
-// not a memset, so the graph that holds it replays correctly).
-__global__ void k_batch_reset(unsigned int *done, uint32_t n, unsigned int *err)
+// Zero the persistent kernel's completion counters, queues and error flag (a
+// kernel, not a memset, so the graph that holds it replays correctly).
+__global__ void k_batch_reset(unsigned int *done, uint32_t n, unsigned int *next, unsigned int *err)
 {
     for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) done[i] = 0u;
+    if (threadIdx.x < kMaxXcd) next[threadIdx.x] = 0u;
     if (threadIdx.x == 0) *err = 0u;
 }
 
-__global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchDev b,
+__global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchDev b, XcdMap xm,
                                                              const uint32_t *__restrict__ sweep_ptr,
                                                              uint32_t nsweeps, uint32_t k,
-                                                             unsigned int *done, unsigned int *err,
+                                                             unsigned int *done, unsigned int *next,
+                                                             unsigned int *err,
                                                              unsigned long long spin_limit)
 {
     extern __shared__ float reserve[];
     (void)reserve;
-    __shared__ uint32_t ok_sh;
-    const uint32_t per_pass = b.prefix[b.n];
-    const uint64_t total = (uint64_t)nsweeps * 8u * per_pass;
+    __shared__ uint32_t item_sh, ok_sh;
+    const uint32_t x = xcc_id();
+    if (x >= kMaxXcd || xm.off[x] == xm.off[x + 1]) return;  // no replica on this XCD
+    const uint32_t j0 = xm.off[x], j1 = xm.off[x + 1];
+    const uint32_t per_pass = xm.total[x];
+    const uint32_t total = nsweeps * 8u * per_pass;  // below 2^32 (checked by the host)
     const uint32_t s0 = *sweep_ptr;
-    for (uint64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const uint32_t sk = (uint32_t)(item / per_pass);  // sweep * 8 + pass
-        const uint32_t rem = (uint32_t)(item - (uint64_t)sk * per_pass);
-        const uint32_t r = find_rep(b, rem);
+    // the next item is taken from the queue while the current one runs
+    uint32_t ahead = 0u;
+    if (threadIdx.x == 0)
+        item_sh = __hip_atomic_fetch_add(&next[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        __syncthreads();
+        const uint32_t item = item_sh;
+        if (item >= total) break;  // workgroup-uniform
+        if (threadIdx.x == 0)
+            ahead = __hip_atomic_fetch_add(&next[x], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t sk = item / per_pass;  // sweep * 8 + pass
+        const uint32_t rem = item - sk * per_pass;
+        uint32_t lo = j0, hi = j1;  // the group's replica holding item rem
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (xm.pre[mid] <= rem) lo = mid; else hi = mid;
+        }
+        const uint32_t r = xm.rep[lo];
         const Rep rep = b.reps[r];
-        const uint32_t it = rem - b.prefix[r];
+        const uint32_t it = rem - xm.pre[lo];
         const uint32_t pass = sk & 7u;
         // Sec. 2.4 order: odd sites for mu = 0..3, then even sites
         const uint32_t p = pass < 4u ? 1u : 0u, mu = pass & 3u;
@@ -123,9 +166,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchDev b,
             // every item of this replica's previous passes must be complete
             const unsigned int target = sk * rep.items;
             unsigned int ok = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0u;
-            if (ok && __hip_atomic_load(&done[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (ok && __hip_atomic_load(&done[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                 const unsigned long long t0 = wall_clock64();
-                while (__hip_atomic_load(&done[r], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                while (__hip_atomic_load(&done[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
                     if (wall_clock64() - t0 > spin_limit ||
                         __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                         ok = 0u;
@@ -139,15 +182,29 @@ __global__ __launch_bounds__(kBlock) void k_batch_persistent(BatchDev b,
         }
         __syncthreads();
         if (!ok_sh) break;  // workgroup-uniform: every wave leaves
-        // make the previous pass's links, written by other workgroups, visible
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // the previous pass's links were written through this XCD's L2: each
+        // wave invalidates the compute unit's L1 (an agent-scope invalidate;
+        // the workgroup-scope one leaves L1 alone), so its loads reach L2
+        asm volatile("buffer_inv sc1" ::: "memory");
         run_item(b, rep, p, mu, s0 + (sk >> 3), it, k);
-        // publish this item's links before counting it done
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        // this wave's link stores have reached L2 before the item counts as done
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        if (threadIdx.x == 0)
-            __hip_atomic_fetch_add(&done[r], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0) {
+            __hip_atomic_fetch_add(&done[r], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            item_sh = ahead;
+        }
     }
+}
+
+// After a persistent launch: every XCD queue that holds items must have been
+// drained (its counter passed the item count), else the launch ran without a
+// workgroup on that XCD and the error flag is raised.
+__global__ void k_batch_check(XcdMap xm, uint32_t nsweeps, const unsigned int *next, unsigned int *err)
+{
+    const uint32_t x = threadIdx.x;
+    if (x < kMaxXcd && xm.off[x] != xm.off[x + 1] && next[x] < nsweeps * 8u * xm.total[x])
+        atomicOr(err, 2u);
 }
 
 // Per-replica plaquette: workgroup w of replica r (tiles of 256 sites over both
@@ -252,6 +309,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_pack(BatchDev b, uint32_t r,
     for (uint32_t mu = 0; mu < 4; ++mu) out[(size_t)lex * 4 + mu] = L[arr(g, mu, p) + h];
 }
 
+// Which XCD each workgroup of a grid of the persistent kernel's size runs on.
+__global__ void k_batch_xcc(uint32_t *out)
+{
+    if (threadIdx.x == 0) out[blockIdx.x] = xcc_id();
+}
+
 }  // namespace su2
 
 // ---------------------------------------------------------------------------
@@ -275,7 +338,13 @@ struct Batch {
     uint32_t *d_sweep = nullptr;
     uint64_t sweep = 0;
     unsigned int *d_done = nullptr;
+    unsigned int *d_next = nullptr;    // persistent: one work queue per XCD
     unsigned int *d_err = nullptr;
+    uint32_t *d_xrep = nullptr;        // persistent: replicas grouped by XCD
+    uint32_t *d_xpre = nullptr;
+    std::vector<uint32_t> xcd_of;      // replica -> XCD
+    std::vector<uint32_t> xcd_wg;      // workgroups of the persistent grid per XCD
+    XcdMap xm{};
     double2 *d_partials = nullptr;
     double *d_out = nullptr;
     int32_t mode = 0;                  // 0 grouped, 1 persistent
@@ -321,7 +390,7 @@ void batch_release()
     if (B.ready) hipDeviceSynchronize();
     drop_graphs();
     void *ptrs[] = { B.d_reps, B.d_prefix, B.d_site_prefix, B.links, B.counters, B.d_sweep,
-                     B.d_done, B.d_err, B.d_partials, B.d_out };
+                     B.d_done, B.d_next, B.d_err, B.d_xrep, B.d_xpre, B.d_partials, B.d_out };
     for (void *p : ptrs)
         if (p) hipFree(p);
     B = Batch{};
@@ -336,6 +405,55 @@ BatchDev dev()
     d.links = B.links;
     d.counters = B.counters;
     return d;
+}
+
+// The persistent kernel's replica groups: replicas (largest first) go to the
+// XCD with the least work per workgroup so far, among the XCDs the persistent
+// grid's workgroups land on; then each group's item prefix for the current k.
+int set_xcd_map()
+{
+    const size_t n = B.reps.size();
+    if (B.xcd_wg.size() != kMaxXcd) return SU2_OK;  // built once the grid has been probed
+    if (B.xcd_of.size() != n) {
+        B.xcd_of.assign(n, 0u);
+        std::vector<size_t> order(n);
+        for (size_t r = 0; r < n; ++r) order[r] = r;
+        std::stable_sort(order.begin(), order.end(),
+                         [](size_t a, size_t b) { return B.reps[a].tiles > B.reps[b].tiles; });
+        std::vector<double> load(kMaxXcd, 0.0);
+        for (size_t r : order) {
+            uint32_t best = kMaxXcd;
+            for (uint32_t x = 0; x < kMaxXcd; ++x) {
+                if (B.xcd_wg[x] == 0) continue;
+                if (best == kMaxXcd || (load[x] + B.reps[r].tiles) / B.xcd_wg[x] <
+                                           (load[best] + B.reps[r].tiles) / B.xcd_wg[best])
+                    best = x;
+            }
+            if (best == kMaxXcd) return bfail(SU2_EDEVICE, "no XCD found for the persistent kernel");
+            B.xcd_of[r] = best;
+            load[best] += B.reps[r].tiles;
+        }
+    }
+    std::vector<uint32_t> rep, pre;
+    XcdMap m{};
+    for (uint32_t x = 0; x < kMaxXcd; ++x) {
+        m.off[x] = (uint32_t)rep.size();
+        uint32_t acc = 0;
+        for (size_t r = 0; r < n; ++r)
+            if (B.xcd_of[r] == x) {
+                rep.push_back((uint32_t)r);
+                pre.push_back(acc);
+                acc += B.reps[r].items;
+            }
+        m.total[x] = acc;
+    }
+    m.off[kMaxXcd] = (uint32_t)rep.size();
+    BTRY(hipMemcpy(B.d_xrep, rep.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice));
+    BTRY(hipMemcpy(B.d_xpre, pre.data(), n * sizeof(uint32_t), hipMemcpyHostToDevice));
+    m.rep = B.d_xrep;
+    m.pre = B.d_xpre;
+    B.xm = m;
+    return SU2_OK;
 }
 
 // item prefix for k tiles per item; uploads reps (items field) and prefix
@@ -353,7 +471,7 @@ int set_items(uint32_t k)
     B.per_pass = prefix.back();
     B.k = k;
     drop_graphs();
-    return SU2_OK;
+    return set_xcd_map();
 }
 
 int add_node(hipGraph_t g, hipGraphNode_t *prev, const void *func, dim3 grid, dim3 block,
@@ -411,18 +529,24 @@ int build_persistent_graph(int32_t n)
     BTRY(hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
     BatchDev d = dev();
-    unsigned int *done = B.d_done, *err = B.d_err;
+    unsigned int *done = B.d_done, *next = B.d_next, *err = B.d_err;
     uint32_t nrep = (uint32_t)B.reps.size();
-    void *a0[] = { &done, &nrep, &err };
+    XcdMap xm = B.xm;
+    void *a0[] = { &done, &nrep, &next, &err };
     int rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_reset), dim3(1), dim3(kBlock),
                       0, a0);
     const uint32_t *sp = B.d_sweep;
     uint32_t ns = (uint32_t)n, k = B.k;
     unsigned long long lim = B.spin_limit;
     if (rc == SU2_OK) {
-        void *a1[] = { &d, &sp, &ns, &k, &done, &err, &lim };
+        void *a1[] = { &d, &xm, &sp, &ns, &k, &done, &next, &err, &lim };
         rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_persistent),
                       dim3(B.grid_persistent), dim3(kBlock), B.lds, a1);
+    }
+    const unsigned int *cnext = B.d_next;
+    if (rc == SU2_OK) {
+        void *a3[] = { &xm, &ns, &cnext, &err };
+        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_check), dim3(1), dim3(64), 0, a3);
     }
     uint32_t *spw = B.d_sweep;
     if (rc == SU2_OK) {
@@ -450,6 +574,25 @@ int size_persistent_grid()
     if (per_cu < 1) return bfail(SU2_EDEVICE, "persistent kernel does not fit on a compute unit");
     B.grid_persistent = (uint32_t)(ncu * per_cu);
     if (B.spin_limit == 0) B.spin_limit = (unsigned long long)clk_khz * 1000ull * 2ull;  // 2 s
+    // where the workgroups of such a grid run: the replica groups follow it
+    uint32_t *d_x = nullptr;
+    if (hipMalloc(&d_x, B.grid_persistent * sizeof(uint32_t)) != hipSuccess) {
+        hipGetLastError();
+        return bfail(SU2_ENOMEM, "cannot allocate the XCD probe");
+    }
+    hipLaunchKernelGGL(k_batch_xcc, dim3(B.grid_persistent), dim3(kBlock), B.lds, nullptr, d_x);
+    std::vector<uint32_t> h(B.grid_persistent);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(h.data(), d_x, h.size() * sizeof(uint32_t), hipMemcpyDeviceToHost);
+    hipFree(d_x);
+    if (e != hipSuccess) return bfail(SU2_EDEVICE, "XCD probe: %s", hipGetErrorString(e));
+    std::vector<uint32_t> wg(kMaxXcd, 0u);
+    for (uint32_t v : h) wg[v < kMaxXcd ? v : 0]++;
+    if (wg != B.xcd_wg) {
+        B.xcd_wg = wg;
+        B.xcd_of.clear();
+        return set_xcd_map();
+    }
     return SU2_OK;
 }
 
@@ -457,7 +600,8 @@ int check_error_flag()
 {
     unsigned int err = 0;
     BTRY(hipMemcpy(&err, B.d_err, sizeof err, hipMemcpyDeviceToHost));
-    if (err) return bfail(SU2_EDEVICE, "a persistent-kernel dependency wait exceeded its time limit");
+    if (err & 1u) return bfail(SU2_EDEVICE, "a persistent-kernel dependency wait exceeded its time limit");
+    if (err) return bfail(SU2_EDEVICE, "a persistent launch left an XCD's work queue unfinished");
     return SU2_OK;
 }
 
@@ -471,9 +615,11 @@ int run_batch(int32_t n)
         }
         for (int32_t i = 0; i < n; ++i) BTRY(hipGraphLaunch(B.graph, nullptr));
     } else {
-        // items of one launch must stay below 2^32
+        // the item counters of one launch (items plus one last take per
+        // workgroup) must stay below 2^32
         const uint64_t per_sweep = 8ull * B.per_pass;
-        const int32_t chunk = (int32_t)std::min<uint64_t>((uint64_t)n, 0xffffffffull / per_sweep);
+        const uint64_t room = 0xffffffffull - (uint64_t)B.grid_persistent - 1ull;
+        const int32_t chunk = (int32_t)std::min<uint64_t>((uint64_t)n, room / per_sweep);
         if (chunk < 1) return bfail(SU2_EINVAL, "batch too large for one persistent launch");
         int32_t left = n;
         while (left > 0) {
@@ -558,7 +704,10 @@ int su2_batch_init(int32_t n, const int32_t *dims, const double *betas, const ui
         hipMalloc(&B.counters, coff * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&B.d_sweep, sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&B.d_done, reps.size() * sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&B.d_next, kMaxXcd * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc(&B.d_err, sizeof(unsigned int)) != hipSuccess ||
+        hipMalloc(&B.d_xrep, reps.size() * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&B.d_xpre, reps.size() * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&B.d_partials, np * sizeof(double2)) != hipSuccess ||
         hipMalloc(&B.d_out, reps.size() * 3 * sizeof(double)) != hipSuccess) {
         hipGetLastError();
@@ -632,7 +781,7 @@ int su2_batch_tune(int32_t sweeps, int32_t out[3])
     struct Cand { int32_t mode, k, lds; };
     std::vector<Cand> cands;
     for (int32_t mode : { 0, 1 })
-        for (int32_t k : { 1, 2, 4 })
+        for (int32_t k : { 1, 2, 4, 8, 16 })
             for (int32_t lds : { 0, 24576 }) cands.push_back({ mode, k, lds });
     float best = 1e30f;
     Cand bc{ 0, 1, 0 };

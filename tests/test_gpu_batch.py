@@ -83,7 +83,7 @@ def test_batch_tune_keeps_state(lib, singles):
     lib.su2_batch_sweep(1)
     before = [lib.su2_batch_links(r) for r in range(len(REPLICAS))]
     choice = lib.su2_batch_tune(1)
-    assert choice[0] in (0, 1) and choice[1] in (1, 2, 4)
+    assert choice[0] in (0, 1) and choice[1] in (1, 2, 4, 8, 16)
     assert lib.su2_batch_sweep_index() == 1
     for r in range(len(REPLICAS)):
         assert np.array_equal(lib.su2_batch_links(r), before[r])
@@ -110,6 +110,26 @@ def test_persistent_wait_limit_reports_and_recovers(lib, singles):
     lib.su2_batch_sweep(NSWEEPS)
     for r, (U, _, _) in enumerate(singles):
         assert np.array_equal(lib.su2_batch_links(r), U)
+
+
+def test_persistent_equals_grouped_on_64_replicas(lib):
+    """The 64-replica workload (L in {8, ..., 24}, beta in [1.8, 2.8]): three
+    sweeps in the persistent mode (replicas pinned to XCDs, several tile
+    counts per item) leave every link of every replica bit-identical to the
+    grouped mode."""
+    table = su2_inputs.replica_table(64, 1)
+    args = ([t["dims"] for t in table], [t["beta"] for t in table], [t["seed"] for t in table], lib.HOT)
+    lib.su2_batch_init(*args)
+    lib.su2_batch_set_mode(0, 1, 0)
+    lib.su2_batch_sweep(3)
+    ref = [lib.su2_batch_links(r) for r in range(len(table))]
+    for mode in [(1, 1, 0), (1, 8, 24576)]:
+        lib.su2_batch_init(*args)
+        lib.su2_batch_set_mode(*mode)
+        lib.su2_batch_sweep(1)
+        lib.su2_batch_sweep(2)
+        for r in range(len(table)):
+            assert np.array_equal(lib.su2_batch_links(r), ref[r]), (mode, r)
 
 
 def test_batch_errors(lib):

@@ -131,10 +131,12 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
     integrated CDFs of 4096 alphas, then 32^4 beta = 2.3 from the same hot start
     for `sweeps` sweeps with the heat-bath and with the learned independence-
     Metropolis step; plaquette measured every sweep, averages after a 20 %
-    thermalisation cut with binned errors."""
+    thermalisation cut with Gamma-method errors and integrated autocorrelation
+    times."""
     import numpy as np
     import torch
     import su2_inputs
+    from paper_0903_3053_amd.stats import gamma_method
     dims, beta, seed = (32, 32, 32, 32), 2.3, 1
     V = int(np.prod(dims))
     su2.su2_mlp_set_params(su2_inputs.mlp_init(1))
@@ -145,11 +147,6 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
     # alpha between rows); 31 rows fit the pass kernel's LDS copy
     su2.su2_mlp_tabulate(TABLE_ROWS)
     t_train = time.perf_counter() - t0
-
-    def binned(x, nb=20):
-        b = len(x) // nb
-        m = np.asarray(x[: b * nb]).reshape(nb, b).mean(axis=1)
-        return float(m.mean()), float(m.std(ddof=1) / np.sqrt(nb))
 
     out = {}
     for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
@@ -167,8 +164,9 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
         su2.su2_set_plan(*plan)
         su2.su2_set_proposal(kind)
         h = su2.su2_sweep_measure(sweeps, 1)[:, 0]
-        m, e = binned(h[sweeps // 5:])
+        m, e, tau, dtau, _ = gamma_method(h[sweeps // 5:])
         rec = {"link_updates_per_s": rate, "plaquette": m, "plaquette_err": e,
+               "tau_int_sweeps": tau, "tau_int_err": dtau,
                "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}}
         if kind:
             prop, acc = su2.su2_imh_counters()
@@ -181,7 +179,10 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
                          "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
             **out,
             "z_plaquette": (lp["plaquette"] - kp["plaquette"]) / float(np.hypot(kp["plaquette_err"], lp["plaquette_err"])),
-            "speed_ratio": lp["link_updates_per_s"] / kp["link_updates_per_s"]}
+            "speed_ratio": lp["link_updates_per_s"] / kp["link_updates_per_s"],
+            # updates/s per integrated autocorrelation time of <P>: independent samples/s
+            "effective_speed_ratio": (lp["link_updates_per_s"] / lp["tau_int_sweeps"])
+                                     / (kp["link_updates_per_s"] / kp["tau_int_sweeps"])}
 
 
 def main():

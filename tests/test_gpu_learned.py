@@ -13,6 +13,7 @@ import pytest
 import oracle
 import su2_inputs
 from oracle import cdf, mlp
+from paper_0903_3053_amd.stats import gamma_method
 from parity import UNIT_TOL, parity_of, unitarity_error
 
 pytestmark = pytest.mark.gpu
@@ -157,16 +158,10 @@ def test_learned_sweeps_identical_across_plans(lib):
         assert lib.su2_imh_counters() == before[1] and lib.su2_counters() == before[2]
 
 
-def _binned(x, nbins=10):
-    x = np.asarray(x)
-    b = len(x) // nbins
-    m = x[: b * nbins].reshape(nbins, b).mean(axis=1)
-    return m.mean(), m.std(ddof=1) / np.sqrt(nbins)
-
-
 def test_learned_chain_matches_heat_bath(lib, trained):
     """Same lattice, same start: the plaquette of the learned-proposal chain
-    agrees with the heat-bath chain within 3 sigma, and the trained proposal is
+    agrees with the heat-bath chain within 3 sigma (Gamma-method errors), and
+    the trained proposal is
     accepted far more often than an untrained or a uniform one."""
     dims, beta = (16, 16, 16, 16), 2.3
     _use(lib, trained[1])
@@ -180,12 +175,12 @@ def test_learned_chain_matches_heat_bath(lib, trained):
     im = lib.su2_sweep_measure(400, 1)[:, 0]
     prop, acc = lib.su2_imh_counters()
     prop, acc = prop - p0, acc - a0
-    m1, s1 = _binned(kp)
-    m2, s2 = _binned(im)
+    m1, s1, t1, _, _ = gamma_method(kp)
+    m2, s2, t2, _, _ = gamma_method(im)
     z = (m2 - m1) / np.hypot(s1, s2)
     rate_trained = acc / prop
-    print(f"16^4 beta 2.3: <P> heat-bath {m1:.6f}+-{s1:.6f}, learned {m2:.6f}+-{s2:.6f}, z = {z:+.2f}; "
-          f"acceptance {rate_trained:.4f}")
+    print(f"16^4 beta 2.3: <P> heat-bath {m1:.6f}+-{s1:.6f} (tau_int {t1:.1f}), learned "
+          f"{m2:.6f}+-{s2:.6f} (tau_int {t2:.1f}), z = {z:+.2f}; acceptance {rate_trained:.4f}")
     assert abs(z) < 3.0
     assert rate_trained > 0.85
     rates = {}

@@ -10,6 +10,7 @@ import pytest
 
 import su2_np
 from exact_density import haar_cdf, mean_x0
+from paper_0903_3053_amd.stats import gamma_method
 from parity import UNIT_TOL, unitarity_error
 
 pytestmark = pytest.mark.gpu
@@ -26,13 +27,6 @@ def lib():
     su2.su2_finalize()
 
 
-def binned(x, nbins=16):
-    """Mean and its standard error from nbins consecutive bins (bins longer
-    than the autocorrelation time make the bin means independent)."""
-    x = np.asarray(x, dtype=np.float64)
-    b = len(x) // nbins
-    m = x[: b * nbins].reshape(nbins, b).mean(axis=1)
-    return float(m.mean()), float(m.std(ddof=1) / np.sqrt(nbins))
 
 
 def test_beta_zero_is_haar(lib):
@@ -53,8 +47,8 @@ def test_strong_coupling(lib):
     lib.su2_init((16, 16, 16, 16), 0.1, 5, lib.HOT)
     lib.su2_sweep(50)
     hist = lib.su2_sweep_measure(800, 1)
-    m, se = binned(hist[:, 0])
-    print(f"strong coupling: <P> = {m:.6f} +- {se:.6f}, I2/I1 = {mean_x0(0.1):.6f}")
+    m, se, tau, _, _ = gamma_method(hist[:, 0])
+    print(f"strong coupling: <P> = {m:.6f} +- {se:.6f} (tau_int {tau:.2f}), I2/I1 = {mean_x0(0.1):.6f}")
     assert abs(m - mean_x0(0.1)) < 4 * se
 
 
@@ -71,8 +65,8 @@ def test_equilibrium_identity(lib):
         U = lib.su2_links().astype(np.float64)
         k = np.linalg.norm(su2_np.staples(U, dims), axis=2)
         D.append(6 * su2_np.plaquette(U, dims)[0] - np.mean(k * mean_x0(beta * k)))
-    m, se = binned(D)
-    print(f"equilibrium identity at beta 2.3: <D> = {m:.2e} +- {se:.2e}")
+    m, se, tau, _, _ = gamma_method(D)
+    print(f"equilibrium identity at beta 2.3: <D> = {m:.2e} +- {se:.2e} (tau_int {tau:.2f})")
     assert abs(m) < 4 * se
     assert unitarity_error(U) <= UNIT_TOL
 
@@ -80,7 +74,7 @@ def test_equilibrium_identity(lib):
 def test_long_run_32x32x32x32_vs_oracle(lib):
     """32^4 hot start, beta in {2.2, 2.3, 2.4, 2.5}, 1000 sweeps: the GPU's
     mean plaquette over sweeps 200-999 agrees with the oracle's stored chain
-    within 3 sigma (binned errors of both)."""
+    within 3 sigma (autocorrelation-corrected errors of both, Gamma method)."""
     path = os.path.join(HERE, "golden", "oracle_su2_32x32x32x32_hot.json")
     if not os.path.exists(path):
         pytest.skip("stored oracle histories not generated")
@@ -94,11 +88,11 @@ def test_long_run_32x32x32x32_vs_oracle(lib):
         att, fail = lib.su2_counters()
         cut = n // 5
         for col, name in ((0, "P"), (1, "P_s"), (2, "P_t")):
-            mg, sg = binned(h_g[cut:, col])
-            mo, so = binned(h_o[cut:, col])
+            mg, sg, tg, _, _ = gamma_method(h_g[cut:, col])
+            mo, so, to, _, _ = gamma_method(h_o[cut:, col])
             z = (mg - mo) / np.hypot(sg, so)
-            print(f"32^4 beta {run['beta']}: {name} gpu {mg:.6f}+-{sg:.6f} oracle {mo:.6f}+-{so:.6f} "
-                  f"z = {z:+.2f}")
+            print(f"32^4 beta {run['beta']}: {name} gpu {mg:.6f}+-{sg:.6f} (tau_int {tg:.1f}) "
+                  f"oracle {mo:.6f}+-{so:.6f} (tau_int {to:.1f}) z = {z:+.2f}")
             assert abs(z) < 3.0
         upd = 4 * int(np.prod(dims)) * n
         print(f"   KP attempts/update gpu {att / upd:.5f} oracle {run['attempts'] / upd:.5f}")

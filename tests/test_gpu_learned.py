@@ -196,3 +196,26 @@ def test_learned_chain_matches_heat_bath(lib, trained):
     print(f"acceptance: trained {rate_trained:.4f}, untrained {rates['untrained']:.4f}, "
           f"uniform {rates['uniform']:.4f}")
     assert rate_trained > rates["untrained"] + 0.1 and rate_trained > rates["uniform"] + 0.1
+
+
+def test_learned_full_size_32x32x32x32(lib, trained):
+    """The learned-proposal workload at full size: 32^4, beta 2.3, hot start
+    seed 1, 1000 sweeps with each proposal from the same start, a 31-row
+    table: <P> over sweeps 200-999 agrees within 3 sigma (Gamma-method errors)
+    and the proposal is accepted > 85 % of the time."""
+    dims, beta = (32, 32, 32, 32), 2.3
+    lib.su2_mlp_set_params(trained[1])
+    lib.su2_mlp_tabulate(31)
+    out = {}
+    for kind in (0, 1):
+        lib.su2_init(dims, beta, 1, lib.HOT)
+        lib.su2_set_proposal(kind)
+        h = lib.su2_sweep_measure(1000, 1)[200:, 0]
+        out[kind] = gamma_method(h)
+    prop, acc = lib.su2_imh_counters()
+    (m0, s0, t0, _, _), (m1, s1, t1, _, _) = out[0], out[1]
+    z = (m1 - m0) / np.hypot(s0, s1)
+    print(f"32^4 beta 2.3, 1000 sweeps: <P> heat-bath {m0:.6f}+-{s0:.6f} (tau_int {t0:.1f}), learned "
+          f"{m1:.6f}+-{s1:.6f} (tau_int {t1:.1f}), z = {z:+.2f}; acceptance {acc / prop:.4f}")
+    assert abs(z) < 3.0
+    assert acc / prop > 0.85

@@ -143,6 +143,35 @@ def test_sweep_parity_per_sweep(lib):
     assert abs(att_g - att_o) <= 8 * off
 
 
+def test_full_size_64x64x64x64_sweep(lib):
+    """The benchmark workload at full size and in the benchmark's launch
+    configuration (64^4, beta 2.4, hot start seed 1, tile order 8 with 24 KiB
+    of LDS, measured sweep): the hot start equals the oracle's, and after one
+    sweep every link agrees with the oracle's sweep to 1e-5 except near the
+    few accept decisions that flip at FP32 rounding (the same per-update rate
+    as the 4^4 per-sweep test allows), the fused plaquette to 2e-6."""
+    dims, beta, seed = (64, 64, 64, 64), 2.4, 1
+    n_upd = 4 * 64**4
+    U = oracle.init(dims, seed, oracle.HOT)
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    lib.su2_set_plan(8, 24576)
+    assert np.max(np.abs(lib.su2_links() - U)) <= 1e-6
+    hist = lib.su2_sweep_measure(1, 1)
+    gpu = lib.su2_links()
+    att_o, _ = oracle.sweep(dims, U, beta, seed, 0)
+    err = np.max(np.abs(gpu - U), axis=2)
+    off = int(np.sum(err > 1e-5))
+    worst = float(np.max(err[err <= 1e-5]))
+    P = oracle.plaquette(dims, U)
+    att_g = lib.su2_counters()[0]
+    print(f"64^4 one sweep: {n_upd} updates, {off} links off by > 1e-5, max err of the rest {worst:.2e}; "
+          f"P gpu {hist[0, 0]:.8f} oracle {P[0]:.8f}; attempts gpu {att_g} oracle {att_o}")
+    assert off <= 5e-5 * n_upd
+    assert np.all(np.abs(hist[0, :3] - P) <= 2e-6)
+    assert abs(att_g - att_o) <= 8 * off
+    assert unitarity_error(gpu) <= UNIT_TOL
+
+
 def test_trajectory_4x4_cold(lib):
     """Free-running 100 sweeps of the 4^4 beta = 2.3 cold workload (seed 1),
     GPU and oracle from the same start with the same random numbers.  Rounding

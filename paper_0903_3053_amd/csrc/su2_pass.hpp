@@ -294,7 +294,7 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
             const uint32_t g0 = min((uint32_t)tpos, imh.G - 2u);
             const float f = tpos - (float)g0;
             const uint4 r = draw(key, lex, MU, kPurposeImh, s, 0u);
-            const float ik = 1.0f / k;
+            const float ik = __builtin_amdgcn_rcpf(k);
             const float xc = fminf(1.0f, fmaxf(-1.0f, qdot(uold, w) * ik));
             float xp, num;
             bool acc;
@@ -309,7 +309,7 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
             if (acc) {
                 rotate = true;
                 x0n = xp;
-                amag = sqrtf(num);
+                amag = __builtin_amdgcn_sqrtf(num);
                 rz = r.z;
                 rphi = r.w;
             } else {
@@ -333,18 +333,21 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
             const uint4 r = draw(key, lex, MU, kPurposeUpdate, s, kSlotDirection);
             rotate = true;
             x0n = 1.0f - 2.0f * lam2;
-            amag = 2.0f * sqrtf(lam2 * (1.0f - lam2));
+            amag = 2.0f * __builtin_amdgcn_sqrtf(lam2 * (1.0f - lam2));
             rz = r.x;
             rphi = r.y;
         }
     }
     if (rotate) {
+        // the direction and the rotation feed only the link's value (checked to
+        // 1e-5), not a decision: hardware sin/cos of 2 pi u (their argument in
+        // revolutions), reciprocal and square root, each within a few ulp
         const float cz = 2.0f * unit24(rz) - 1.0f;
-        float sphi, cphi;
-        sincospif(2.0f * unit24(rphi), &sphi, &cphi);
-        const float sn = sqrtf(1.0f - cz * cz);
+        const float sphi = __builtin_amdgcn_sinf(unit24(rphi));
+        const float cphi = __builtin_amdgcn_cosf(unit24(rphi));
+        const float sn = __builtin_amdgcn_sqrtf(1.0f - cz * cz);
         const float4 X = make_float4(x0n, amag * sn * cphi, amag * sn * sphi, amag * cz);
-        const float ik = 1.0f / k;
+        const float ik = __builtin_amdgcn_rcpf(k);
         const float4 V = make_float4(w.x * ik, w.y * ik, w.z * ik, w.w * ik);
         un = unitize(qmul(X, V));
         st4_stream<OFF32>(Lout, h, un);

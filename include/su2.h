@@ -238,9 +238,9 @@ int su2_batch_sweep(int32_t n);
 int su2_batch_set_mode(int32_t mode, int32_t tiles_per_item, int32_t lds_bytes);
 
 /* Time every {mode 0, 1} x {1, 2, 4, 8, 16 tiles per item} x {0, 24 KiB LDS} over
- * `sweeps` sweeps on a saved copy of the state (restored afterwards) and
- * install the fastest; out (nullable) receives {mode, tiles_per_item,
- * lds_bytes}. */
+ * `sweeps` sweeps, in three rounds over all candidates, on a saved copy of the
+ * state (restored afterwards) and install the one with the smallest median;
+ * out (nullable) receives {mode, tiles_per_item, lds_bytes}. */
 int su2_batch_tune(int32_t sweeps, int32_t out[3]);
 
 /* Bound, in wall-clock ticks, on any single dependency wait of the

@@ -783,31 +783,42 @@ int su2_batch_tune(int32_t sweeps, int32_t out[3])
     for (int32_t mode : { 0, 1 })
         for (int32_t k : { 1, 2, 4, 8, 16 })
             for (int32_t lds : { 0, 24576 }) cands.push_back({ mode, k, lds });
-    float best = 1e30f;
-    Cand bc{ 0, 1, 0 };
+    // three rounds over all candidates; each ranked by the median of its rounds
+    constexpr int kRounds = 3;
+    std::vector<float> ms_all(cands.size() * kRounds, 1e30f);
     hipEvent_t e0, e1;
     BTRY(hipEventCreate(&e0));
     BTRY(hipEventCreate(&e1));
-    for (const Cand &c : cands) {
-        rc = su2_batch_set_mode(c.mode, c.k, c.lds);
-        if (rc) break;
-        rc = run_batch(1);  // build graphs, warm up
-        if (rc) break;
-        BTRY(hipDeviceSynchronize());
-        BTRY(hipEventRecord(e0, nullptr));
-        rc = run_batch(sweeps);
-        if (rc) break;
-        BTRY(hipEventRecord(e1, nullptr));
-        BTRY(hipEventSynchronize(e1));
-        float ms = 0.f;
-        BTRY(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < best) {
-            best = ms;
-            bc = c;
+    for (int round = 0; round < kRounds && !rc; ++round) {
+        for (size_t ci = 0; ci < cands.size(); ++ci) {
+            const Cand &c = cands[ci];
+            rc = su2_batch_set_mode(c.mode, c.k, c.lds);
+            if (rc) break;
+            rc = run_batch(1);  // build graphs, warm up
+            if (rc) break;
+            BTRY(hipDeviceSynchronize());
+            BTRY(hipEventRecord(e0, nullptr));
+            rc = run_batch(sweeps);
+            if (rc) break;
+            BTRY(hipEventRecord(e1, nullptr));
+            BTRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            BTRY(hipEventElapsedTime(&ms, e0, e1));
+            ms_all[ci * kRounds + round] = ms;
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
+    float best = 1e30f;
+    Cand bc{ 0, 1, 0 };
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+        float *m = &ms_all[ci * kRounds];
+        std::sort(m, m + kRounds);
+        if (m[kRounds / 2] < best) {
+            best = m[kRounds / 2];
+            bc = cands[ci];
+        }
+    }
     BTRY(hipMemcpy(B.links, save_l, B.link_floats4 * sizeof(float4), hipMemcpyDeviceToDevice));
     BTRY(hipMemcpy(B.counters, save_c, B.n_counters * sizeof(unsigned long long), hipMemcpyDeviceToDevice));
     const uint32_t s32 = (uint32_t)sweep0;

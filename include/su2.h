@@ -133,15 +133,18 @@ int su2_counters(uint64_t out[2]);
 int su2_set_stream(void *hip_stream);
 
 /* Launch plan of the pass kernel: order_kind 0 = workgroups in lattice order;
- * T > 0 = each XCD takes a band of x1 rows of every (x2, x3) plane and walks
- * the planes in T x T squares (only where a plane holds a multiple of 8
+ * T in 1..99 = each XCD takes a band of x1 rows of every (x2, x3) plane and
+ * walks the planes in T x T squares (only where a plane holds a multiple of 8
  * tiles of 256 half-sites and T divides L2 and L3, else SU2_EINVAL);
+ * 100 + T = the same with squares and planes walked back and forth;
+ * 200 + T = four XCDs share each plane (bands twice as thick), XCDs 0-3 on
+ * the planes with x2 < L2/2, walked as 100 + T;
  * lds_bytes (0..65536) of local memory reserved per workgroup to cap the
  * workgroups resident on a compute unit.  Results are bit-identical for every
  * plan; only the speed changes. */
 int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
 
-/* Time each plan in {order 0, 4, 8, 16} x {LDS 0, 16, 24, 32, 40 KiB} on a
+/* Time each plan in {order 0, 4, 8, 16, 108, 208} x {LDS 0, 16, 24, 32, 40 KiB} on a
  * scratch copy of the links (reps measured sweeps each, in three rounds over
  * all plans; the lattice, sweep index and all counters are untouched) and
  * install the plan with the smallest median; out (nullable) receives

@@ -568,7 +568,7 @@ int su2_tune(int32_t reps, int32_t out[2])
     // measured sweeps (as su2_sweep_measured runs them) of a copy of the links,
     // in three rounds over all candidates; the median of its rounds ranks it,
     // so slow drifts of the clock or of the cache state do not pick the plan.
-    const int32_t kinds[] = { 0, 4, 8, 16 };
+    const int32_t kinds[] = { 0, 4, 8, 16, 108, 208 };
     const uint32_t ldss[] = { 0u, 16384u, 24576u, 32768u, 40960u };
     constexpr int kRounds = 3;
     std::vector<int32_t> cand_kind;

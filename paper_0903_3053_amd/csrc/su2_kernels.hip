@@ -253,31 +253,47 @@ const void *pass_func(uint32_t mu, bool off32, bool measure, bool imh)
 uint32_t pass_blocks(const Geo &g) { return blocks_for(g.half); }
 
 // Tile orders (workgroup w runs tile order[w]; the hardware deals workgroups
-// to the 8 XCDs round-robin, w mod 8).  kind 0: identity.  kind T > 0: when a
-// (x2, x3) plane holds a multiple of 8 tiles, XCD k takes the k-th eighth of
-// every plane (a band of x1 rows) and walks the planes in T x T squares of
-// (x2, x3), so that the planes whose rows a tile's staples read were fetched
-// into the same L2 shortly before.  Returns false if the geometry does not fit
-// the scheme (the identity is then used).
+// to the 8 XCDs round-robin, w mod 8).  kind 0: identity.  kind T (1..99):
+// when a (x2, x3) plane holds a multiple of 8 tiles, XCD k takes the k-th
+// eighth of every plane (a band of x1 rows) and walks the planes in T x T
+// squares of (x2, x3), so that the planes whose rows a tile's staples read
+// were fetched into the same L2 shortly before.  kind 100 + T: the same with
+// squares and the planes inside them walked back and forth (consecutive
+// squares share an edge).  kind 200 + T: four XCDs share each plane (bands
+// twice as thick, so fewer rows are fetched by two XCDs), XCDs 0-3 taking the
+// planes with x2 < L2/2 and XCDs 4-7 the rest, walked as kind 100 + T.
+// Returns false if the geometry does not fit the scheme (the identity is then
+// used).
 bool make_order(const Geo &g, int kind, std::vector<uint32_t> &order)
 {
     const uint32_t n = pass_blocks(g);
     order.resize(n);
     for (uint32_t w = 0; w < n; ++w) order[w] = w;
     if (kind <= 0) return true;
-    const uint32_t T = (uint32_t)kind;
+    const uint32_t T = (uint32_t)(kind % 100), variant = (uint32_t)(kind / 100);
+    if (T == 0 || variant > 2) return false;
+    const bool serp = variant >= 1;
+    const uint32_t share = variant == 2 ? 4u : 8u;  // XCDs per plane
+    const uint32_t groups2 = 8u / share;            // plane groups along x2
     const uint64_t per_plane = (uint64_t)g.H0 * g.L[1];
-    if (per_plane % (8u * kBlock) || g.L[2] % T || g.L[3] % T || n % 8u) return false;
+    if (per_plane % ((uint64_t)share * kBlock) || n % 8u) return false;
+    const uint32_t P2 = g.L[2] / groups2;  // planes per group along x2
+    if (g.L[2] % groups2 || P2 % T || g.L[3] % T) return false;
     const uint32_t bpp = (uint32_t)(per_plane / kBlock);  // tiles per plane
-    const uint32_t band = bpp / 8u;                       // tiles per plane per XCD
-    const uint32_t nt2 = g.L[2] / T;
+    const uint32_t band = bpp / share;                    // tiles per plane per XCD
+    const uint32_t nt2 = P2 / T;
     for (uint32_t w = 0; w < n; ++w) {
         const uint32_t k = w % 8u, j = w / 8u;
+        const uint32_t bi = k % share, gi2 = k / share;
         const uint32_t in_band = j % band, pj = j / band;  // pj-th plane of this XCD
         const uint32_t sq = pj / (T * T), in_sq = pj % (T * T);
-        const uint32_t x2 = (sq % nt2) * T + in_sq % T;
-        const uint32_t x3 = (sq / nt2) * T + in_sq / T;
-        order[w] = (x2 + g.L[2] * x3) * bpp + k * band + in_band;
+        const uint32_t s3 = sq / nt2, i3 = in_sq / T;
+        uint32_t s2 = sq % nt2, i2 = in_sq % T;
+        if (serp && (s3 & 1u)) s2 = nt2 - 1u - s2;
+        if (serp && (i3 & 1u)) i2 = T - 1u - i2;
+        const uint32_t x2 = gi2 * P2 + s2 * T + i2;
+        const uint32_t x3 = s3 * T + i3;
+        order[w] = (x2 + g.L[2] * x3) * bpp + bi * band + in_band;
     }
     return true;
 }

@@ -10,8 +10,10 @@
 //                  weights, FP32 accumulation; the head turns outputs 0..31
 //                  into segment widths 2 softmax(z) and knots, and (training)
 //                  the log-width loss and its gradient.
-//   k_bwd3, k_bwd2, k_wgrad   backward; weight gradients summed over the
-//                  batch in a fixed order (FP64), so they are deterministic.
+//   k_bwd3, k_bwd2 backward signals per sample.
+//   k_wgrad_part, k_wgrad_reduce   weight gradients: the batch contractions on
+//                  the matrix cores (MFMA, FP32), chunk partials added in a
+//                  fixed order (FP64), so they are deterministic.
 //   k_adam         Adam on the FP32 master weights, then RNE rounding to BF16.
 // Parameters are one flat vector: W1 (64x1), b1 (64), W2 (64x64), b2 (64),
 // W3 (33x64), b3 (33) -- 6433 numbers.
@@ -239,30 +241,91 @@ __global__ void k_bwd2(const uint16_t *__restrict__ P, const float *__restrict__
     da1[i] = d * s * (1.0f + a * (1.0f - s));
 }
 
-// One thread per parameter; the sum over the batch runs in sample order (FP64).
-__global__ void k_wgrad(const float *__restrict__ alpha, const float *__restrict__ h1,
-                        const float *__restrict__ h2, const float *__restrict__ dz,
-                        const float *__restrict__ da2, const float *__restrict__ da1, uint32_t B,
-                        float *__restrict__ grad)
+// Weight gradients: sums over the batch of products of a backward signal and
+// a forward activation -- dense contractions with the batch as the inner
+// dimension, done on the matrix cores.  Workgroup c takes samples
+// [c * kChunk, (c + 1) * kChunk) and writes its partial of every parameter to
+// part[c][.]; k_wgrad_reduce then adds the partials in chunk order (FP64), so
+// the result does not depend on scheduling.
+//   dW2[u][j] = sum_b da2[b][u] h1[b][j]   four 32 x 32 tiles (waves 0..3)
+//   dW3[o][j] = sum_b dz[b][o]  h2[b][j]   o < 32: two tiles (waves 0, 1);
+//                                          o = 32 (reserved output) is zero
+// with v_mfma_f32_32x32x2f32: per instruction lane l supplies A[i][k] and
+// B[k][j] for i = j = l mod 32, k = l / 32 (two samples per instruction), and
+// holds D[8 (r / 4) + 4 (l / 32) + r mod 4][l mod 32] in accumulator r.  The
+// first- and last-layer bias and W1 sums (225 of them) run on plain lanes.
+constexpr uint32_t kChunk = 64;
+typedef float mfma_acc16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void mfma_tile(const float *__restrict__ A, uint32_t lda, uint32_t a0,
+                                          const float *__restrict__ Bm, uint32_t ldb, uint32_t b0,
+                                          uint32_t s0, uint32_t s1, float *__restrict__ out,
+                                          uint32_t ldo)
+{
+    const uint32_t l = threadIdx.x % kWave, i = l % 32u, kk = l / 32u;
+    mfma_acc16 acc = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    for (uint32_t b = s0; b < s1; b += 2u) {
+        const uint32_t bs = b + kk;
+        const float av = bs < s1 ? A[(size_t)lda * bs + a0 + i] : 0.f;
+        const float bv = bs < s1 ? Bm[(size_t)ldb * bs + b0 + i] : 0.f;
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < 16u; ++r) {
+        const uint32_t row = 8u * (r / 4u) + 4u * kk + (r % 4u);
+        out[(size_t)ldo * row + i] = acc[r];
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_wgrad_part(const float *__restrict__ alpha,
+                                                       const float *__restrict__ h1,
+                                                       const float *__restrict__ h2,
+                                                       const float *__restrict__ dz,
+                                                       const float *__restrict__ da2,
+                                                       const float *__restrict__ da1, uint32_t B,
+                                                       float *__restrict__ part)
+{
+    const uint32_t c = blockIdx.x, s0 = c * kChunk, s1 = min(B, s0 + kChunk);
+    float *pc = part + (size_t)c * kNParam;
+    const uint32_t w = threadIdx.x / kWave;
+    // dW2 tile (u0, j0) = (32 (w / 2), 32 (w % 2))
+    mfma_tile(da2, kH, 32u * (w / 2u), h1, kH, 32u * (w % 2u), s0, s1,
+              pc + kW2 + kH * (32u * (w / 2u)) + 32u * (w % 2u), kH);
+    if (w < 2u)  // dW3 tile (o0, j0) = (0, 32 w)
+        mfma_tile(dz, kOut, 0u, h2, kH, 32u * w, s0, s1, pc + kW3 + 32u * w, kH);
+    // plain sums: W1 and b1 (64 each), b2 (64), b3 (33); the reserved row of W3
+    const uint32_t t = threadIdx.x;
+    if (t < 64u) {
+        float gw = 0.f, gb = 0.f;
+        for (uint32_t b = s0; b < s1; ++b) {
+            const float d = da1[(size_t)kH * b + t];
+            gw += d * (alpha[b] / kAlphaMax);
+            gb += d;
+        }
+        pc[kW1 + t] = gw;
+        pc[kB1 + t] = gb;
+    } else if (t < 128u) {
+        const uint32_t u = t - 64u;
+        float g = 0.f;
+        for (uint32_t b = s0; b < s1; ++b) g += da2[(size_t)kH * b + u];
+        pc[kB2 + u] = g;
+    } else if (t < 128u + (uint32_t)kOut) {
+        const uint32_t o = t - 128u;
+        float g = 0.f;
+        for (uint32_t b = s0; b < s1; ++b) g += dz[(size_t)kOut * b + o];
+        pc[kB3 + o] = g;
+        pc[kW3 + kH * 32 + (o % 32u) * 2u] = 0.f;  // reserved output 32: zero gradient
+        pc[kW3 + kH * 32 + (o % 32u) * 2u + 1u] = 0.f;
+    }
+}
+
+__global__ void k_wgrad_reduce(const float *__restrict__ part, uint32_t nchunk,
+                               float *__restrict__ grad)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= (uint32_t)kNParam) return;
     double acc = 0.0;
-    if (q < (uint32_t)kB1) {
-        for (uint32_t b = 0; b < B; ++b) acc += (double)da1[kH * b + q] * (double)(alpha[b] / kAlphaMax);
-    } else if (q < (uint32_t)kW2) {
-        for (uint32_t b = 0; b < B; ++b) acc += da1[kH * b + (q - kB1)];
-    } else if (q < (uint32_t)kB2) {
-        const uint32_t u = (q - kW2) / kH, j = (q - kW2) % kH;
-        for (uint32_t b = 0; b < B; ++b) acc += (double)da2[kH * b + u] * (double)h1[kH * b + j];
-    } else if (q < (uint32_t)kW3) {
-        for (uint32_t b = 0; b < B; ++b) acc += da2[kH * b + (q - kB2)];
-    } else if (q < (uint32_t)kB3) {
-        const uint32_t o = (q - kW3) / kH, j = (q - kW3) % kH;
-        for (uint32_t b = 0; b < B; ++b) acc += (double)dz[kOut * b + o] * (double)h2[kH * b + j];
-    } else {
-        for (uint32_t b = 0; b < B; ++b) acc += dz[kOut * b + (q - kB3)];
-    }
+    for (uint32_t c = 0; c < nchunk; ++c) acc += part[(size_t)c * kNParam + q];
     grad[q] = (float)acc;
 }
 
@@ -339,6 +402,7 @@ struct Learn {
     float *loss1 = nullptr;  // one loss value
     float *table = nullptr;  // [G][33]
     uint32_t G = 0;
+    float *part = nullptr;   // [ceil(cap / kChunk)][kNParam] weight-gradient partials
 };
 
 Learn LN;
@@ -361,6 +425,7 @@ int lfail(int code, const char *fmt, ...)
     } while (0)
 
 inline uint32_t nb(size_t n, uint32_t t = 256) { return (uint32_t)((n + t - 1) / t); }
+inline uint32_t nchunks(uint32_t B) { return (B + kChunk - 1) / kChunk; }
 
 int ensure_params()
 {
@@ -388,12 +453,19 @@ int ensure_batch(uint32_t B)
         if (*bufs[i]) hipFree(*bufs[i]);
         *bufs[i] = nullptr;
     }
+    if (LN.part) hipFree(LN.part);
+    LN.part = nullptr;
     for (int i = 0; i < 12; ++i)
         if (hipMalloc(bufs[i], (size_t)B * sizes[i] * sizeof(float)) != hipSuccess) {
             hipGetLastError();
             LN.cap = 0;
             return lfail(SU2_ENOMEM, "cannot allocate network buffers for %u samples", B);
         }
+    if (hipMalloc(&LN.part, (size_t)nchunks(B) * kNParam * sizeof(float)) != hipSuccess) {
+        hipGetLastError();
+        LN.cap = 0;
+        return lfail(SU2_ENOMEM, "cannot allocate gradient partials for %u samples", B);
+    }
     LN.cap = B;
     return SU2_OK;
 }
@@ -418,8 +490,10 @@ hipError_t backward(uint32_t B)
                        B, LN.da2);
     hipLaunchKernelGGL(k_bwd2, dim3(nb((size_t)B * kH)), dim3(256), 0, nullptr, LN.P, LN.da2, LN.a1,
                        B, LN.da1);
-    hipLaunchKernelGGL(k_wgrad, dim3(nb(kNParam)), dim3(256), 0, nullptr, LN.alpha, LN.h1, LN.h2,
-                       LN.dz, LN.da2, LN.da1, B, LN.grad);
+    hipLaunchKernelGGL(k_wgrad_part, dim3(nchunks(B)), dim3(kBlock), 0, nullptr, LN.alpha, LN.h1,
+                       LN.h2, LN.dz, LN.da2, LN.da1, B, LN.part);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(kNParam)), dim3(256), 0, nullptr, LN.part,
+                       nchunks(B), LN.grad);
     return hipGetLastError();
 }
 
@@ -579,8 +653,10 @@ int su2_mlp_train(const double *alphas, int32_t n, int32_t steps, float lr0, flo
         hipLaunchKernelGGL(k_loss, dim3(1), dim3(kBlock), 0, st, LN.terms, B, d_hist, LN.step);
         hipLaunchKernelGGL(k_bwd3, dim3(nb((size_t)B * kH)), dim3(256), 0, st, LN.P, LN.dz, LN.a2, B, LN.da2);
         hipLaunchKernelGGL(k_bwd2, dim3(nb((size_t)B * kH)), dim3(256), 0, st, LN.P, LN.da2, LN.a1, B, LN.da1);
-        hipLaunchKernelGGL(k_wgrad, dim3(nb(kNParam)), dim3(256), 0, st, LN.alpha, LN.h1, LN.h2, LN.dz,
-                           LN.da2, LN.da1, B, LN.grad);
+        hipLaunchKernelGGL(k_wgrad_part, dim3(nchunks(B)), dim3(kBlock), 0, st, LN.alpha, LN.h1, LN.h2,
+                           LN.dz, LN.da2, LN.da1, B, LN.part);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(nb(kNParam)), dim3(256), 0, st, LN.part, nchunks(B),
+                           LN.grad);
         hipLaunchKernelGGL(k_adam, dim3(nb(kNParam)), dim3(256), 0, st, LN.master, LN.P, LN.grad, LN.m,
                            LN.v, LN.step, lr0, lr_min, steps);
         hipLaunchKernelGGL(k_step_tick, dim3(1), dim3(1), 0, st, LN.step);

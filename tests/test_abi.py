@@ -73,3 +73,37 @@ def test_python_binding_raises(lib):
     from paper_0903_3053_amd import su2
     with pytest.raises(su2.Su2Error):
         su2.su2_init((5, 4, 4, 4), 2.3, 1, 0, torch_memory=False)
+
+
+def test_extension_entry_points_reject_bad_arguments(lib):
+    """The batched-replica and learned-proposal entry points check their
+    arguments and state before any device work."""
+    from paper_0903_3053_amd import su2
+    i32, f64, u64 = ctypes.c_int32, ctypes.c_double, ctypes.c_uint64
+    # batch: count, extents, coupling, start; calls before a batch exists
+    dims = (i32 * 4)(3, 4, 4, 4)
+    betas = (f64 * 1)(2.0)
+    seeds = (u64 * 1)(1)
+    assert lib.su2_batch_init(0, dims, betas, seeds, 1) == su2.SU2_EINVAL
+    assert lib.su2_batch_init(1, dims, betas, seeds, 1) == su2.SU2_EINVAL  # odd extent
+    dims_ok = (i32 * 4)(4, 4, 4, 4)
+    assert lib.su2_batch_init(1, dims_ok, (f64 * 1)(-1.0), seeds, 1) == su2.SU2_EINVAL
+    assert lib.su2_batch_init(1, dims_ok, betas, seeds, 7) == su2.SU2_EINVAL
+    assert lib.su2_batch_init(1, None, betas, seeds, 1) == su2.SU2_EINVAL
+    assert lib.su2_batch_sweep(1) == su2.SU2_ESTATE
+    assert lib.su2_batch_set_mode(0, 1, 0) == su2.SU2_ESTATE
+    # learned proposal: parameter count, CDF arguments, calls before parameters exist
+    p = np.zeros(6432, dtype=np.float32)
+    assert lib.su2_mlp_set_params(p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), 6432) == su2.SU2_EINVAL
+    a = (f64 * 2)(1.0, -1.0)
+    k = (f64 * 66)()
+    assert lib.su2_cdf_knots(a, 2, k) == su2.SU2_EINVAL  # negative alpha
+    assert lib.su2_cdf_knots(a, -1, k) == su2.SU2_EINVAL
+    assert lib.su2_cdf_knots(a, 0, k) == su2.SU2_OK
+    af = (ctypes.c_float * 1)(1.0)
+    kf = (ctypes.c_float * 33)()
+    assert lib.su2_mlp_forward(af, 1, kf) == su2.SU2_ESTATE
+    assert lib.su2_mlp_tabulate(31) == su2.SU2_ESTATE
+    # the lattice is gone after su2_finalize: proposal selection is a state error
+    lib.su2_finalize()
+    assert lib.su2_set_proposal(1) == su2.SU2_ESTATE

@@ -106,7 +106,9 @@ def batched_replicas(su2, sweeps=500, compare_sweeps=50):
         dt = time.perf_counter() - t0
         modes[name] = 4 * V * compare_sweeps / dt
     su2.su2_batch_init(dims, [t["beta"] for t in table], [t["seed"] for t in table], 1)
-    chosen = su2.su2_batch_tune(2)
+    # a persistent launch pays its start and drain once per call: time candidates
+    # over enough sweeps per call for that to amortise as in the run below
+    chosen = su2.su2_batch_tune(20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     su2.su2_batch_sweep(sweeps)

@@ -605,7 +605,16 @@ int check_error_flag()
     return SU2_OK;
 }
 
-int run_batch(int32_t n)
+// Enqueue n sweeps; in persistent mode also wait for them and check the error
+// flag unless `check` is false (the caller then calls finish_batch).
+int finish_batch()
+{
+    if (B.mode == 0) return SU2_OK;
+    BTRY(hipDeviceSynchronize());
+    return check_error_flag();
+}
+
+int run_batch(int32_t n, bool check = true)
 {
     if (n <= 0) return SU2_OK;
     if (B.mode == 0) {
@@ -631,9 +640,10 @@ int run_batch(int32_t n)
             BTRY(hipGraphLaunch(B.pgraph, nullptr));
             left -= m;
         }
-        BTRY(hipDeviceSynchronize());
-        int rc = check_error_flag();
-        if (rc) return rc;
+        if (check) {
+            int rc = finish_batch();
+            if (rc) return rc;
+        }
     }
     B.sweep += (uint64_t)n;
     return SU2_OK;
@@ -798,10 +808,12 @@ int su2_batch_tune(int32_t sweeps, int32_t out[3])
             if (rc) break;
             BTRY(hipDeviceSynchronize());
             BTRY(hipEventRecord(e0, nullptr));
-            rc = run_batch(sweeps);
+            rc = run_batch(sweeps, false);  // the device time of the launches only
             if (rc) break;
             BTRY(hipEventRecord(e1, nullptr));
             BTRY(hipEventSynchronize(e1));
+            rc = finish_batch();
+            if (rc) break;
             float ms = 0.f;
             BTRY(hipEventElapsedTime(&ms, e0, e1));
             ms_all[ci * kRounds + round] = ms;

@@ -205,7 +205,7 @@ def main():
                          "profile of this command also holds the copy of known size")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(replicas and couplings would shard with no communication)", file=sys.stderr)
         sys.exit(2)
 

@@ -175,8 +175,12 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
             rec["acceptance"] = acc / max(prop, 1)
         out[name] = rec
     kp, lp = out["kennedy_pendleton"], out["learned_imh"]
+    plans = {0: (kp["pass_plan"]["tile_order"], kp["pass_plan"]["lds_bytes"]),
+             1: (lp["pass_plan"]["tile_order"], lp["pass_plan"]["lds_bytes"])}
+    scan = beta_scan(su2, dims, seed, plans)
     su2.su2_finalize()
     return {"workload": f"32^4 beta 2.3 hot seed 1, {sweeps} sweeps, heat-bath vs learned proposal",
+            "beta_scan": scan,
             "training": {"steps": train_steps, "alphas": 4096, "seconds": t_train, "table_rows": TABLE_ROWS,
                          "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
             **out,
@@ -185,6 +189,50 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
             # updates/s per integrated autocorrelation time of <P>: independent samples/s
             "effective_speed_ratio": (lp["link_updates_per_s"] / lp["tau_int_sweeps"])
                                      / (kp["link_updates_per_s"] / kp["tau_int_sweeps"])}
+
+
+SCAN_BETAS = (0.5, 1.0, 1.5, 2.0, 2.3, 2.8)
+
+
+def beta_scan(su2, dims, seed, plans, therm=20, sweeps=100):
+    """Both proposals over a range of couplings on the same lattice, each with
+    its launch plan: updates/s over `sweeps` sweeps after `therm` sweeps from
+    the hot start, heat-bath attempts and cap failures per update, and the
+    learned proposal's acceptance.  At small beta*|staple| the heat-bath's
+    rejection loop is long and a wavefront runs until its slowest lane has
+    accepted (or hit the cap of 8 attempts)."""
+    import numpy as np
+    import torch
+    V = int(np.prod(dims))
+    upd = 4 * V * sweeps
+    rows = []
+    for beta in SCAN_BETAS:
+        rec = {"beta": beta}
+        for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
+            su2.su2_init(dims, beta, seed, 1)
+            su2.su2_set_plan(*plans[kind])
+            su2.su2_set_proposal(kind)
+            su2.su2_sweep(therm)
+            a0, f0 = su2.su2_counters()
+            p0, c0 = su2.su2_imh_counters()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            su2.su2_sweep(sweeps)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            a1, f1 = su2.su2_counters()
+            r = {"link_updates_per_s": upd / dt, "plaquette": su2.su2_plaquette()}
+            if kind:
+                p1, c1 = su2.su2_imh_counters()
+                r["acceptance"] = (c1 - c0) / max(p1 - p0, 1)
+            else:
+                r["attempts_per_update"] = (a1 - a0) / upd
+                r["cap_failures_per_update"] = (f1 - f0) / upd
+            rec[name] = r
+        rec["speed_ratio"] = rec["learned_imh"]["link_updates_per_s"] / rec["kennedy_pendleton"]["link_updates_per_s"]
+        rows.append(rec)
+    return {"lattice": list(dims), "hot_start_seed": seed, "thermalisation_sweeps": therm,
+            "timed_sweeps": sweeps, "points": rows}
 
 
 def main():

@@ -139,12 +139,20 @@ int su2_set_stream(void *hip_stream);
  * 100 + T = the same with squares and planes walked back and forth;
  * 200 + T = four XCDs share each plane (bands twice as thick), XCDs 0-3 on
  * the planes with x2 < L2/2, walked as 100 + T;
+ * 300 = fused pairs: each parity's four passes run as two launches, U_0 then
+ * U_1 and U_2 then U_3, each workgroup taking a set of sites that the shift
+ * x -> x - mu + nu maps onto itself (an (x0, x1) plane, or an orbit of the
+ * (x2, x3) step (-1, +1) times one x0 row), so the second pass reads the
+ * first one's results from LDS (only for L0 <= 256, else SU2_EINVAL; the
+ * single-pass entry su2_pass is unaffected);
  * lds_bytes (0..65536) of local memory reserved per workgroup to cap the
- * workgroups resident on a compute unit.  Results are bit-identical for every
- * plan; only the speed changes. */
+ * workgroups resident on a compute unit.  Links and counters are
+ * bit-identical for every plan, only the speed changes; the plaquette of a
+ * measured sweep is summed in another order under plan 300 (rounding-level
+ * differences). */
 int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
 
-/* Time each plan in {order 0, 4, 8, 16, 108, 208} x {LDS 0, 16, 24, 32, 40 KiB} on a
+/* Time each plan in {order 0, 4, 8, 16, 108, 208, 300} x {LDS 0, 16, 24, 32, 40 KiB} on a
  * scratch copy of the links (reps measured sweeps each, in three rounds over
  * all plans; the lattice, sweep index and all counters are untouched) and
  * install the plan with the smallest median; out (nullable) receives

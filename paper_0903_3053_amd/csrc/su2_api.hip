@@ -37,6 +37,7 @@ struct Context {
     uint32_t n_waves = 0;
     double2 *d_partials = nullptr;      // per-workgroup partial sums of a measurement
     double2 *d_meas = nullptr;          // plaquette partials written by a measured sweep
+    size_t n_meas = 0;                  // ... room for that many
     double2 *d_scratch = nullptr;       // first-level reduction results
     double *d_out = nullptr;            // 3 doubles for scalar results
     bool meas_fresh = false;            // d_meas holds the plaquette of the current links
@@ -138,31 +139,29 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
     hipGraphNode_t prev = nullptr;
     int rc = SU2_OK;
     for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
-        // Sec. 2.4: odd sites for every direction, then even sites
-        for (int p = 1; p >= 0 && rc == SU2_OK; --p) {
-            for (int mu = 0; mu < 4; ++mu) {
-                const bool measure = measure_last && s == nsweeps - 1;
-                PassLaunch pl = pass_launch(ctx.links, ctx.g, ctx.key, (float)ctx.beta,
-                                            (uint32_t)p, (uint32_t)mu, ctx.d_sweep,
-                                            ctx.d_counters, measure ? ctx.d_meas : nullptr,
-                                            ctx.plan);
-                pl.bind();
-                hipKernelNodeParams kp{};
-                kp.func = const_cast<void *>(pl.func);
-                kp.gridDim = pl.grid;
-                kp.blockDim = pl.block;
-                kp.sharedMemBytes = pl.lds;
-                kp.kernelParams = pl.args;
-                kp.extra = nullptr;
-                hipGraphNode_t node;
-                hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr,
-                                                     prev ? 1 : 0, &kp);
-                if (e != hipSuccess) {
-                    rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
-                    break;
-                }
-                prev = node;
+        const bool measure = measure_last && s == nsweeps - 1;
+        // eight passes (Sec. 2.4: odd sites for every direction, then even
+        // sites), or four fused pairs of them
+        std::vector<PassLaunch> pls = sweep_launches(ctx.links, ctx.g, ctx.key, (float)ctx.beta,
+                                                     ctx.d_sweep, ctx.d_counters,
+                                                     measure ? ctx.d_meas : nullptr, ctx.plan);
+        for (PassLaunch &pl : pls) {
+            pl.bind();
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void *>(pl.func);
+            kp.gridDim = pl.grid;
+            kp.blockDim = pl.block;
+            kp.sharedMemBytes = pl.lds;
+            kp.kernelParams = pl.args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr,
+                                                 prev ? 1 : 0, &kp);
+            if (e != hipSuccess) {
+                rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+                break;
             }
+            prev = node;
         }
         if (rc != SU2_OK) break;
         uint32_t *sp = ctx.d_sweep;
@@ -190,7 +189,9 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
 int set_plan(int32_t kind, uint32_t lds)
 {
     std::vector<uint32_t> order;
-    if (!make_order(ctx.g, kind, order))
+    PairGeo pg01, pg23;
+    const bool fused = kind == kFusedPairs;
+    if (fused ? !make_pair_geo(ctx.g, ctx.n_waves, pg01, pg23) : !make_order(ctx.g, kind, order))
         return fail(SU2_EINVAL, "tile order %d does not fit this lattice", kind);
     if (lds > 65536u) return fail(SU2_EINVAL, "LDS reservation must be <= 65536 bytes");
     HIP_TRY(hipStreamSynchronize(ctx.stream));
@@ -198,7 +199,7 @@ int set_plan(int32_t kind, uint32_t lds)
         hipFree(ctx.d_order);
         ctx.d_order = nullptr;
     }
-    if (kind > 0) {
+    if (kind > 0 && !fused) {
         if (hipMalloc(&ctx.d_order, order.size() * sizeof(uint32_t)) != hipSuccess) {
             hipGetLastError();
             return fail(SU2_ENOMEM, "cannot allocate the tile order");
@@ -208,7 +209,11 @@ int set_plan(int32_t kind, uint32_t lds)
     }
     ctx.plan.order = ctx.d_order;
     ctx.plan.lds_bytes = lds;
+    ctx.plan.fused = fused;
+    ctx.plan.pg01 = pg01;
+    ctx.plan.pg23 = pg23;
     ctx.order_kind = kind;
+    ctx.meas_fresh = false;  // partials of a measured sweep are laid out per plan
     release_graphs();
     return SU2_OK;
 }
@@ -253,7 +258,8 @@ int run_sweeps(int32_t n, bool measured = false)
 hipError_t enqueue_plaquette(double *out)
 {
     if (ctx.meas_fresh)
-        return launch_measure_reduce(ctx.d_meas, ctx.g, ctx.d_scratch, out, ctx.stream);
+        return launch_measure_reduce(ctx.d_meas, meas_partials(ctx.g, ctx.plan), ctx.g,
+                                     ctx.d_scratch, out, ctx.stream);
     return launch_plaquette(ctx.links, ctx.g, ctx.d_partials, ctx.d_scratch, out, ctx.stream);
 }
 
@@ -283,7 +289,12 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
     ctx.key = Key{ (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
     ctx.n_waves = counter_waves(ctx.g);
     const uint32_t nb = std::max(plaquette_blocks(ctx.g), polyakov_blocks(ctx.g));
-    const size_t n_meas = (size_t)3 * pass_blocks(ctx.g);
+    // room for the plaquette partials of either sweep form
+    size_t n_meas = (size_t)3 * pass_blocks(ctx.g);
+    PairGeo pg01, pg23;
+    if (make_pair_geo(ctx.g, ctx.n_waves, pg01, pg23))
+        n_meas = std::max(n_meas, (size_t)pg01.n_wg + pg23.n_wg);
+    ctx.n_meas = n_meas;
     if (dev_links) {
         ctx.links = static_cast<float4 *>(dev_links);
         ctx.owns_links = false;
@@ -548,7 +559,7 @@ int su2_tune(int32_t reps, int32_t out[2])
     if (reps < 1) return fail(SU2_EINVAL, "reps must be >= 1");
     const size_t link_bytes = (size_t)ctx.V * 4 * sizeof(float4);
     const size_t ctr_bytes = (size_t)ctx.n_waves * 2 * sizeof(unsigned long long);
-    const size_t part_bytes = (size_t)3 * pass_blocks(ctx.g) * sizeof(double2);
+    const size_t part_bytes = ctx.n_meas * sizeof(double2);
     float4 *tl = nullptr;
     unsigned long long *tc = nullptr;
     double2 *tp = nullptr;
@@ -568,14 +579,17 @@ int su2_tune(int32_t reps, int32_t out[2])
     // measured sweeps (as su2_sweep_measured runs them) of a copy of the links,
     // in three rounds over all candidates; the median of its rounds ranks it,
     // so slow drifts of the clock or of the cache state do not pick the plan.
-    const int32_t kinds[] = { 0, 4, 8, 16, 108, 208 };
+    const int32_t kinds[] = { 0, 4, 8, 16, 108, 208, kFusedPairs };
     const uint32_t ldss[] = { 0u, 16384u, 24576u, 32768u, 40960u };
     constexpr int kRounds = 3;
     std::vector<int32_t> cand_kind;
     std::vector<uint32_t> cand_lds;
     for (int32_t kind : kinds) {
         std::vector<uint32_t> order;
-        if (!make_order(ctx.g, kind, order)) continue;
+        PairGeo pg01, pg23;
+        if (kind == kFusedPairs ? !make_pair_geo(ctx.g, ctx.n_waves, pg01, pg23)
+                                : !make_order(ctx.g, kind, order))
+            continue;
         for (uint32_t lds : ldss) {
             cand_kind.push_back(kind);
             cand_lds.push_back(lds);
@@ -594,14 +608,11 @@ int su2_tune(int32_t reps, int32_t out[2])
             ctx.plan.lds_bytes = cand_lds[c];
             for (int warm = 0; warm < 2 && e == hipSuccess; ++warm) {
                 if (warm == 1) e = hipEventRecord(e0, ctx.stream);
-                for (int32_t r = 0; r < (warm ? reps : 1) && e == hipSuccess; ++r)
-                    for (int p = 1; p >= 0 && e == hipSuccess; --p)
-                        for (uint32_t mu = 0; mu < 4 && e == hipSuccess; ++mu) {
-                            PassLaunch pl = pass_launch(tl, ctx.g, ctx.key, (float)ctx.beta,
-                                                        (uint32_t)p, mu, ctx.d_sweep, tc, tp,
-                                                        ctx.plan);
-                            e = launch(pl, ctx.stream);
-                        }
+                for (int32_t r = 0; r < (warm ? reps : 1) && e == hipSuccess; ++r) {
+                    std::vector<PassLaunch> pls = sweep_launches(tl, ctx.g, ctx.key, (float)ctx.beta,
+                                                                 ctx.d_sweep, tc, tp, ctx.plan);
+                    for (size_t i = 0; i < pls.size() && e == hipSuccess; ++i) e = launch(pls[i], ctx.stream);
+                }
             }
             if (e == hipSuccess) e = hipEventRecord(e1, ctx.stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);

@@ -5,6 +5,8 @@
 //                rotation, FP64-normed reunitarisation, store (Eqs. (5)-(7)).
 //                The paper's separate staple and update kernels and its staple
 //                buffer (Sec. 2.4) are fused: the staple stays in registers.
+//   k_pair       the passes of U_0 and U_1 (or U_2 and U_3) of one parity in
+//                one launch (su2_pair.hpp)
 //   k_tick       advances the device-resident sweep index (graph-friendly)
 //   k_plaquette  per-workgroup FP64 partial sums of spatial / temporal
 //                plaquettes (Sec. 2.4, Eq. (3))
@@ -13,6 +15,7 @@
 //   k_pack / k_unpack   device checkerboard layout <-> host [V][4][4]
 //   k_philox     raw generator blocks, for bit-exact checks
 #include <algorithm>
+#include <numeric>
 
 #include "su2_kernels.hpp"
 #include "su2_pass.hpp"
@@ -322,6 +325,91 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
     return pl;
 }
 
+bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo &pg23)
+{
+    if (g.L[0] > (uint32_t)kBlock) return false;  // both lags (2 H0 - 1 and H0) within one block
+    const uint32_t gc = std::gcd(g.L[2], g.L[3]);
+    pg01 = PairGeo{};
+    pg01.n_t = g.H0 * g.L[1];
+    pg01.n_wg = g.L[2] * g.L[3];
+    pg01.lag = 2u * g.H0 - 1u;
+    pg23 = PairGeo{};
+    pg23.orbit = g.L[2] / gc * g.L[3];
+    pg23.n_t = pg23.orbit * g.H0;
+    pg23.n_wg = gc * g.L[1];
+    pg23.lag = g.H0;
+    for (PairGeo *pg : { &pg01, &pg23 }) {
+        pg->nblk = (pg->n_t + kBlock - 1u) / kBlock;
+        pg->xcd_chunk = pg->n_wg % 8u == 0u ? pg->n_wg / 8u : 0u;
+        pg->counter_slots = counter_slots;
+        pg->dL3 = make_fastdiv(g.L[3]);
+    }
+    return true;
+}
+
+template <uint32_t MU, uint32_t NU, bool MEAS1, bool MEAS2>
+static const void *pair_func_4(bool off32, bool imh)
+{
+    if (imh)
+        return off32 ? reinterpret_cast<const void *>(&k_pair<MU, NU, true, MEAS1, MEAS2, true>)
+                     : reinterpret_cast<const void *>(&k_pair<MU, NU, false, MEAS1, MEAS2, true>);
+    return off32 ? reinterpret_cast<const void *>(&k_pair<MU, NU, true, MEAS1, MEAS2, false>)
+                 : reinterpret_cast<const void *>(&k_pair<MU, NU, false, MEAS1, MEAS2, false>);
+}
+
+// (0, 1) measures through its U_1 updates; (2, 3) through both passes
+static const void *pair_func(uint32_t mu, bool off32, bool measure, bool imh)
+{
+    if (mu == 0u)
+        return measure ? pair_func_4<0, 1, false, true>(off32, imh) : pair_func_4<0, 1, false, false>(off32, imh);
+    return measure ? pair_func_4<2, 3, true, true>(off32, imh) : pair_func_4<2, 3, false, false>(off32, imh);
+}
+
+uint32_t meas_partials(const Geo &g, const PassPlan &plan)
+{
+    return plan.fused ? plan.pg01.n_wg + plan.pg23.n_wg : 3u * pass_blocks(g);
+}
+
+std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, float beta,
+                                       const uint32_t *sweep_ptr, unsigned long long *counters,
+                                       double2 *meas_out, const PassPlan &plan)
+{
+    std::vector<PassLaunch> out;
+    // Sec. 2.4: odd sites for every direction, then even sites
+    for (int p = 1; p >= 0; --p) {
+        if (!plan.fused) {
+            for (uint32_t mu = 0; mu < 4; ++mu)
+                out.push_back(pass_launch(links, g, key, beta, (uint32_t)p, mu, sweep_ptr, counters,
+                                          meas_out, plan));
+            continue;
+        }
+        for (uint32_t mu = 0; mu < 4; mu += 2) {
+            const PairGeo &pg = mu == 0u ? plan.pg01 : plan.pg23;
+            const bool measure = meas_out != nullptr && p == 0;
+            PassLaunch pl;
+            pl.pair = true;
+            pl.pg = pg;
+            pl.lds = plan.learned ? std::max(plan.lds_bytes, plan.imh_lds_bytes) : plan.lds_bytes;
+            pl.order = nullptr;
+            pl.func = pair_func(mu, use_off32(g), measure, plan.learned);
+            pl.imh = plan.imh;
+            pl.grid = dim3(pg.n_wg);
+            pl.block = dim3(kBlock);
+            pl.links = links;
+            pl.g = g;
+            pl.key = key;
+            pl.beta = beta;
+            pl.p = (uint32_t)p;
+            pl.sweep_ptr = sweep_ptr;
+            pl.counters = counters;
+            pl.meas_out = measure ? meas_out + (mu == 0u ? 0u : plan.pg01.n_wg) : nullptr;
+            pl.bind();
+            out.push_back(pl);
+        }
+    }
+    return out;
+}
+
 hipError_t launch(PassLaunch &pl, hipStream_t st)
 {
     pl.bind();
@@ -365,12 +453,12 @@ hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials
     return reduce2(partials, nb, scratch, scale, scale, 0, out, st);
 }
 
-hipError_t launch_measure_reduce(const double2 *meas_partials, const Geo &g, double2 *scratch,
-                                 double *out, hipStream_t st)
+hipError_t launch_measure_reduce(const double2 *meas_partials, uint32_t n, const Geo &g,
+                                 double2 *scratch, double *out, hipStream_t st)
 {
-    // spatial planes from the mu = 1, 2 passes (x), temporal from mu = 3 (y)
+    // spatial planes from the mu = 1, 2 updates (x), temporal from mu = 3 (y)
     const double scale = 1.0 / (3.0 * 2.0 * (double)g.half);
-    return reduce2(meas_partials, 3u * pass_blocks(g), scratch, scale, scale, 0, out, st);
+    return reduce2(meas_partials, n, scratch, scale, scale, 0, out, st);
 }
 
 hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials,

@@ -3,6 +3,7 @@
 
 #include <vector>
 
+#include "su2_pair.hpp"
 #include "su2_pass.hpp"
 
 namespace su2 {
@@ -14,12 +15,15 @@ namespace su2 {
 struct PassPlan {
     const uint32_t *order = nullptr;
     uint32_t lds_bytes = 0;
+    bool fused = false;             // a sweep as four k_pair launches (U_0,U_1 and U_2,U_3 per parity)
+    PairGeo pg01, pg23;             // their workgroup sets (valid when fused)
     bool learned = false;           // learned proposal (imh) or heat-bath only
     ImhTable imh;                   // the learned proposal's table, passed by value
     uint32_t imh_lds_bytes = 0;     // LDS the learned-proposal pass stages its table in
 };
 
-// Arguments of one k_pass launch, kept together so a graph node can point at them.
+// Arguments of one k_pass or k_pair launch, kept together so a graph node can
+// point at them.
 struct PassLaunch {
     const void *func;
     dim3 grid, block;
@@ -34,10 +38,17 @@ struct PassLaunch {
     const uint32_t *order;
     ImhTable imh;
     uint32_t lds;
+    bool pair = false;
+    PairGeo pg;
     void *args[10];
     // point args at this object's own fields (call after every copy)
     void bind()
     {
+        if (pair) {
+            void *a[10] = { &links, &g, &pg, &key, &beta, &p, &sweep_ptr, &counters, &meas_out, &imh };
+            for (int i = 0; i < 10; ++i) args[i] = a[i];
+            return;
+        }
         args[0] = &links;
         args[1] = &g;
         args[2] = &key;
@@ -59,6 +70,18 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
                        const uint32_t *sweep_ptr, unsigned long long *counters,
                        double2 *meas_out, const PassPlan &plan);
 bool make_order(const Geo &g, int kind, std::vector<uint32_t> &order);
+// Tile order kind of the fused-pair sweep (k_pair with XCD-chunked workgroups).
+constexpr int kFusedPairs = 300;
+// The workgroup sets of the two k_pair launches of a parity; false if the
+// lattice does not fit them (L0 > 256).
+bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo &pg23);
+// The launches of one sweep in order (odd parity, then even): eight k_pass,
+// or four k_pair when plan.fused.  meas_out != nullptr: the even-parity
+// launches leave their plaquette partials in meas_out (meas_partials of them).
+std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, float beta,
+                                       const uint32_t *sweep_ptr, unsigned long long *counters,
+                                       double2 *meas_out, const PassPlan &plan);
+uint32_t meas_partials(const Geo &g, const PassPlan &plan);
 hipError_t launch(PassLaunch &pl, hipStream_t st);
 hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st);
 hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st);
@@ -70,8 +93,8 @@ uint32_t counter_waves(const Geo &g);
 uint32_t reduce_scratch();
 hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials,
                             double2 *scratch, double *out, hipStream_t st);
-hipError_t launch_measure_reduce(const double2 *meas_partials, const Geo &g, double2 *scratch,
-                                 double *out, hipStream_t st);
+hipError_t launch_measure_reduce(const double2 *meas_partials, uint32_t n, const Geo &g,
+                                 double2 *scratch, double *out, hipStream_t st);
 hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials,
                            double2 *scratch, double *out, hipStream_t st);
 hipError_t launch_pack(const float4 *links, const Geo &g, float4 *stage, hipStream_t st);

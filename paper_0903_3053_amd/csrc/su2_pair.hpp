@@ -1,0 +1,177 @@
+// su2_pair.hpp -- two consecutive passes of one parity in one launch: the
+// updates of U_MU and then of U_NU on the sites of parity p, (MU, NU) = (0, 1)
+// or (2, 3) (Sec. 2.4: within a parity the directions are updated in turn).
+//
+// Why this is exact and needs no grid-wide ordering.  The update of U_NU(x)
+// reads the freshly updated U_MU only at x and at y = x - MU + NU (both of
+// parity p: the forward and backward staples of the plane (NU, MU), Eq. (6));
+// every other link it reads is left alone by both passes.  The update of
+// U_MU(x') reads U_NU of parity p only at x' and x' + MU - NU.  So if each
+// workgroup takes a set T of parity-p sites that the shift x -> x - MU + NU
+// maps onto itself, a workgroup reads U_MU and U_NU of parity p only inside
+// its own T, and other workgroups write only outside it: the workgroup can
+// run the U_MU updates of T, keep their results in LDS, and run the U_NU
+// updates of T from them, while other workgroups do the same elsewhere.  Every
+// update sees exactly the links it sees in the two separate passes, with the
+// same Philox counter, so the links come out bit for bit the same.
+//
+//   (0, 1): T = the parity-p sites of one (x0, x1) plane (fixed x2, x3);
+//           position pos = x1 * H0 + x0 / 2, a contiguous range of half indices.
+//   (2, 3): T = the parity-p sites with fixed x1 and (x2, x3) on one orbit of
+//           the step (-1, +1): points t = 0 .. lcm(L2, L3) - 1 at
+//           (x2, x3) = (-t mod L2, (o + t) mod L3), o < gcd(L2, L3); position
+//           pos = t * H0 + x0 / 2, whole x0 rows of 16-byte links.
+//
+// Within a workgroup the second pass trails the first by `lag` positions (the
+// largest forward distance from x to y in position order), so both read
+// nearly the same links at nearly the same time: the second pass's neighbour
+// reads hit the cache lines the first one just fetched.  LDS keeps the first
+// pass's results for the current and the previous block of positions, and
+// for block 0 (the y of the last positions wrap around to it).
+#pragma once
+
+#include "su2_pass.hpp"
+
+namespace su2 {
+
+struct PairGeo {
+    uint32_t n_t = 0;         // sites (positions) per workgroup
+    uint32_t n_wg = 0;        // workgroups
+    uint32_t lag = 0;         // positions by which the NU pass trails the MU pass
+    uint32_t nblk = 0;        // blocks of kBlock positions of the MU pass
+    uint32_t orbit = 0;       // (2, 3): orbit length lcm(L2, L3)
+    uint32_t xcd_chunk = 0;   // != 0: workgroup w takes T number (w % 8) * xcd_chunk + w / 8
+    uint32_t counter_slots = 0;
+    FastDiv dL3;
+};
+
+// Half index and site of position pos of the set T number j.
+template <uint32_t MU>
+__device__ __forceinline__ uint32_t pair_site(const Geo &g, const PairGeo &pg, uint32_t j,
+                                              uint32_t p, uint32_t pos, Site &x)
+{
+    if constexpr (MU == 0u) {
+        const uint32_t h = j * (g.H0 * g.L[1]) + pos;
+        x = site_of(g, h, p);
+        return h;
+    } else {
+        const uint32_t o = fdiv(j, g.dL1);
+        const uint32_t x1 = j - o * g.L[1];
+        const uint32_t t = fdiv(pos, g.dH0);
+        const uint32_t h0 = pos - t * g.H0;
+        const uint32_t t2 = t - fdiv(t, g.dL2) * g.L[2];
+        const uint32_t ot = o + t;
+        x.x[1] = x1;
+        x.x[2] = t2 == 0u ? 0u : g.L[2] - t2;
+        x.x[3] = ot - fdiv(ot, pg.dL3) * g.L[3];
+        x.x[0] = 2u * h0 + ((p + x1 + x.x[2] + x.x[3]) & 1u);
+        return h0 + x1 * g.st[1] + x.x[2] * g.st[2] + x.x[3] * g.st[3];
+    }
+}
+
+// Position of y = x - MU + NU for the site x at position pos (half index h).
+template <uint32_t MU>
+__device__ __forceinline__ uint32_t pair_shift(const Geo &g, const PairGeo &pg, uint32_t j,
+                                               uint32_t pos, uint32_t h, const Site &x)
+{
+    if constexpr (MU == 0u) {
+        return h_minus<0>(g, h_plus<1>(g, h, x.x[1]), x.x[0]) - j * (g.H0 * g.L[1]);
+    } else {
+        const uint32_t t = fdiv(pos, g.dH0);
+        return t + 1u == pg.orbit ? pos - t * g.H0 : pos + g.H0;
+    }
+}
+
+// The staple links of U_NU(x) in the plane (NU, MU) whose U_MU(x) (a) and
+// U_MU(x + NU - MU) (f) come from the first pass; the other four from memory.
+template <uint32_t NU, uint32_t MU, bool OFF32>
+__device__ __forceinline__ StapleLinks gather_fresh(const float4 *L, const Geo &g, uint32_t p,
+                                                    uint32_t h, uint32_t h_pn, const Site &x,
+                                                    float4 a, float4 f)
+{
+    const uint32_t q = p ^ 1u;
+    const uint32_t h_pm = h_plus<MU>(g, h, x.x[MU]);
+    const uint32_t h_mm = h_minus<MU>(g, h, x.x[MU]);
+    const float4 *Lmq = L + arr(g, MU, q), *Lnq = L + arr(g, NU, q);
+    StapleLinks s;
+    s.a = a;                          // U_MU(x)
+    s.b = ld4<OFF32>(Lnq, h_pm);      // U_NU(x+MU)
+    s.c = ld4<OFF32>(Lmq, h_pn);      // U_MU(x+NU)
+    s.d = ld4<OFF32>(Lmq, h_mm);      // U_MU(x-MU)
+    s.e = ld4<OFF32>(Lnq, h_mm);      // U_NU(x-MU)
+    s.f = f;                          // U_MU(x+NU-MU)
+    return s;
+}
+
+template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS1, bool MEAS2, bool IMH>
+__global__ __launch_bounds__(kBlock) void k_pair(
+    float4 *__restrict__ L, Geo g, PairGeo pg, Key key, float beta, uint32_t p,
+    const uint32_t *__restrict__ sweep_ptr, unsigned long long *__restrict__ counters,
+    double2 *__restrict__ meas_out, ImhTable imh)
+{
+    static_assert((MU == 0u && NU == 1u) || (MU == 2u && NU == 3u), "pairs (0,1) and (2,3)");
+    __shared__ float4 ring[2][kBlock];  // MU-pass results of blocks b - 1 and b
+    __shared__ float4 first[kBlock];    // ... and of block 0
+    const uint32_t w = blockIdx.x;
+    const uint32_t j = pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w;
+    const uint32_t s = *sweep_ptr;
+    const uint32_t slot = (w * (kBlock / kWave) + threadIdx.x / kWave) % pg.counter_slots;
+    if constexpr (IMH) {
+        stage_table(imh);
+        __syncthreads();  // (the first barrier below would do as well)
+    }
+    double acc_s = 0.0, acc_t = 0.0;
+    for (uint32_t b = 0; b <= pg.nblk; ++b) {
+        // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
+        if (b < pg.nblk) {
+            const uint32_t pos = b * kBlock + threadIdx.x;
+            const bool valid = pos < pg.n_t;
+            Site x;
+            const uint32_t h = pair_site<MU>(g, pg, j, p, valid ? pos : 0u, x);
+            const TileStaples in = staples_of(load_site<MU, OFF32, IMH>(L, g, p, h, x));
+            double m = 0.0;
+            const float4 un = update_link<MU, OFF32, MEAS1, IMH, true>(L, g, key, beta, p, s, h, valid,
+                                                                       slot, in, counters, imh, m);
+            acc_s += m;  // MU = 2: spatial planes (0, 2), (1, 2)
+            ring[b & 1u][threadIdx.x] = un;
+            if (b == 0u) first[threadIdx.x] = un;
+        }
+        __syncthreads();
+        // the NU pass on positions [b * kBlock - lag, (b + 1) * kBlock - lag)
+        {
+            const int ipos = (int)(b * kBlock + threadIdx.x) - (int)pg.lag;
+            const bool valid = ipos >= 0 && (uint32_t)ipos < pg.n_t;
+            const uint32_t pos = valid ? (uint32_t)ipos : 0u;
+            Site x;
+            const uint32_t h = pair_site<MU>(g, pg, j, p, pos, x);
+            const uint32_t posy = pair_shift<MU>(g, pg, j, pos, h, x);
+            auto fresh = [&](uint32_t q) {
+                const uint32_t blk = q / kBlock;
+                return (blk == b || blk + 1u == b) ? ring[blk & 1u][q % kBlock] : first[q % kBlock];
+            };
+            const float4 a = fresh(pos), f = fresh(posy);
+            constexpr uint32_t N0 = other_dir<NU, 0>(), N1 = other_dir<NU, 1>(), N2 = other_dir<NU, 2>();
+            const uint32_t h_pn = h_plus<NU>(g, h, x.x[NU]);
+            TileLoad t;
+            t.lex = 2u * h + (x.x[0] & 1u);
+            if constexpr (N0 == MU) t.s0 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
+            else t.s0 = gather<NU, N0, OFF32>(L, g, p, h, h_pn, x);
+            if constexpr (N1 == MU) t.s1 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
+            else t.s1 = gather<NU, N1, OFF32>(L, g, p, h, h_pn, x);
+            if constexpr (N2 == MU) t.s2 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
+            else t.s2 = gather<NU, N2, OFF32>(L, g, p, h, h_pn, x);
+            t.uold = IMH ? ld4<OFF32>(L + arr(g, NU, p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
+            double m = 0.0;
+            update_link<NU, OFF32, MEAS2, IMH, false>(L, g, key, beta, p, s, h, valid, slot,
+                                                      staples_of(t), counters, imh, m);
+            if (NU == 3u) acc_t += m; else acc_s += m;
+        }
+        __syncthreads();  // before the next block's MU results replace block b - 1
+    }
+    if constexpr (MEAS1 || MEAS2) {
+        const double2 r = block_sum2(acc_s, acc_t);
+        if (threadIdx.x == 0) meas_out[w] = r;
+    }
+}
+
+}  // namespace su2

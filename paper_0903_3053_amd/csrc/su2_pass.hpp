@@ -177,14 +177,13 @@ struct TileLoad {
     uint32_t lex;
 };
 
+// The loads of the update of U_MU(x) at the site x of parity p with half index
+// hh (any lane may call it with a valid site).
 template <uint32_t MU, bool OFF32, bool IMH>
-__device__ __forceinline__ TileLoad load_tile(const float4 *__restrict__ L, const Geo &g, uint32_t p,
-                                              uint32_t tile)
+__device__ __forceinline__ TileLoad load_site(const float4 *__restrict__ L, const Geo &g, uint32_t p,
+                                              uint32_t hh, const Site &x)
 {
     constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
-    const uint32_t h = tile * kBlock + threadIdx.x;
-    const uint32_t hh = h < g.half ? h : 0u;
-    const Site x = site_of(g, hh, p);
     const uint32_t h_pm = h_plus<MU>(g, hh, x.x[MU]);
     TileLoad t;
     t.lex = 2u * hh + (x.x[0] & 1u);  // L0 = 2*H0, so lex = 2h + (x0 mod 2)
@@ -195,6 +194,15 @@ __device__ __forceinline__ TileLoad load_tile(const float4 *__restrict__ L, cons
     // the gathers
     t.uold = IMH ? ld4<OFF32>(L + arr(g, MU, p), hh) : make_float4(0.f, 0.f, 0.f, 0.f);
     return t;
+}
+
+template <uint32_t MU, bool OFF32, bool IMH>
+__device__ __forceinline__ TileLoad load_tile(const float4 *__restrict__ L, const Geo &g, uint32_t p,
+                                              uint32_t tile)
+{
+    const uint32_t h = tile * kBlock + threadIdx.x;
+    const uint32_t hh = h < g.half ? h : 0u;
+    return load_site<MU, OFF32, IMH>(L, g, p, hh, site_of(g, hh, p));
 }
 
 // Learned proposal: every workgroup copies the first kImhLdsVec4 float4 of the
@@ -230,25 +238,27 @@ __device__ __forceinline__ TileStaples staples_of(const TileLoad &in)
     return t;
 }
 
-// The updates of one tile (256 half-sites) of a heat-bath pass over the links
-// U_MU(x), parity(x) = p, at sweep index s, from the staples in `in`.  With
-// MEASURE (even passes MU >= 1 of a measured sweep), each lane also adds
-// dot(U_new, staple_nu) for nu < MU: over the three even passes this counts
-// every plaquette of the final configuration exactly once (planes (nu, MU),
-// nu < MU), so the plaquette of the sweep's result comes out of the sweep
-// itself.  meas_out receives one FP64 partial per tile.
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH>
-__device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g, Key key,
-                                            float beta, uint32_t p, uint32_t s, uint32_t tile,
-                                            const TileStaples &in,
-                                            unsigned long long *__restrict__ counters,
-                                            double2 *__restrict__ meas_out, const ImhTable &imh)
+// The update of one link U_MU(x), parity(x) = p, half index h, at sweep index
+// s, from the staples in `in`, by every lane of a wave (lanes with !valid take
+// part in the wave-wide steps only); counter_slot names the wave's pair of
+// counters.  Returns the link's value after the update when KEEP is set (a
+// lane whose heat-bath hit the cap re-reads its unchanged link).  With MEASURE
+// (even passes MU >= 1 of a measured sweep), meas receives dot(U_new,
+// staple_nu) summed over nu < MU: over the three even passes this counts every
+// plaquette of the final configuration exactly once (planes (nu, MU), nu < MU),
+// so the plaquette of the sweep's result comes out of the sweep itself.  With
+// IMH the caller has made the staged knot table visible (a barrier).
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool KEEP>
+__device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo &g, Key key,
+                                              float beta, uint32_t p, uint32_t s, uint32_t h,
+                                              bool valid, uint32_t counter_slot,
+                                              const TileStaples &in,
+                                              unsigned long long *__restrict__ counters,
+                                              const ImhTable &imh, double &meas)
 {
     // every operation rounds as written, whatever kernel inlines this
 #pragma clang fp contract(off)
     constexpr uint32_t N0 = other_dir<MU, 0>(), N1 = other_dir<MU, 1>(), N2 = other_dir<MU, 2>();
-    const uint32_t h = tile * kBlock + threadIdx.x;
-    const bool valid = h < g.half;
     const uint32_t lex = in.lex;
     float4 *Lout = L + arr(g, MU, p);
     [[maybe_unused]] const float4 uold = in.uold;
@@ -288,7 +298,6 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
     if constexpr (IMH) {
         bool rejected = false;
         const bool staged = imh.G <= kImhLdsRows;
-        __syncthreads();  // the staged table is complete
         if (imh_lane) {
             const float tpos = alpha * imh.inv_step;
             const uint32_t g0 = min((uint32_t)tpos, imh.G - 2u);
@@ -320,9 +329,8 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
         const unsigned long long nprop = __popcll(__ballot(imh_lane));
         const unsigned long long nacc = __popcll(__ballot(imh_lane && !rejected));
         if ((threadIdx.x & (kWave - 1)) == 0 && nprop != 0ull) {
-            const uint32_t wave = h / kWave;
-            atomicAdd(&imh.stats[2 * wave], nprop);
-            atomicAdd(&imh.stats[2 * wave + 1], nacc);
+            atomicAdd(&imh.stats[2 * counter_slot], nprop);
+            atomicAdd(&imh.stats[2 * counter_slot + 1], nacc);
         }
     }
     if (valid && !failed && !imh_lane) {
@@ -355,20 +363,41 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
     // each wave owns its two counters; the adds return nothing, so the wave
     // does not wait on a read-modify-write before it retires
     if ((threadIdx.x & (kWave - 1)) == 0 && attempts != 0ull) {
-        const uint32_t wave = h / kWave;
-        atomicAdd(&counters[2 * wave], attempts);
-        if (failures != 0ull) atomicAdd(&counters[2 * wave + 1], failures);
+        atomicAdd(&counters[2 * counter_slot], attempts);
+        if (failures != 0ull) atomicAdd(&counters[2 * counter_slot + 1], failures);
+    }
+    if constexpr (MEASURE || KEEP) {
+        if (failed) un = ld4<OFF32>(Lout, h);  // the link kept its value
     }
     if constexpr (MEASURE) {
-        if (failed) un = ld4<OFF32>(Lout, h);  // the link kept its value
         double acc = 0.0;
         if (valid) {
             if (N0 < MU) acc += (double)qdot(un, w0);
             if (N1 < MU) acc += (double)qdot(un, w1);
             if (N2 < MU) acc += (double)qdot(un, w2);
         }
+        meas = acc;
+    }
+    return un;
+}
+
+// The updates of one tile (256 half-sites) of a pass; meas_out receives the
+// tile's FP64 plaquette partial (spatial planes, MU = 1, 2, in .x; temporal
+// planes, MU = 3, in .y).
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH>
+__device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g, Key key,
+                                            float beta, uint32_t p, uint32_t s, uint32_t tile,
+                                            const TileStaples &in,
+                                            unsigned long long *__restrict__ counters,
+                                            double2 *__restrict__ meas_out, const ImhTable &imh)
+{
+    const uint32_t h = tile * kBlock + threadIdx.x;
+    if constexpr (IMH) __syncthreads();  // the staged table is complete
+    double acc = 0.0;
+    update_link<MU, OFF32, MEASURE, IMH, false>(L, g, key, beta, p, s, h, h < g.half, h / kWave, in,
+                                                counters, imh, acc);
+    if constexpr (MEASURE) {
         const double2 r = block_sum2(acc, 0.0);
-        // spatial planes (MU = 1, 2) in .x, temporal planes (MU = 3) in .y
         if (threadIdx.x == 0)
             meas_out[tile] = MU == 3u ? make_double2(0.0, r.x) : make_double2(r.x, 0.0);
     }

@@ -16,6 +16,7 @@ LIBPATH = os.path.join(HERE, "libsu2.so")
 
 SU2_OK, SU2_EINVAL, SU2_ESTATE, SU2_ENOMEM, SU2_EDEVICE = 0, -1, -2, -3, -4
 COLD, HOT = 0, 1
+FUSED_PAIRS = 300  # su2_set_plan order kind: each parity as two fused launches
 
 # every symbol include/su2.h declares
 EXPORTS = (

@@ -135,13 +135,14 @@ def test_imh_pass_parity(lib, dims, points):
 
 def test_learned_sweeps_identical_across_plans(lib):
     """The learned pass gives bit-identical links and proposal counts for every
-    launch plan, with the table read from LDS (31 rows) or global memory (64)."""
+    launch plan (fused pairs included), with the table read from LDS (31 rows)
+    or global memory (64)."""
     lib.su2_mlp_set_params(su2_inputs.mlp_init(5))
     dims = (64, 64, 8, 8)
     for points in (31, 64):
         lib.su2_mlp_tabulate(points)
         ref = None
-        for plan in [(0, 0), (8, 16384), (4, 40960)]:
+        for plan in [(0, 0), (8, 16384), (4, 40960), (lib.FUSED_PAIRS, 0)]:
             lib.su2_init(dims, 2.3, 4, lib.HOT)
             lib.su2_set_plan(*plan)
             lib.su2_set_proposal(1)

@@ -172,6 +172,70 @@ def test_full_size_64x64x64x64_sweep(lib):
     assert unitarity_error(gpu) <= UNIT_TOL
 
 
+FUSED_SHAPES = [(8, 6, 10, 4), (2, 4, 2, 6), (4, 4, 4, 4), (2, 2, 2, 2), (6, 4, 10, 8), (12, 12, 12, 12),
+                (16, 16, 16, 16), (32, 8, 6, 10)]
+
+
+@pytest.mark.parametrize("dims", FUSED_SHAPES)
+def test_fused_pairs_bit_identical(lib, dims):
+    """The fused-pair sweep (U_0 with U_1, U_2 with U_3 of each parity in one
+    launch) against the eight separate passes from the same hot start: links
+    and heat-bath counters bit-identical after three sweeps (the last
+    measured), the in-sweep plaquette to 1e-13 (the same terms summed per
+    workgroup of the fused launches).  Shapes include ragged extents, L2 != L3
+    (orbits of the (x2, x3) step shorter than L2 L3) and sets of fewer sites
+    than a workgroup has lanes."""
+    beta, seed = 2.2, 9
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    lib.su2_sweep(2)
+    m_ref = lib.su2_sweep_measure(1, 1)
+    ref, c_ref = lib.su2_links(), lib.su2_counters()
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    lib.su2_set_plan(lib.FUSED_PAIRS, 0)
+    lib.su2_sweep(2)
+    m = lib.su2_sweep_measure(1, 1)
+    assert np.array_equal(lib.su2_links(), ref)
+    assert lib.su2_counters() == c_ref
+    np.testing.assert_allclose(m, m_ref, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(lib.su2_plaquette_st(), m[0], rtol=0, atol=2e-6)
+
+
+def test_fused_pairs_against_oracle(lib):
+    """One fused-pair sweep of the 8x6x10x4 lattice against the oracle's sweep
+    from the same hot start (<= 1e-5, the per-sweep bar), and the plan's
+    geometry limit (L0 <= 256)."""
+    dims, beta, seed = (8, 6, 10, 4), 2.3, 3
+    U = oracle.init(dims, seed, oracle.HOT)
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    lib.su2_set_plan(lib.FUSED_PAIRS, 0)
+    lib.su2_sweep(1)
+    att_o, fail_o = oracle.sweep(dims, U, beta, seed, 0)
+    gpu = lib.su2_links()
+    err = float(np.max(np.abs(gpu - U)))
+    print(f"fused-pair sweep {dims} vs oracle: max |dU| {err:.1e}")
+    assert err <= 1e-5
+    assert lib.su2_counters() == (att_o, fail_o)
+    lib.su2_init((258, 2, 2, 2), beta, seed, lib.HOT)
+    with pytest.raises(lib.Su2Error):
+        lib.su2_set_plan(lib.FUSED_PAIRS, 0)
+
+
+def test_fused_pairs_full_size_64x64x64x64(lib):
+    """The fused-pair sweep at 64^4 (beta 2.4, hot start seed 1): one measured
+    sweep leaves every link bit-identical to the benchmark plan's sweep."""
+    dims, beta, seed = (64, 64, 64, 64), 2.4, 1
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    lib.su2_set_plan(108, 32768)
+    h_ref = lib.su2_sweep_measure(1, 1)
+    ref, c_ref = lib.su2_links(), lib.su2_counters()
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    lib.su2_set_plan(lib.FUSED_PAIRS, 0)
+    h = lib.su2_sweep_measure(1, 1)
+    assert lib.su2_counters() == c_ref
+    assert np.array_equal(lib.su2_links(), ref)
+    np.testing.assert_allclose(h, h_ref, rtol=0, atol=1e-13)
+
+
 def test_trajectory_4x4_cold(lib):
     """Free-running 100 sweeps of the 4^4 beta = 2.3 cold workload (seed 1),
     GPU and oracle from the same start with the same random numbers.  Rounding
@@ -349,19 +413,23 @@ def test_launch_plans_bit_identical(lib):
     m_ref = lib.su2_sweep_measure(1, 1)
     ref = lib.su2_links()
     c_ref = lib.su2_counters()
-    for kind, lds in [(0, 0), (4, 0), (8, 32768), (4, 40960), (0, 16384), (108, 0), (104, 24576), (204, 0)]:
+    for kind, lds in [(0, 0), (4, 0), (8, 32768), (4, 40960), (0, 16384), (108, 0), (104, 24576), (204, 0),
+                      (lib.FUSED_PAIRS, 0), (lib.FUSED_PAIRS, 24576)]:
         lib.su2_init(dims, 2.3, 5, lib.HOT)
         lib.su2_set_plan(kind, lds)
         lib.su2_sweep(2)
         m = lib.su2_sweep_measure(1, 1)
         assert np.array_equal(lib.su2_links(), ref), (kind, lds)
-        assert np.array_equal(m, m_ref), (kind, lds)
+        if kind == lib.FUSED_PAIRS:  # the same terms, summed per workgroup of the fused launches
+            np.testing.assert_allclose(m, m_ref, rtol=0, atol=1e-13)
+        else:
+            assert np.array_equal(m, m_ref), (kind, lds)
         assert lib.su2_counters() == c_ref
     lib.su2_init(dims, 2.3, 5, lib.HOT)
     lib.su2_sweep(1)
     before = lib.su2_links()
     plan = lib.su2_tune(1)
-    assert plan[0] in (0, 4, 8, 16, 108, 208)
+    assert plan[0] in (0, 4, 8, 16, 108, 208, lib.FUSED_PAIRS)
     assert np.array_equal(lib.su2_links(), before)
     assert lib.su2_sweep_index() == 1
     lib.su2_sweep(2)

@@ -340,6 +340,7 @@ bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo 
     pg23.lag = g.H0;
     for (PairGeo *pg : { &pg01, &pg23 }) {
         pg->nblk = (pg->n_t + kBlock - 1u) / kBlock;
+        if (pg->n_t <= 3u * kBlock) pg->lag = 0u;  // the whole set stays in LDS
         pg->xcd_chunk = pg->n_wg % 8u == 0u ? pg->n_wg / 8u : 0u;
         pg->counter_slots = counter_slots;
         pg->dL3 = make_fastdiv(g.L[3]);

@@ -22,12 +22,13 @@
 //           (x2, x3) = (-t mod L2, (o + t) mod L3), o < gcd(L2, L3); position
 //           pos = t * H0 + x0 / 2, whole x0 rows of 16-byte links.
 //
-// Within a workgroup the second pass trails the first by `lag` positions (the
-// largest forward distance from x to y in position order), so both read
-// nearly the same links at nearly the same time: the second pass's neighbour
-// reads hit the cache lines the first one just fetched.  LDS keeps the first
-// pass's results for the current and the previous block of positions, and
-// for block 0 (the y of the last positions wrap around to it).
+// When T has at most 3 * 256 sites, LDS holds all of the first pass's
+// results: the workgroup runs every U_MU update, then every U_NU update.
+// Larger sets go block by block, the second pass trailing the first by `lag`
+// positions (the largest forward distance from x to y in position order), so
+// both read nearly the same links at nearly the same time; LDS then keeps the
+// first pass's results for the current and the previous block of positions,
+// and for block 0 (the y of the last positions wrap around to it).
 #pragma once
 
 #include "su2_pass.hpp"
@@ -37,7 +38,7 @@ namespace su2 {
 struct PairGeo {
     uint32_t n_t = 0;         // sites (positions) per workgroup
     uint32_t n_wg = 0;        // workgroups
-    uint32_t lag = 0;         // positions by which the NU pass trails the MU pass
+    uint32_t lag = 0;         // positions by which the NU pass trails the MU pass (0: whole set in LDS)
     uint32_t nblk = 0;        // blocks of kBlock positions of the MU pass
     uint32_t orbit = 0;       // (2, 3): orbit length lcm(L2, L3)
     uint32_t xcd_chunk = 0;   // != 0: workgroup w takes T number (w % 8) * xcd_chunk + w / 8
@@ -110,8 +111,9 @@ __global__ __launch_bounds__(kBlock) void k_pair(
     double2 *__restrict__ meas_out, ImhTable imh)
 {
     static_assert((MU == 0u && NU == 1u) || (MU == 2u && NU == 3u), "pairs (0,1) and (2,3)");
-    __shared__ float4 ring[2][kBlock];  // MU-pass results of blocks b - 1 and b
-    __shared__ float4 first[kBlock];    // ... and of block 0
+    // MU-pass results: with lag, blocks b - 1 and b in buf[0 .. 2 kBlock) and
+    // block 0 in buf[2 kBlock .. 3 kBlock); without lag, the whole set
+    __shared__ float4 buf[3 * kBlock];
     const uint32_t w = blockIdx.x;
     const uint32_t j = pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w;
     const uint32_t s = *sweep_ptr;
@@ -121,52 +123,74 @@ __global__ __launch_bounds__(kBlock) void k_pair(
         __syncthreads();  // (the first barrier below would do as well)
     }
     double acc_s = 0.0, acc_t = 0.0;
-    for (uint32_t b = 0; b <= pg.nblk; ++b) {
-        // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
-        if (b < pg.nblk) {
+    // the U_MU update at position pos (lanes with !valid join the wave-wide steps)
+    auto update1 = [&](uint32_t pos, bool valid) {
+        Site x;
+        const uint32_t h = pair_site<MU>(g, pg, j, p, valid ? pos : 0u, x);
+        const TileStaples in = staples_of(load_site<MU, OFF32, IMH>(L, g, p, h, x));
+        double m = 0.0;
+        const float4 un = update_link<MU, OFF32, MEAS1, IMH, true>(L, g, key, beta, p, s, h, valid,
+                                                                   slot, in, counters, imh, m);
+        acc_s += m;  // MU = 2: spatial planes (0, 2), (1, 2)
+        return un;
+    };
+    // the U_NU update at position pos; fresh(q) is the new U_MU at position q
+    auto update2 = [&](uint32_t pos, bool valid, auto fresh) {
+        Site x;
+        const uint32_t h = pair_site<MU>(g, pg, j, p, pos, x);
+        const uint32_t posy = pair_shift<MU>(g, pg, j, pos, h, x);
+        const float4 a = fresh(pos), f = fresh(posy);
+        constexpr uint32_t N0 = other_dir<NU, 0>(), N1 = other_dir<NU, 1>(), N2 = other_dir<NU, 2>();
+        const uint32_t h_pn = h_plus<NU>(g, h, x.x[NU]);
+        TileLoad t;
+        t.lex = 2u * h + (x.x[0] & 1u);
+        if constexpr (N0 == MU) t.s0 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
+        else t.s0 = gather<NU, N0, OFF32>(L, g, p, h, h_pn, x);
+        if constexpr (N1 == MU) t.s1 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
+        else t.s1 = gather<NU, N1, OFF32>(L, g, p, h, h_pn, x);
+        if constexpr (N2 == MU) t.s2 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
+        else t.s2 = gather<NU, N2, OFF32>(L, g, p, h, h_pn, x);
+        t.uold = IMH ? ld4<OFF32>(L + arr(g, NU, p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
+        double m = 0.0;
+        update_link<NU, OFF32, MEAS2, IMH, false>(L, g, key, beta, p, s, h, valid, slot,
+                                                  staples_of(t), counters, imh, m);
+        if (NU == 3u) acc_t += m; else acc_s += m;
+    };
+    if (pg.lag == 0u) {
+        // the set fits in LDS (n_t <= 3 kBlock): every U_MU update, one
+        // barrier, every U_NU update
+        for (uint32_t b = 0; b < pg.nblk; ++b) {
             const uint32_t pos = b * kBlock + threadIdx.x;
             const bool valid = pos < pg.n_t;
-            Site x;
-            const uint32_t h = pair_site<MU>(g, pg, j, p, valid ? pos : 0u, x);
-            const TileStaples in = staples_of(load_site<MU, OFF32, IMH>(L, g, p, h, x));
-            double m = 0.0;
-            const float4 un = update_link<MU, OFF32, MEAS1, IMH, true>(L, g, key, beta, p, s, h, valid,
-                                                                       slot, in, counters, imh, m);
-            acc_s += m;  // MU = 2: spatial planes (0, 2), (1, 2)
-            ring[b & 1u][threadIdx.x] = un;
-            if (b == 0u) first[threadIdx.x] = un;
+            const float4 un = update1(pos, valid);
+            if (valid) buf[pos] = un;
         }
         __syncthreads();
-        // the NU pass on positions [b * kBlock - lag, (b + 1) * kBlock - lag)
-        {
+        for (uint32_t b = 0; b < pg.nblk; ++b) {
+            const uint32_t pos = b * kBlock + threadIdx.x;
+            const bool valid = pos < pg.n_t;
+            update2(valid ? pos : 0u, valid, [&](uint32_t q) { return buf[q]; });
+        }
+    } else {
+        for (uint32_t b = 0; b <= pg.nblk; ++b) {
+            // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
+            if (b < pg.nblk) {
+                const uint32_t pos = b * kBlock + threadIdx.x;
+                const float4 un = update1(pos, pos < pg.n_t);
+                buf[(b & 1u) * kBlock + threadIdx.x] = un;
+                if (b == 0u) buf[2u * kBlock + threadIdx.x] = un;
+            }
+            __syncthreads();
+            // the NU pass on positions [b * kBlock - lag, (b + 1) * kBlock - lag)
             const int ipos = (int)(b * kBlock + threadIdx.x) - (int)pg.lag;
             const bool valid = ipos >= 0 && (uint32_t)ipos < pg.n_t;
-            const uint32_t pos = valid ? (uint32_t)ipos : 0u;
-            Site x;
-            const uint32_t h = pair_site<MU>(g, pg, j, p, pos, x);
-            const uint32_t posy = pair_shift<MU>(g, pg, j, pos, h, x);
-            auto fresh = [&](uint32_t q) {
+            update2(valid ? (uint32_t)ipos : 0u, valid, [&](uint32_t q) {
                 const uint32_t blk = q / kBlock;
-                return (blk == b || blk + 1u == b) ? ring[blk & 1u][q % kBlock] : first[q % kBlock];
-            };
-            const float4 a = fresh(pos), f = fresh(posy);
-            constexpr uint32_t N0 = other_dir<NU, 0>(), N1 = other_dir<NU, 1>(), N2 = other_dir<NU, 2>();
-            const uint32_t h_pn = h_plus<NU>(g, h, x.x[NU]);
-            TileLoad t;
-            t.lex = 2u * h + (x.x[0] & 1u);
-            if constexpr (N0 == MU) t.s0 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
-            else t.s0 = gather<NU, N0, OFF32>(L, g, p, h, h_pn, x);
-            if constexpr (N1 == MU) t.s1 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
-            else t.s1 = gather<NU, N1, OFF32>(L, g, p, h, h_pn, x);
-            if constexpr (N2 == MU) t.s2 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
-            else t.s2 = gather<NU, N2, OFF32>(L, g, p, h, h_pn, x);
-            t.uold = IMH ? ld4<OFF32>(L + arr(g, NU, p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
-            double m = 0.0;
-            update_link<NU, OFF32, MEAS2, IMH, false>(L, g, key, beta, p, s, h, valid, slot,
-                                                      staples_of(t), counters, imh, m);
-            if (NU == 3u) acc_t += m; else acc_s += m;
+                return buf[(blk == b || blk + 1u == b) ? (blk & 1u) * kBlock + q % kBlock
+                                                       : 2u * kBlock + q % kBlock];
+            });
+            __syncthreads();  // before the next block's MU results replace block b - 1
         }
-        __syncthreads();  // before the next block's MU results replace block b - 1
     }
     if constexpr (MEAS1 || MEAS2) {
         const double2 r = block_sum2(acc_s, acc_t);

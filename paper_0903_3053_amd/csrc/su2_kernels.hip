@@ -340,7 +340,6 @@ bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo 
     pg23.lag = g.H0;
     for (PairGeo *pg : { &pg01, &pg23 }) {
         pg->nblk = (pg->n_t + kBlock - 1u) / kBlock;
-        if (pg->n_t <= 3u * kBlock) pg->lag = 0u;  // the whole set stays in LDS
         pg->xcd_chunk = pg->n_wg % 8u == 0u ? pg->n_wg / 8u : 0u;
         pg->counter_slots = counter_slots;
         pg->dL3 = make_fastdiv(g.L[3]);
@@ -348,22 +347,31 @@ bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo 
     return true;
 }
 
+template <uint32_t MU, uint32_t NU, bool MEAS1, bool MEAS2, bool OFF32, bool IMH>
+static const void *pair_func_6(bool small)
+{
+    return small ? reinterpret_cast<const void *>(&k_pair_small<MU, NU, OFF32, MEAS1, MEAS2, IMH>)
+                 : reinterpret_cast<const void *>(&k_pair<MU, NU, OFF32, MEAS1, MEAS2, IMH>);
+}
+
 template <uint32_t MU, uint32_t NU, bool MEAS1, bool MEAS2>
-static const void *pair_func_4(bool off32, bool imh)
+static const void *pair_func_4(bool off32, bool imh, bool small)
 {
     if (imh)
-        return off32 ? reinterpret_cast<const void *>(&k_pair<MU, NU, true, MEAS1, MEAS2, true>)
-                     : reinterpret_cast<const void *>(&k_pair<MU, NU, false, MEAS1, MEAS2, true>);
-    return off32 ? reinterpret_cast<const void *>(&k_pair<MU, NU, true, MEAS1, MEAS2, false>)
-                 : reinterpret_cast<const void *>(&k_pair<MU, NU, false, MEAS1, MEAS2, false>);
+        return off32 ? pair_func_6<MU, NU, MEAS1, MEAS2, true, true>(small)
+                     : pair_func_6<MU, NU, MEAS1, MEAS2, false, true>(small);
+    return off32 ? pair_func_6<MU, NU, MEAS1, MEAS2, true, false>(small)
+                 : pair_func_6<MU, NU, MEAS1, MEAS2, false, false>(small);
 }
 
 // (0, 1) measures through its U_1 updates; (2, 3) through both passes
-static const void *pair_func(uint32_t mu, bool off32, bool measure, bool imh)
+static const void *pair_func(uint32_t mu, bool off32, bool measure, bool imh, bool small)
 {
     if (mu == 0u)
-        return measure ? pair_func_4<0, 1, false, true>(off32, imh) : pair_func_4<0, 1, false, false>(off32, imh);
-    return measure ? pair_func_4<2, 3, true, true>(off32, imh) : pair_func_4<2, 3, false, false>(off32, imh);
+        return measure ? pair_func_4<0, 1, false, true>(off32, imh, small)
+                       : pair_func_4<0, 1, false, false>(off32, imh, small);
+    return measure ? pair_func_4<2, 3, true, true>(off32, imh, small)
+                   : pair_func_4<2, 3, false, false>(off32, imh, small);
 }
 
 uint32_t meas_partials(const Geo &g, const PassPlan &plan)
@@ -392,10 +400,11 @@ std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, flo
             pl.pg = pg;
             pl.lds = plan.learned ? std::max(plan.lds_bytes, plan.imh_lds_bytes) : plan.lds_bytes;
             pl.order = nullptr;
-            pl.func = pair_func(mu, use_off32(g), measure, plan.learned);
+            const bool small = pg.n_t <= kPairLanes;
+            pl.func = pair_func(mu, use_off32(g), measure, plan.learned, small);
             pl.imh = plan.imh;
             pl.grid = dim3(pg.n_wg);
-            pl.block = dim3(kBlock);
+            pl.block = dim3(small ? (pg.n_t + kWave - 1u) / kWave * kWave : kBlock);
             pl.links = links;
             pl.g = g;
             pl.key = key;

@@ -22,13 +22,14 @@
 //           (x2, x3) = (-t mod L2, (o + t) mod L3), o < gcd(L2, L3); position
 //           pos = t * H0 + x0 / 2, whole x0 rows of 16-byte links.
 //
-// When T has at most 3 * 256 sites, LDS holds all of the first pass's
-// results: the workgroup runs every U_MU update, then every U_NU update.
-// Larger sets go block by block, the second pass trailing the first by `lag`
-// positions (the largest forward distance from x to y in position order), so
-// both read nearly the same links at nearly the same time; LDS then keeps the
-// first pass's results for the current and the previous block of positions,
-// and for block 0 (the y of the last positions wrap around to it).
+// A set of at most 1024 sites gets one lane per site (k_pair_small): every
+// U_MU update, one barrier, every U_NU update, the first pass's results in
+// LDS.  Larger sets go block by block with 256 lanes (k_pair), the second pass
+// trailing the first by `lag` positions (the largest forward distance from x
+// to y in position order), so both read nearly the same links at nearly the
+// same time; LDS then keeps the first pass's results for the current and the
+// previous block of positions, and for block 0 (the y of the last positions
+// wrap around to it).
 #pragma once
 
 #include "su2_pass.hpp"
@@ -38,7 +39,7 @@ namespace su2 {
 struct PairGeo {
     uint32_t n_t = 0;         // sites (positions) per workgroup
     uint32_t n_wg = 0;        // workgroups
-    uint32_t lag = 0;         // positions by which the NU pass trails the MU pass (0: whole set in LDS)
+    uint32_t lag = 0;         // positions by which the NU pass trails the MU pass
     uint32_t nblk = 0;        // blocks of kBlock positions of the MU pass
     uint32_t orbit = 0;       // (2, 3): orbit length lcm(L2, L3)
     uint32_t xcd_chunk = 0;   // != 0: workgroup w takes T number (w % 8) * xcd_chunk + w / 8
@@ -104,6 +105,137 @@ __device__ __forceinline__ StapleLinks gather_fresh(const float4 *L, const Geo &
     return s;
 }
 
+// Arguments every pair kernel passes to the per-site updates.
+struct PairCtx {
+    float4 *L;
+    Geo g;
+    PairGeo pg;
+    Key key;
+    float beta;
+    uint32_t p, s, j, slot;
+    unsigned long long *counters;
+    ImhTable imh;
+};
+
+// The U_MU update at position pos (lanes with !valid join the wave-wide steps);
+// returns the new link and adds the plaquette terms it measures to acc_s.
+template <uint32_t MU, bool OFF32, bool MEAS, bool IMH>
+__device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, bool valid, double &acc_s)
+{
+    Site x;
+    const uint32_t h = pair_site<MU>(c.g, c.pg, c.j, c.p, valid ? pos : 0u, x);
+    const TileStaples in = staples_of(load_site<MU, OFF32, IMH>(c.L, c.g, c.p, h, x));
+    double m = 0.0;
+    const float4 un = update_link<MU, OFF32, MEAS, IMH, true>(c.L, c.g, c.key, c.beta, c.p, c.s, h, valid,
+                                                              c.slot, in, c.counters, c.imh, m);
+    acc_s += m;  // MU = 2: spatial planes (0, 2), (1, 2)
+    return un;
+}
+
+// The U_NU update at position pos; fresh(q) is the new U_MU at position q.
+template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS, bool IMH, typename Fresh>
+__device__ __forceinline__ void pair_update2(const PairCtx &c, uint32_t pos, bool valid, Fresh fresh,
+                                             double &acc_s, double &acc_t)
+{
+    const Geo &g = c.g;
+    Site x;
+    const uint32_t h = pair_site<MU>(g, c.pg, c.j, c.p, pos, x);
+    const uint32_t posy = pair_shift<MU>(g, c.pg, c.j, pos, h, x);
+    const float4 a = fresh(pos), f = fresh(posy);
+    constexpr uint32_t N0 = other_dir<NU, 0>(), N1 = other_dir<NU, 1>(), N2 = other_dir<NU, 2>();
+    const uint32_t h_pn = h_plus<NU>(g, h, x.x[NU]);
+    TileLoad t;
+    t.lex = 2u * h + (x.x[0] & 1u);
+    if constexpr (N0 == MU) t.s0 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
+    else t.s0 = gather<NU, N0, OFF32>(c.L, g, c.p, h, h_pn, x);
+    if constexpr (N1 == MU) t.s1 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
+    else t.s1 = gather<NU, N1, OFF32>(c.L, g, c.p, h, h_pn, x);
+    if constexpr (N2 == MU) t.s2 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
+    else t.s2 = gather<NU, N2, OFF32>(c.L, g, c.p, h, h_pn, x);
+    t.uold = IMH ? ld4<OFF32>(c.L + arr(g, NU, c.p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
+    double m = 0.0;
+    update_link<NU, OFF32, MEAS, IMH, false>(c.L, g, c.key, c.beta, c.p, c.s, h, valid, c.slot,
+                                             staples_of(t), c.counters, c.imh, m);
+    if (NU == 3u) acc_t += m; else acc_s += m;
+}
+
+// FP64 sum of two values over a workgroup of any multiple of 64 threads (at
+// most 1024): wave butterflies, then the waves in order.
+__device__ __forceinline__ double2 block_sum2_any(double a, double b)
+{
+    __shared__ double sh[2][16];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off);
+        b += __shfl_xor(b, off);
+    }
+    const uint32_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        sh[0][wv] = a;
+        sh[1][wv] = b;
+    }
+    __syncthreads();
+    double2 r = make_double2(0.0, 0.0);
+    if (threadIdx.x == 0) {
+        for (uint32_t i = 0; i < nw; ++i) {
+            r.x += sh[0][i];
+            r.y += sh[1][i];
+        }
+    }
+    return r;
+}
+
+// The learned proposal's knot table copied into LDS by a workgroup of any
+// multiple of 64 threads: the same kImhLdsVec4 float4 as stage_table, wave v
+// copying the 64-float4 chunks v, v + waves, ...
+__device__ __forceinline__ void stage_table_any(const ImhTable &imh)
+{
+    extern __shared__ float4 imh_lds[];
+    const uint32_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave, lane = threadIdx.x % kWave;
+    for (uint32_t c = wv; c < kImhLdsVec4 / kWave; c += nw)
+        __builtin_amdgcn_global_load_lds(
+            (const __attribute__((address_space(1))) void *)(reinterpret_cast<const float4 *>(imh.knots) +
+                                                             c * kWave + lane),
+            (__attribute__((address_space(3))) void *)(imh_lds + c * kWave), 16u, 0, 0);
+}
+
+// Sets of at most kPairLanes sites: one lane per site (the launch has
+// n_t rounded up to a multiple of 64 threads), so each pass is one phase --
+// every U_MU update, one barrier, every U_NU update.
+constexpr uint32_t kPairLanes = 1024;
+
+template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS1, bool MEAS2, bool IMH>
+__global__ __launch_bounds__(kPairLanes) void k_pair_small(
+    float4 *__restrict__ L, Geo g, PairGeo pg, Key key, float beta, uint32_t p,
+    const uint32_t *__restrict__ sweep_ptr, unsigned long long *__restrict__ counters,
+    double2 *__restrict__ meas_out, ImhTable imh)
+{
+    static_assert((MU == 0u && NU == 1u) || (MU == 2u && NU == 3u), "pairs (0,1) and (2,3)");
+    __shared__ float4 buf[kPairLanes];  // the new U_MU of the set
+    const uint32_t w = blockIdx.x;
+    const PairCtx c{ L, g, pg, key, beta, p, *sweep_ptr,
+                     pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w,
+                     (w * (blockDim.x / kWave) + threadIdx.x / kWave) % pg.counter_slots, counters, imh };
+    if constexpr (IMH) {
+        stage_table_any(imh);
+        __syncthreads();
+    }
+    double acc_s = 0.0, acc_t = 0.0;
+    const uint32_t pos = threadIdx.x;
+    const bool valid = pos < pg.n_t;
+    const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, valid, acc_s);
+    if (valid) buf[pos] = un;
+    __syncthreads();
+    pair_update2<MU, NU, OFF32, MEAS2, IMH>(c, valid ? pos : 0u, valid,
+                                            [&](uint32_t q) { return buf[q]; }, acc_s, acc_t);
+    if constexpr (MEAS1 || MEAS2) {
+        const double2 r = block_sum2_any(acc_s, acc_t);
+        if (threadIdx.x == 0) meas_out[w] = r;
+    }
+}
+
+// Larger sets, block by block with 256 threads: the U_NU updates trail the
+// U_MU updates by `lag` positions.
 template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS1, bool MEAS2, bool IMH>
 __global__ __launch_bounds__(kBlock) void k_pair(
     float4 *__restrict__ L, Geo g, PairGeo pg, Key key, float beta, uint32_t p,
@@ -111,86 +243,36 @@ __global__ __launch_bounds__(kBlock) void k_pair(
     double2 *__restrict__ meas_out, ImhTable imh)
 {
     static_assert((MU == 0u && NU == 1u) || (MU == 2u && NU == 3u), "pairs (0,1) and (2,3)");
-    // MU-pass results: with lag, blocks b - 1 and b in buf[0 .. 2 kBlock) and
-    // block 0 in buf[2 kBlock .. 3 kBlock); without lag, the whole set
+    // MU-pass results: blocks b - 1 and b in buf[0 .. 2 kBlock), block 0 in
+    // buf[2 kBlock .. 3 kBlock)
     __shared__ float4 buf[3 * kBlock];
     const uint32_t w = blockIdx.x;
-    const uint32_t j = pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w;
-    const uint32_t s = *sweep_ptr;
-    const uint32_t slot = (w * (kBlock / kWave) + threadIdx.x / kWave) % pg.counter_slots;
+    const PairCtx c{ L, g, pg, key, beta, p, *sweep_ptr,
+                     pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w,
+                     (w * (kBlock / kWave) + threadIdx.x / kWave) % pg.counter_slots, counters, imh };
     if constexpr (IMH) {
         stage_table(imh);
-        __syncthreads();  // (the first barrier below would do as well)
+        __syncthreads();
     }
     double acc_s = 0.0, acc_t = 0.0;
-    // the U_MU update at position pos (lanes with !valid join the wave-wide steps)
-    auto update1 = [&](uint32_t pos, bool valid) {
-        Site x;
-        const uint32_t h = pair_site<MU>(g, pg, j, p, valid ? pos : 0u, x);
-        const TileStaples in = staples_of(load_site<MU, OFF32, IMH>(L, g, p, h, x));
-        double m = 0.0;
-        const float4 un = update_link<MU, OFF32, MEAS1, IMH, true>(L, g, key, beta, p, s, h, valid,
-                                                                   slot, in, counters, imh, m);
-        acc_s += m;  // MU = 2: spatial planes (0, 2), (1, 2)
-        return un;
-    };
-    // the U_NU update at position pos; fresh(q) is the new U_MU at position q
-    auto update2 = [&](uint32_t pos, bool valid, auto fresh) {
-        Site x;
-        const uint32_t h = pair_site<MU>(g, pg, j, p, pos, x);
-        const uint32_t posy = pair_shift<MU>(g, pg, j, pos, h, x);
-        const float4 a = fresh(pos), f = fresh(posy);
-        constexpr uint32_t N0 = other_dir<NU, 0>(), N1 = other_dir<NU, 1>(), N2 = other_dir<NU, 2>();
-        const uint32_t h_pn = h_plus<NU>(g, h, x.x[NU]);
-        TileLoad t;
-        t.lex = 2u * h + (x.x[0] & 1u);
-        if constexpr (N0 == MU) t.s0 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
-        else t.s0 = gather<NU, N0, OFF32>(L, g, p, h, h_pn, x);
-        if constexpr (N1 == MU) t.s1 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
-        else t.s1 = gather<NU, N1, OFF32>(L, g, p, h, h_pn, x);
-        if constexpr (N2 == MU) t.s2 = gather_fresh<NU, MU, OFF32>(L, g, p, h, h_pn, x, a, f);
-        else t.s2 = gather<NU, N2, OFF32>(L, g, p, h, h_pn, x);
-        t.uold = IMH ? ld4<OFF32>(L + arr(g, NU, p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
-        double m = 0.0;
-        update_link<NU, OFF32, MEAS2, IMH, false>(L, g, key, beta, p, s, h, valid, slot,
-                                                  staples_of(t), counters, imh, m);
-        if (NU == 3u) acc_t += m; else acc_s += m;
-    };
-    if (pg.lag == 0u) {
-        // the set fits in LDS (n_t <= 3 kBlock): every U_MU update, one
-        // barrier, every U_NU update
-        for (uint32_t b = 0; b < pg.nblk; ++b) {
+    for (uint32_t b = 0; b <= pg.nblk; ++b) {
+        // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
+        if (b < pg.nblk) {
             const uint32_t pos = b * kBlock + threadIdx.x;
-            const bool valid = pos < pg.n_t;
-            const float4 un = update1(pos, valid);
-            if (valid) buf[pos] = un;
+            const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, pos < pg.n_t, acc_s);
+            buf[(b & 1u) * kBlock + threadIdx.x] = un;
+            if (b == 0u) buf[2u * kBlock + threadIdx.x] = un;
         }
         __syncthreads();
-        for (uint32_t b = 0; b < pg.nblk; ++b) {
-            const uint32_t pos = b * kBlock + threadIdx.x;
-            const bool valid = pos < pg.n_t;
-            update2(valid ? pos : 0u, valid, [&](uint32_t q) { return buf[q]; });
-        }
-    } else {
-        for (uint32_t b = 0; b <= pg.nblk; ++b) {
-            // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
-            if (b < pg.nblk) {
-                const uint32_t pos = b * kBlock + threadIdx.x;
-                const float4 un = update1(pos, pos < pg.n_t);
-                buf[(b & 1u) * kBlock + threadIdx.x] = un;
-                if (b == 0u) buf[2u * kBlock + threadIdx.x] = un;
-            }
-            __syncthreads();
-            // the NU pass on positions [b * kBlock - lag, (b + 1) * kBlock - lag)
-            const int ipos = (int)(b * kBlock + threadIdx.x) - (int)pg.lag;
-            const bool valid = ipos >= 0 && (uint32_t)ipos < pg.n_t;
-            update2(valid ? (uint32_t)ipos : 0u, valid, [&](uint32_t q) {
-                const uint32_t blk = q / kBlock;
-                return buf[(blk == b || blk + 1u == b) ? (blk & 1u) * kBlock + q % kBlock
-                                                       : 2u * kBlock + q % kBlock];
-            });
-            __syncthreads();  // before the next block's MU results replace block b - 1
-        }
+        // the NU pass on positions [b * kBlock - lag, (b + 1) * kBlock - lag)
+        const int ipos = (int)(b * kBlock + threadIdx.x) - (int)pg.lag;
+        const bool valid = ipos >= 0 && (uint32_t)ipos < pg.n_t;
+        pair_update2<MU, NU, OFF32, MEAS2, IMH>(c, valid ? (uint32_t)ipos : 0u, valid, [&](uint32_t q) {
+            const uint32_t blk = q / kBlock;
+            return buf[(blk == b || blk + 1u == b) ? (blk & 1u) * kBlock + q % kBlock
+                                                   : 2u * kBlock + q % kBlock];
+        }, acc_s, acc_t);
+        __syncthreads();  // before the next block's MU results replace block b - 1
     }
     if constexpr (MEAS1 || MEAS2) {
         const double2 r = block_sum2(acc_s, acc_t);

@@ -119,12 +119,17 @@ struct PairCtx {
 
 // The U_MU update at position pos (lanes with !valid join the wave-wide steps);
 // returns the new link and adds the plaquette terms it measures to acc_s.
-template <uint32_t MU, bool OFF32, bool MEAS, bool IMH>
-__device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, bool valid, double &acc_s)
+// before_update(), called by every lane once the update's loads are issued,
+// may stage the knot table and wait for it (the loads stay in flight).
+template <uint32_t MU, bool OFF32, bool MEAS, bool IMH, typename Hook>
+__device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, bool valid, double &acc_s,
+                                               Hook before_update)
 {
     Site x;
     const uint32_t h = pair_site<MU>(c.g, c.pg, c.j, c.p, valid ? pos : 0u, x);
-    const TileStaples in = staples_of(load_site<MU, OFF32, IMH>(c.L, c.g, c.p, h, x));
+    const TileLoad ld = load_site<MU, OFF32, IMH>(c.L, c.g, c.p, h, x);
+    before_update();
+    const TileStaples in = staples_of(ld);
     double m = 0.0;
     const float4 un = update_link<MU, OFF32, MEAS, IMH, true>(c.L, c.g, c.key, c.beta, c.p, c.s, h, valid,
                                                               c.slot, in, c.counters, c.imh, m);
@@ -216,14 +221,16 @@ __global__ __launch_bounds__(kPairLanes) void k_pair_small(
     const PairCtx c{ L, g, pg, key, beta, p, *sweep_ptr,
                      pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w,
                      (w * (blockDim.x / kWave) + threadIdx.x / kWave) % pg.counter_slots, counters, imh };
-    if constexpr (IMH) {
-        stage_table_any(imh);
-        __syncthreads();
-    }
     double acc_s = 0.0, acc_t = 0.0;
     const uint32_t pos = threadIdx.x;
     const bool valid = pos < pg.n_t;
-    const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, valid, acc_s);
+    // the knot table's copy goes out behind the first pass's loads
+    const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, valid, acc_s, [&] {
+        if constexpr (IMH) {
+            stage_table_any(imh);
+            __syncthreads();
+        }
+    });
     if (valid) buf[pos] = un;
     __syncthreads();
     pair_update2<MU, NU, OFF32, MEAS2, IMH>(c, valid ? pos : 0u, valid,
@@ -250,16 +257,20 @@ __global__ __launch_bounds__(kBlock) void k_pair(
     const PairCtx c{ L, g, pg, key, beta, p, *sweep_ptr,
                      pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w,
                      (w * (kBlock / kWave) + threadIdx.x / kWave) % pg.counter_slots, counters, imh };
-    if constexpr (IMH) {
-        stage_table(imh);
-        __syncthreads();
-    }
     double acc_s = 0.0, acc_t = 0.0;
     for (uint32_t b = 0; b <= pg.nblk; ++b) {
         // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
         if (b < pg.nblk) {
             const uint32_t pos = b * kBlock + threadIdx.x;
-            const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, pos < pg.n_t, acc_s);
+            // block 0: the knot table's copy goes out behind its loads
+            const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, pos < pg.n_t, acc_s, [&] {
+                if constexpr (IMH) {
+                    if (b == 0u) {
+                        stage_table(imh);
+                        __syncthreads();
+                    }
+                }
+            });
             buf[(b & 1u) * kBlock + threadIdx.x] = un;
             if (b == 0u) buf[2u * kBlock + threadIdx.x] = un;
         }

@@ -117,17 +117,55 @@ struct PairCtx {
     ImhTable imh;
 };
 
+// Links the U_MU update at x loads that the U_NU update at the same x reads
+// again (one lane per site): U_rho(x) and U_rho(x - rho) for the two other
+// directions rho, U_NU(x + MU), U_MU(x + NU), and U_NU(x) (not yet updated).
+struct PairCarry {
+    float4 ra[2], rd[2];
+    float4 nu_pm, mu_pn, nu_old;
+};
+
+// slot of the direction RHO (not MU, NU) in PairCarry: the smaller one first
+template <uint32_t MU, uint32_t NU, uint32_t RHO>
+constexpr int rho_slot()
+{
+    return RHO == (MU == 0u ? 2u : 0u) ? 0 : 1;
+}
+
+template <uint32_t MU, uint32_t NU, uint32_t NUI>
+__device__ __forceinline__ void carry_plane(const StapleLinks &sl, PairCarry &cr)
+{
+    if constexpr (NUI == NU) {
+        cr.nu_old = sl.a;
+        cr.mu_pn = sl.b;
+        cr.nu_pm = sl.c;
+    } else {
+        cr.ra[rho_slot<MU, NU, NUI>()] = sl.a;
+        cr.rd[rho_slot<MU, NU, NUI>()] = sl.d;
+    }
+}
+
+template <uint32_t MU, uint32_t NU>
+__device__ __forceinline__ void carry_of(const TileLoad &ld, PairCarry &cr)
+{
+    carry_plane<MU, NU, other_dir<MU, 0>()>(ld.s0, cr);
+    carry_plane<MU, NU, other_dir<MU, 1>()>(ld.s1, cr);
+    carry_plane<MU, NU, other_dir<MU, 2>()>(ld.s2, cr);
+}
+
 // The U_MU update at position pos (lanes with !valid join the wave-wide steps);
 // returns the new link and adds the plaquette terms it measures to acc_s.
 // before_update(), called by every lane once the update's loads are issued,
 // may stage the knot table and wait for it (the loads stay in flight).
-template <uint32_t MU, bool OFF32, bool MEAS, bool IMH, typename Hook>
+template <uint32_t MU, bool OFF32, bool MEAS, bool IMH, bool CARRY, typename Hook>
 __device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, bool valid, double &acc_s,
-                                               Hook before_update)
+                                               Hook before_update, PairCarry &carry)
 {
+    constexpr uint32_t NU = MU + 1u;
     Site x;
     const uint32_t h = pair_site<MU>(c.g, c.pg, c.j, c.p, valid ? pos : 0u, x);
     const TileLoad ld = load_site<MU, OFF32, IMH>(c.L, c.g, c.p, h, x);
+    if constexpr (CARRY) carry_of<MU, NU>(ld, carry);
     before_update();
     const TileStaples in = staples_of(ld);
     double m = 0.0;
@@ -137,10 +175,59 @@ __device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, b
     return un;
 }
 
-// The U_NU update at position pos; fresh(q) is the new U_MU at position q.
-template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS, bool IMH, typename Fresh>
+// The staple links of U_NU(x) in the plane (NU, RHO) when U_RHO(x) (a) and
+// U_RHO(x - RHO) (d) are at hand; the other four from memory.
+template <uint32_t NU, uint32_t RHO, bool OFF32>
+__device__ __forceinline__ StapleLinks gather_carried(const float4 *L, const Geo &g, uint32_t p,
+                                                      uint32_t h, uint32_t h_pn, const Site &x,
+                                                      float4 a, float4 d)
+{
+    const uint32_t q = p ^ 1u;
+    const uint32_t h_pr = h_plus<RHO>(g, h, x.x[RHO]);
+    const uint32_t h_mr = h_minus<RHO>(g, h, x.x[RHO]);
+    const uint32_t h_pn_mr = h_minus<RHO>(g, h_pn, x.x[RHO]);  // x+NU has the same x_RHO
+    const float4 *Lrp = L + arr(g, RHO, p), *Lrq = L + arr(g, RHO, q), *Lnq = L + arr(g, NU, q);
+    StapleLinks s;
+    s.a = a;                             // U_RHO(x)
+    s.b = ld4<OFF32>(Lnq, h_pr);         // U_NU(x+RHO)
+    s.c = ld4<OFF32>(Lrq, h_pn);         // U_RHO(x+NU)
+    s.d = d;                             // U_RHO(x-RHO)
+    s.e = ld4<OFF32>(Lnq, h_mr);         // U_NU(x-RHO)
+    s.f = ld4<OFF32>(Lrp, h_pn_mr);      // U_RHO(x+NU-RHO)
+    return s;
+}
+
+// The staple links of U_NU(x) in the plane (NU, RHO) with the carried links
+// in place of loads (RHO = MU: the plane of the fresh U_MU).
+template <uint32_t MU, uint32_t NU, uint32_t RHO, bool OFF32>
+__device__ __forceinline__ StapleLinks plane_carried(const PairCtx &c, uint32_t h, uint32_t h_pn,
+                                                     const Site &x, float4 a, float4 f,
+                                                     const PairCarry &cr)
+{
+    if constexpr (RHO == MU) {
+        // as gather_fresh, with U_NU(x+MU) and U_MU(x+NU) carried
+        const uint32_t h_mm = h_minus<MU>(c.g, h, x.x[MU]);
+        const uint32_t q = c.p ^ 1u;
+        StapleLinks sl;
+        sl.a = a;                                          // U_MU(x)
+        sl.b = cr.nu_pm;                                   // U_NU(x+MU)
+        sl.c = cr.mu_pn;                                   // U_MU(x+NU)
+        sl.d = ld4<OFF32>(c.L + arr(c.g, MU, q), h_mm);    // U_MU(x-MU)
+        sl.e = ld4<OFF32>(c.L + arr(c.g, NU, q), h_mm);    // U_NU(x-MU)
+        sl.f = f;                                          // U_MU(x+NU-MU)
+        return sl;
+    } else {
+        return gather_carried<NU, RHO, OFF32>(c.L, c.g, c.p, h, h_pn, x, cr.ra[rho_slot<MU, NU, RHO>()],
+                                              cr.rd[rho_slot<MU, NU, RHO>()]);
+    }
+}
+
+// The U_NU update at position pos; fresh(q) is the new U_MU at position q;
+// carry (one lane per site) holds the links the U_MU update at pos loaded
+// that this one reads again.
+template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS, bool IMH, bool CARRY, typename Fresh>
 __device__ __forceinline__ void pair_update2(const PairCtx &c, uint32_t pos, bool valid, Fresh fresh,
-                                             double &acc_s, double &acc_t)
+                                             double &acc_s, double &acc_t, const PairCarry &carry)
 {
     const Geo &g = c.g;
     Site x;
@@ -151,13 +238,20 @@ __device__ __forceinline__ void pair_update2(const PairCtx &c, uint32_t pos, boo
     const uint32_t h_pn = h_plus<NU>(g, h, x.x[NU]);
     TileLoad t;
     t.lex = 2u * h + (x.x[0] & 1u);
-    if constexpr (N0 == MU) t.s0 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
-    else t.s0 = gather<NU, N0, OFF32>(c.L, g, c.p, h, h_pn, x);
-    if constexpr (N1 == MU) t.s1 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
-    else t.s1 = gather<NU, N1, OFF32>(c.L, g, c.p, h, h_pn, x);
-    if constexpr (N2 == MU) t.s2 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
-    else t.s2 = gather<NU, N2, OFF32>(c.L, g, c.p, h, h_pn, x);
-    t.uold = IMH ? ld4<OFF32>(c.L + arr(g, NU, c.p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (CARRY) {
+        t.s0 = plane_carried<MU, NU, N0, OFF32>(c, h, h_pn, x, a, f, carry);
+        t.s1 = plane_carried<MU, NU, N1, OFF32>(c, h, h_pn, x, a, f, carry);
+        t.s2 = plane_carried<MU, NU, N2, OFF32>(c, h, h_pn, x, a, f, carry);
+        t.uold = IMH ? carry.nu_old : make_float4(0.f, 0.f, 0.f, 0.f);
+    } else {
+        if constexpr (N0 == MU) t.s0 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
+        else t.s0 = gather<NU, N0, OFF32>(c.L, g, c.p, h, h_pn, x);
+        if constexpr (N1 == MU) t.s1 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
+        else t.s1 = gather<NU, N1, OFF32>(c.L, g, c.p, h, h_pn, x);
+        if constexpr (N2 == MU) t.s2 = gather_fresh<NU, MU, OFF32>(c.L, g, c.p, h, h_pn, x, a, f);
+        else t.s2 = gather<NU, N2, OFF32>(c.L, g, c.p, h, h_pn, x);
+        t.uold = IMH ? ld4<OFF32>(c.L + arr(g, NU, c.p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
     double m = 0.0;
     update_link<NU, OFF32, MEAS, IMH, false>(c.L, g, c.key, c.beta, c.p, c.s, h, valid, c.slot,
                                              staples_of(t), c.counters, c.imh, m);
@@ -224,17 +318,19 @@ __global__ __launch_bounds__(kPairLanes) void k_pair_small(
     double acc_s = 0.0, acc_t = 0.0;
     const uint32_t pos = threadIdx.x;
     const bool valid = pos < pg.n_t;
-    // the knot table's copy goes out behind the first pass's loads
-    const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, valid, acc_s, [&] {
+    // the knot table's copy goes out behind the first pass's loads; the links
+    // both updates of a site read stay in registers
+    PairCarry carry;
+    const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, true>(c, pos, valid, acc_s, [&] {
         if constexpr (IMH) {
             stage_table_any(imh);
             __syncthreads();
         }
-    });
+    }, carry);
     if (valid) buf[pos] = un;
     __syncthreads();
-    pair_update2<MU, NU, OFF32, MEAS2, IMH>(c, valid ? pos : 0u, valid,
-                                            [&](uint32_t q) { return buf[q]; }, acc_s, acc_t);
+    pair_update2<MU, NU, OFF32, MEAS2, IMH, true>(c, valid ? pos : 0u, valid,
+                                                  [&](uint32_t q) { return buf[q]; }, acc_s, acc_t, carry);
     if constexpr (MEAS1 || MEAS2) {
         const double2 r = block_sum2_any(acc_s, acc_t);
         if (threadIdx.x == 0) meas_out[w] = r;
@@ -258,19 +354,20 @@ __global__ __launch_bounds__(kBlock) void k_pair(
                      pg.xcd_chunk ? (w % 8u) * pg.xcd_chunk + w / 8u : w,
                      (w * (kBlock / kWave) + threadIdx.x / kWave) % pg.counter_slots, counters, imh };
     double acc_s = 0.0, acc_t = 0.0;
+    PairCarry unused;  // (the two passes of a site run on different lanes here)
     for (uint32_t b = 0; b <= pg.nblk; ++b) {
         // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
         if (b < pg.nblk) {
             const uint32_t pos = b * kBlock + threadIdx.x;
             // block 0: the knot table's copy goes out behind its loads
-            const float4 un = pair_update1<MU, OFF32, MEAS1, IMH>(c, pos, pos < pg.n_t, acc_s, [&] {
+            const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, false>(c, pos, pos < pg.n_t, acc_s, [&] {
                 if constexpr (IMH) {
                     if (b == 0u) {
                         stage_table(imh);
                         __syncthreads();
                     }
                 }
-            });
+            }, unused);
             buf[(b & 1u) * kBlock + threadIdx.x] = un;
             if (b == 0u) buf[2u * kBlock + threadIdx.x] = un;
         }
@@ -278,11 +375,11 @@ __global__ __launch_bounds__(kBlock) void k_pair(
         // the NU pass on positions [b * kBlock - lag, (b + 1) * kBlock - lag)
         const int ipos = (int)(b * kBlock + threadIdx.x) - (int)pg.lag;
         const bool valid = ipos >= 0 && (uint32_t)ipos < pg.n_t;
-        pair_update2<MU, NU, OFF32, MEAS2, IMH>(c, valid ? (uint32_t)ipos : 0u, valid, [&](uint32_t q) {
+        pair_update2<MU, NU, OFF32, MEAS2, IMH, false>(c, valid ? (uint32_t)ipos : 0u, valid, [&](uint32_t q) {
             const uint32_t blk = q / kBlock;
             return buf[(blk == b || blk + 1u == b) ? (blk & 1u) * kBlock + q % kBlock
                                                    : 2u * kBlock + q % kBlock];
-        }, acc_s, acc_t);
+        }, acc_s, acc_t, unused);
         __syncthreads();  // before the next block's MU results replace block b - 1
     }
     if constexpr (MEAS1 || MEAS2) {

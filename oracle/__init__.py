@@ -72,6 +72,10 @@ def _load():
     lib.oracle_sweep_imh.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, u64p]
     lib.oracle_sweep_imh.restype = ctypes.c_int
+    lib.oracle_or_pass.argtypes = [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_or_pass.restype = ctypes.c_int
+    lib.oracle_or_sweep.argtypes = [i32p, ctypes.c_int, dp]
+    lib.oracle_or_sweep.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -267,6 +271,28 @@ def sweep(dims, U, beta, seed, sweep_index, prec32=True):
     if rc:
         raise ValueError("oracle_sweep rejected its arguments")
     return int(stats[0]), int(stats[1])
+
+
+def or_pass(dims, U, parity, mu, prec32=True):
+    """In-place overrelaxation pass: U_mu(x) -> V U^dag V, V = w/|w|, on the
+    sites of one parity (links with w = 0 kept)."""
+    lib = _load()
+    d = _dims(dims)
+    if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
+        raise ValueError("U must be a C-contiguous float64 array")
+    if lib.oracle_or_pass(_ptr(d, ctypes.c_int32), int(parity), int(mu), int(bool(prec32)),
+                          _ptr(U, ctypes.c_double)):
+        raise ValueError("oracle_or_pass rejected its arguments")
+
+
+def or_sweep(dims, U, prec32=True):
+    """In-place overrelaxation sweep (odd sites for mu = 0..3, then even)."""
+    lib = _load()
+    d = _dims(dims)
+    if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
+        raise ValueError("U must be a C-contiguous float64 array")
+    if lib.oracle_or_sweep(_ptr(d, ctypes.c_int32), int(bool(prec32)), _ptr(U, ctypes.c_double)):
+        raise ValueError("oracle_or_sweep rejected its arguments")
 
 
 def plaquette(dims, U):

@@ -548,6 +548,50 @@ int oracle_sweep(const int dims[4], double beta, uint64_t seed, uint32_t sweep, 
 }
 
 /* ------------------------------------------------------------------------- */
+/* Overrelaxation (Sec. 2.4 names "heat-bath with overrelaxation" without a    */
+/* formula; this is the standard SU(2) reflection, Adler 1981, Creutz 1987,   */
+/* Brown & Woch 1987).  With the staple sum w of the link, k = |w| and        */
+/* V = w/k, the local weight exp(beta dot(U, w)) depends on U only through     */
+/* dot(U, V) = (1/2)Re Tr(U V^dag); the move U -> V U^dag V keeps it, maps     */
+/* the Haar measure onto itself and undoes itself, so it leaves the local      */
+/* conditional invariant without a random number.  A link with w == 0 is      */
+/* kept.  The result is normalised (Eq. (7)) and stored like a heat-bath link.  */
+/* ------------------------------------------------------------------------- */
+int oracle_or_pass(const int dims[4], int parity, int mu, int prec32, double *U)
+{
+    geom_t g;
+    if (geom_init(&g, dims)) return -1;
+    if (parity < 0 || parity > 1 || mu < 0 || mu > 3) return -1;
+#pragma omp parallel for schedule(static)
+    for (long lex = 0; lex < g.V; ++lex) {
+        int x[4];
+        coords(&g, lex, x);
+        if (((x[0] + x[1] + x[2] + x[3]) & 1) != parity) continue;
+        double w[4];
+        oracle_staple(dims, U, lex, mu, w);
+        double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+        if (k == 0.0) continue;
+        double V[4] = { w[0] / k, w[1] / k, w[2] / k, w[3] / k };
+        double ud[4], t[4], Un[4];
+        qdag(link(U, lex, mu), ud);
+        oracle_qmul(V, ud, t);
+        oracle_qmul(t, V, Un);
+        /* as in oracle_pass, the pass never reads the links it writes */
+        store_unit(U + (lex * 4 + mu) * 4, Un, prec32);
+    }
+    return 0;
+}
+
+/* One overrelaxation sweep, in the heat-bath sweep's pass order. */
+int oracle_or_sweep(const int dims[4], int prec32, double *U)
+{
+    for (int parity = 1; parity >= 0; --parity)
+        for (int mu = 0; mu < 4; ++mu)
+            if (oracle_or_pass(dims, parity, mu, prec32, U)) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Plaquette, Eq. (3): U_mu(x) U_nu(x+mu) U_mu(x+nu)^dag U_nu(x)^dag; its     */
 /* (1/2)Tr is the scalar component.  Sec. 2.4 keeps spatial and temporal      */
 /* averages apart, in double precision.                                       */

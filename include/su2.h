@@ -86,6 +86,21 @@ int su2_sweep_measured(int32_t n);
  * at the current sweep index (which does not advance). */
 int su2_pass(int32_t parity, int32_t mu);
 
+/* n >= 0 overrelaxation sweeps (Sec. 2.4 names the heat-bath "with
+ * overrelaxation" without a formula; this is the standard SU(2) reflection):
+ * in the heat-bath sweep's pass order, every link U_mu(x) becomes V U^dag V
+ * with V = w/|w| (w the Eq. (6) staple sum) and is renormalised as in Eq. (7);
+ * links with w = 0 are kept.  The move keeps each link's local weight
+ * exp(beta dot(U, w)), so the plaquette is conserved up to rounding; it draws
+ * no random numbers, so the sweep index and the counters do not change.
+ * Interleave with su2_sweep (e.g. 1 heat-bath : 3 overrelaxation sweeps) for
+ * an ergodic chain.  Uses the launch plan's tile order (identity under order
+ * 300). */
+int su2_overrelax(int32_t n);
+
+/* One overrelaxation pass: U_mu(x), parity(x) == parity (0 or 1), mu in 0..3. */
+int su2_overrelax_pass(int32_t parity, int32_t mu);
+
 /* Mean plaquette P = (P_s + P_t)/2 of (1/2)Tr U_mu,nu(x) (Eq. (3)), FP64
  * reduction.  Synchronises.  NaN on error. */
 double su2_plaquette(void);

@@ -45,6 +45,7 @@ struct Context {
     hipGraphExec_t graph1 = nullptr;    // one sweep
     hipGraphExec_t graphN = nullptr;    // kGraphSweeps sweeps
     hipGraphExec_t graphM = nullptr;    // one sweep that also measures the plaquette
+    hipGraphExec_t graphOR = nullptr;   // one overrelaxation sweep
     PassPlan plan;                      // launch plan of k_pass (tile order, LDS reservation)
     uint32_t *d_order = nullptr;        // device tile-order table of the plan
     int32_t order_kind = 0;
@@ -77,7 +78,8 @@ void release_graphs()
     if (ctx.graph1) hipGraphExecDestroy(ctx.graph1);
     if (ctx.graphN) hipGraphExecDestroy(ctx.graphN);
     if (ctx.graphM) hipGraphExecDestroy(ctx.graphM);
-    ctx.graph1 = ctx.graphN = ctx.graphM = nullptr;
+    if (ctx.graphOR) hipGraphExecDestroy(ctx.graphOR);
+    ctx.graph1 = ctx.graphN = ctx.graphM = ctx.graphOR = nullptr;
 }
 
 void release_all()
@@ -176,6 +178,37 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
         if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
         prev = node;
     }
+    if (rc == SU2_OK) {
+        hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    hipGraphDestroy(graph);
+    return rc;
+}
+
+// One overrelaxation sweep (the eight passes in the heat-bath sweep's order)
+// as a graph; no sweep-index tick (it draws no random numbers).
+int build_or_graph(hipGraphExec_t *out)
+{
+    hipGraph_t graph;
+    HIP_TRY(hipGraphCreate(&graph, 0));
+    hipGraphNode_t prev = nullptr;
+    int rc = SU2_OK;
+    for (int p = 1; p >= 0 && rc == SU2_OK; --p)
+        for (uint32_t mu = 0; mu < 4 && rc == SU2_OK; ++mu) {
+            PassLaunch pl = or_launch(ctx.links, ctx.g, (uint32_t)p, mu, ctx.plan);
+            hipKernelNodeParams kp{};
+            kp.func = const_cast<void *>(pl.func);
+            kp.gridDim = pl.grid;
+            kp.blockDim = pl.block;
+            kp.sharedMemBytes = pl.lds;
+            kp.kernelParams = pl.args;
+            kp.extra = nullptr;
+            hipGraphNode_t node;
+            hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+            if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+            else prev = node;
+        }
     if (rc == SU2_OK) {
         hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
@@ -360,6 +393,33 @@ int su2_pass(int32_t parity, int32_t mu)
         return fail(SU2_EINVAL, "parity must be 0/1 and mu 0..3");
     PassLaunch pl = pass_launch(ctx.links, ctx.g, ctx.key, (float)ctx.beta, (uint32_t)parity,
                                 (uint32_t)mu, ctx.d_sweep, ctx.d_counters, nullptr, ctx.plan);
+    HIP_TRY(launch(pl, ctx.stream));
+    ctx.meas_fresh = false;
+    return SU2_OK;
+}
+
+int su2_overrelax(int32_t n)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (n < 0) return fail(SU2_EINVAL, "n must be >= 0");
+    if (n == 0) return SU2_OK;
+    if (!ctx.graphOR) {
+        rc = build_or_graph(&ctx.graphOR);
+        if (rc) return rc;
+    }
+    for (int32_t i = 0; i < n; ++i) HIP_TRY(hipGraphLaunch(ctx.graphOR, ctx.stream));
+    ctx.meas_fresh = false;
+    return SU2_OK;
+}
+
+int su2_overrelax_pass(int32_t parity, int32_t mu)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (parity < 0 || parity > 1 || mu < 0 || mu > 3)
+        return fail(SU2_EINVAL, "parity must be 0/1 and mu 0..3");
+    PassLaunch pl = or_launch(ctx.links, ctx.g, (uint32_t)parity, (uint32_t)mu, ctx.plan);
     HIP_TRY(launch(pl, ctx.stream));
     ctx.meas_fresh = false;
     return SU2_OK;

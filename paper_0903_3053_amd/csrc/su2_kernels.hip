@@ -7,6 +7,7 @@
 //                buffer (Sec. 2.4) are fused: the staple stays in registers.
 //   k_pair       the passes of U_0 and U_1 (or U_2 and U_3) of one parity in
 //                one launch (su2_pair.hpp)
+//   k_or         one overrelaxation pass (U -> V U^dag V about the staple)
 //   k_tick       advances the device-resident sweep index (graph-friendly)
 //   k_plaquette  per-workgroup FP64 partial sums of spatial / temporal
 //                plaquettes (Sec. 2.4, Eq. (3))
@@ -51,6 +52,26 @@ __global__ __launch_bounds__(kBlock) void k_pass(
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
     pass_tile<MU, OFF32, MEASURE, IMH>(L, g, key, beta, p, *sweep_ptr, tile, counters, meas_out,
                                        imh);
+}
+
+// One overrelaxation pass over U_MU(x), parity(x) = p: U -> V U^dag V with
+// V = w/|w| (w the Eq. (6) staple sum), the standard SU(2) reflection that
+// keeps the local weight exp(beta dot(U, w)) and needs no random number;
+// links with w = 0 are kept.  The pass reads the old link (144 B per update).
+template <uint32_t MU, bool OFF32>
+__global__ __launch_bounds__(kBlock) void k_or(float4 *__restrict__ L, Geo g, uint32_t p,
+                                               const uint32_t *__restrict__ order)
+{
+#pragma clang fp contract(off)
+    const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
+    const TileStaples t = staples_of(load_tile<MU, OFF32, true>(L, g, p, tile));
+    const uint32_t h = tile * kBlock + threadIdx.x;
+    if (h >= g.half) return;
+    const float k = sqrtf(qdot(t.w, t.w));
+    if (k == 0.0f) return;
+    const float ik = __builtin_amdgcn_rcpf(k);
+    const float4 V = make_float4(t.w.x * ik, t.w.y * ik, t.w.z * ik, t.w.w * ik);
+    st4_stream<OFF32>(L + arr(g, MU, p), h, unitize(qmul(qmul(V, qdag(t.uold)), V)));
 }
 
 __global__ void k_tick(uint32_t *sweep_ptr)
@@ -427,6 +448,31 @@ hipError_t launch(PassLaunch &pl, hipStream_t st)
 }
 
 const void *tick_func() { return reinterpret_cast<const void *>(&k_tick); }
+
+template <uint32_t MU>
+static const void *or_func_mu(bool off32)
+{
+    return off32 ? reinterpret_cast<const void *>(&k_or<MU, true>)
+                 : reinterpret_cast<const void *>(&k_or<MU, false>);
+}
+
+PassLaunch or_launch(float4 *links, const Geo &g, uint32_t p, uint32_t mu, const PassPlan &plan)
+{
+    PassLaunch pl{};
+    const bool off32 = use_off32(g);
+    pl.func = mu == 0u ? or_func_mu<0>(off32) : mu == 1u ? or_func_mu<1>(off32)
+            : mu == 2u ? or_func_mu<2>(off32) : or_func_mu<3>(off32);
+    pl.grid = dim3(pass_blocks(g));
+    pl.block = dim3(kBlock);
+    pl.lds = plan.lds_bytes;
+    pl.links = links;
+    pl.g = g;
+    pl.p = p;
+    pl.order = plan.fused ? nullptr : plan.order;
+    pl.or_pass = true;
+    pl.bind();
+    return pl;
+}
 
 hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st)
 {

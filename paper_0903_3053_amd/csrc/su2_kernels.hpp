@@ -39,11 +39,19 @@ struct PassLaunch {
     ImhTable imh;
     uint32_t lds;
     bool pair = false;
+    bool or_pass = false;  // k_or: (links, g, p, order)
     PairGeo pg;
     void *args[10];
     // point args at this object's own fields (call after every copy)
     void bind()
     {
+        if (or_pass) {
+            args[0] = &links;
+            args[1] = &g;
+            args[2] = &p;
+            args[3] = &order;
+            return;
+        }
         if (pair) {
             void *a[10] = { &links, &g, &pg, &key, &beta, &p, &sweep_ptr, &counters, &meas_out, &imh };
             for (int i = 0; i < 10; ++i) args[i] = a[i];
@@ -82,6 +90,9 @@ std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, flo
                                        const uint32_t *sweep_ptr, unsigned long long *counters,
                                        double2 *meas_out, const PassPlan &plan);
 uint32_t meas_partials(const Geo &g, const PassPlan &plan);
+// One overrelaxation pass (parity p, direction mu) with the plan's tile order
+// and LDS reservation (the identity order under the fused-pair plan).
+PassLaunch or_launch(float4 *links, const Geo &g, uint32_t p, uint32_t mu, const PassPlan &plan);
 hipError_t launch(PassLaunch &pl, hipStream_t st);
 hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st);
 hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st);

@@ -20,7 +20,8 @@ FUSED_PAIRS = 300  # su2_set_plan order kind: each parity as two fused launches
 
 # every symbol include/su2.h declares
 EXPORTS = (
-    "su2_init", "su2_init_ex", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_plaquette", "su2_plaquette_st",
+    "su2_init", "su2_init_ex", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_overrelax",
+    "su2_overrelax_pass", "su2_plaquette", "su2_plaquette_st",
     "su2_polyakov", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
     "su2_counters", "su2_set_stream", "su2_set_plan", "su2_tune", "su2_philox", "su2_synchronize", "su2_last_error",
     "su2_finalize", "su2_batch_init", "su2_batch_sweep", "su2_batch_set_mode", "su2_batch_tune",
@@ -66,6 +67,8 @@ def load():
         "su2_sweep": ([ctypes.c_int32], ctypes.c_int),
         "su2_sweep_measured": ([ctypes.c_int32], ctypes.c_int),
         "su2_pass": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+        "su2_overrelax": ([ctypes.c_int32], ctypes.c_int),
+        "su2_overrelax_pass": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "su2_plaquette": ([], ctypes.c_double),
         "su2_plaquette_st": ([dp], ctypes.c_int),
         "su2_polyakov": ([dp], ctypes.c_int),
@@ -168,6 +171,15 @@ def su2_sweep_measured(n=1):
 
 def su2_pass(parity, mu):
     _check(load().su2_pass(int(parity), int(mu)))
+
+
+def su2_overrelax(n):
+    """n overrelaxation sweeps (U -> V U^dag V about the staple direction)."""
+    _check(load().su2_overrelax(int(n)))
+
+
+def su2_overrelax_pass(parity, mu):
+    _check(load().su2_overrelax_pass(int(parity), int(mu)))
 
 
 def su2_plaquette():

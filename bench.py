@@ -236,6 +236,71 @@ def beta_scan(su2, dims, seed, plans, therm=20, sweeps=100):
             "timed_sweeps": sweeps, "points": rows}
 
 
+def overrelaxation(su2, steps=500, n_or=3):
+    """Overrelaxation sweeps (U -> V U^dag V about the staple direction): their
+    rate on the 64^4 benchmark lattice (old link read: 144 B per update), and
+    at 32^4 beta = 2.3 the plaquette's integrated autocorrelation time of the
+    heat-bath chain against 1 heat-bath + n_or overrelaxation sweeps per step,
+    each with the tuned launch plan, as the time per independent sample."""
+    import numpy as np
+    import torch
+    from paper_0903_3053_amd.stats import gamma_method
+    w = WORKLOADS[64]
+    V64 = int(np.prod(w["dims"]))
+    su2.su2_init(w["dims"], w["beta"], w["seed"], w["start"])
+    su2.su2_set_plan(*w["plan"])
+    su2.su2_sweep(1)
+    su2.su2_overrelax(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    su2.su2_overrelax(20)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pass_ms = dt * 1e3 / (20 * 8)
+    or_bytes = (V64 // 2) * (BYTES_PER_UPDATE + 16)
+    rate64 = 4 * V64 * 20 / dt
+    su2.su2_finalize()
+
+    dims, beta, seed = (32, 32, 32, 32), 2.3, 1
+    V = int(np.prod(dims))
+    su2.su2_init(dims, beta, seed, 1)
+    su2.su2_tune(2)
+    su2.su2_sweep(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hb = su2.su2_sweep_measure(steps, 1)[:, 0]
+    t_hb = (time.perf_counter() - t0) / steps
+    su2.su2_init(dims, beta, seed, 1)
+    su2.su2_sweep(100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(100):
+        su2.su2_sweep(1)
+        su2.su2_overrelax(n_or)
+    torch.cuda.synchronize()
+    t_mix = (time.perf_counter() - t0) / 100
+    mix = []
+    for _ in range(steps):
+        su2.su2_sweep(1)
+        su2.su2_overrelax(n_or)
+        mix.append(su2.su2_plaquette())
+    su2.su2_finalize()
+    m0, e0, tau0, _, _ = gamma_method(hb)
+    m1, e1, tau1, _, _ = gamma_method(np.asarray(mix))
+    return {"sweep_rate_64x64x64x64": {"link_updates_per_s": rate64, "avg_pass_ms": pass_ms,
+                                        "algorithmic_bytes_per_pass": or_bytes,
+                                        "hbm_frac": or_bytes / (pass_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "chain_32x32x32x32_b2.3": {
+                "heat_bath": {"plaquette": m0, "plaquette_err": e0, "tau_int_steps": tau0,
+                              "ms_per_step": t_hb * 1e3},
+                f"heat_bath_plus_{n_or}_overrelaxation": {"plaquette": m1, "plaquette_err": e1,
+                                                          "tau_int_steps": tau1, "ms_per_step": t_mix * 1e3},
+                "z_plaquette": (m1 - m0) / float(np.hypot(e0, e1)),
+                # time per independent sample of <P>: ms per step x 2 tau_int
+                "speedup_per_independent_sample": (t_hb * tau0) / (t_mix * tau1),
+                "steps": steps}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +413,7 @@ def main():
     if not args.no_extras:
         rec["batched_replicas"] = batched_replicas(su2)
         rec["learned_proposal"] = learned_proposal(su2)
+        rec["overrelaxation"] = overrelaxation(su2)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     su2.su2_finalize()

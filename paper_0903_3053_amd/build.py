@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsu2.so")
-SOURCES = ["su2_kernels.hip", "su2_api.hip", "su2_batch.hip", "su2_learned.hip"]
+SOURCES = ["su2_kernels.hip", "su2_api.hip", "su2_batch.hip", "su2_learned.hip", "su2_ising.hip"]
 ARCH = os.environ.get("SU2_OFFLOAD_ARCH", "gfx950")
 
 

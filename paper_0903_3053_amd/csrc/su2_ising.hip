@@ -1,0 +1,405 @@
+// su2_ising.hip -- the 2-D Ising workload (Sec. 2.3, Eq. (1)): Metropolis on a
+// red-black partition of an L0 x L1 periodic lattice, behind include/ising.h.
+//
+// Layout: one int8 array per colour, N/2 bytes each, indexed by the half index
+// h = x/2 + (L0/2) y (a row of one colour is contiguous).  The paper packs
+// 1-bit spins of a "direct-dual" cell into four-component registers
+// (Sec. 2.3, Fig. 2) to save fetches on RV770; on MI355X a byte per spin is
+// already far below what the random numbers cost, so spins stay plain bytes.
+// Each lane updates four consecutive half-sites of one colour from one
+// Philox-4x32-10 call (one 32-bit word each), so the generator's output is
+// used whole.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <vector>
+
+#include "ising.h"
+#include "su2.h"
+#include "su2_device.hpp"
+
+namespace su2 {
+namespace {
+
+constexpr int kIsingBlock = 256;
+constexpr int kIsingWave = 64;
+constexpr uint32_t kPurposeIsing = 4u, kPurposeIsingHot = 5u;
+
+struct IsingGeo {
+    uint32_t L0, L1, H0, half;  // H0 = L0/2, half = N/2
+    FastDiv dH0;
+};
+
+// site (x, y) of colour c at half index h
+__device__ __forceinline__ void ising_site(const IsingGeo &g, uint32_t c, uint32_t h, uint32_t &x,
+                                           uint32_t &y)
+{
+    y = fdiv(h, g.dH0);
+    x = 2u * (h - y * g.H0) + ((c + y) & 1u);
+}
+
+__global__ __launch_bounds__(kIsingBlock) void k_ising_init(int8_t *__restrict__ S, IsingGeo g, Key key,
+                                                            int hot)
+{
+    const uint32_t grp = blockIdx.x * kIsingBlock + threadIdx.x;  // four half-sites of colour c
+    const uint32_t c = blockIdx.y;
+    if (4u * grp >= g.half) return;
+    const uint4 r = hot ? philox(make_uint4(grp, c | (kPurposeIsingHot << 8), 0u, 0u), key)
+                        : make_uint4(0u, 0u, 0u, 0u);
+    const uint32_t w[4] = { r.x, r.y, r.z, r.w };
+#pragma unroll
+    for (uint32_t k = 0; k < 4u; ++k) {
+        const uint32_t h = 4u * grp + k;
+        if (h < g.half) S[(size_t)c * g.half + h] = (w[k] >> 31) ? (int8_t)-1 : (int8_t)1;
+    }
+}
+
+// One colour: every site of colour c tries a flip.  T4, T8: the integer
+// Metropolis thresholds for dE = 4 and 8.
+__global__ __launch_bounds__(kIsingBlock) void k_ising_pass(int8_t *__restrict__ S, IsingGeo g, Key key,
+                                                            uint32_t c, const uint32_t *__restrict__ sweep_ptr,
+                                                            uint32_t T4, uint32_t T8,
+                                                            unsigned long long *__restrict__ accepted)
+{
+    const uint32_t grp = blockIdx.x * kIsingBlock + threadIdx.x;
+    uint32_t flips = 0;
+    if (4u * grp < g.half) {
+        int8_t *own = S + (size_t)c * g.half;
+        const int8_t *oth = S + (size_t)(c ^ 1u) * g.half;
+        const uint4 r = philox(make_uint4(grp, c | (kPurposeIsing << 8), *sweep_ptr, 0u), key);
+        const uint32_t w[4] = { r.x, r.y, r.z, r.w };
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) {
+            const uint32_t h = 4u * grp + k;
+            if (h >= g.half) break;
+            uint32_t x, y;
+            ising_site(g, c, h, x, y);
+            const uint32_t xp = x + 1u == g.L0 ? 0u : x + 1u, xm = x == 0u ? g.L0 - 1u : x - 1u;
+            const uint32_t yp = y + 1u == g.L1 ? 0u : y + 1u, ym = y == 0u ? g.L1 - 1u : y - 1u;
+            const int nb = oth[(xp >> 1) + g.H0 * y] + oth[(xm >> 1) + g.H0 * y] +
+                           oth[(x >> 1) + g.H0 * yp] + oth[(x >> 1) + g.H0 * ym];
+            const int s = own[h];
+            const int dE = 2 * s * nb;
+            const bool flip = dE <= 0 || (w[k] >> 8) < (dE == 4 ? T4 : T8);
+            if (flip) {
+                own[h] = (int8_t)-s;  // same-colour sites are never neighbours
+                ++flips;
+            }
+        }
+    }
+    // one counter add per wave
+    unsigned long long n = flips;
+#pragma unroll
+    for (int off = kIsingWave / 2; off > 0; off >>= 1) n += __shfl_xor(n, off);
+    if ((threadIdx.x & (kIsingWave - 1)) == 0 && n) atomicAdd(accepted, n);
+}
+
+__global__ void k_ising_tick(uint32_t *sweep_ptr)
+{
+    if (threadIdx.x == 0) *sweep_ptr += 1u;
+}
+
+// Exact integer sums over all sites: bonds to the +x and +y neighbours, spins.
+__global__ __launch_bounds__(kIsingBlock) void k_ising_obs(const int8_t *__restrict__ S, IsingGeo g,
+                                                           unsigned long long *__restrict__ sums)
+{
+    const uint32_t i = blockIdx.x * kIsingBlock + threadIdx.x;  // over both colours
+    long long bonds = 0, mag = 0;
+    if (i < 2u * g.half) {
+        const uint32_t c = i >= g.half ? 1u : 0u, h = i - c * g.half;
+        uint32_t x, y;
+        ising_site(g, c, h, x, y);
+        const int8_t *oth = S + (size_t)(c ^ 1u) * g.half;
+        const uint32_t xp = x + 1u == g.L0 ? 0u : x + 1u, yp = y + 1u == g.L1 ? 0u : y + 1u;
+        const int s = S[(size_t)c * g.half + h];
+        bonds = s * (oth[(xp >> 1) + g.H0 * y] + oth[(x >> 1) + g.H0 * yp]);
+        mag = s;
+    }
+#pragma unroll
+    for (int off = kIsingWave / 2; off > 0; off >>= 1) {
+        bonds += __shfl_xor(bonds, off);
+        mag += __shfl_xor(mag, off);
+    }
+    if ((threadIdx.x & (kIsingWave - 1)) == 0) {
+        atomicAdd(&sums[0], (unsigned long long)bonds);  // two's complement: exact modulo 2^64
+        atomicAdd(&sums[1], (unsigned long long)mag);
+    }
+}
+
+// lex order <-> colour arrays
+__global__ __launch_bounds__(kIsingBlock) void k_ising_pack(const int8_t *__restrict__ S, IsingGeo g,
+                                                            int8_t *__restrict__ out)
+{
+    const uint32_t lex = blockIdx.x * kIsingBlock + threadIdx.x;
+    if (lex >= 2u * g.half) return;
+    const uint32_t y = lex / g.L0, x = lex - y * g.L0;
+    out[lex] = S[(size_t)((x + y) & 1u) * g.half + (x >> 1) + g.H0 * y];
+}
+
+__global__ __launch_bounds__(kIsingBlock) void k_ising_unpack(int8_t *__restrict__ S, IsingGeo g,
+                                                              const int8_t *__restrict__ in)
+{
+    const uint32_t lex = blockIdx.x * kIsingBlock + threadIdx.x;
+    if (lex >= 2u * g.half) return;
+    const uint32_t y = lex / g.L0, x = lex - y * g.L0;
+    S[(size_t)((x + y) & 1u) * g.half + (x >> 1) + g.H0 * y] = in[lex];
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+constexpr int kIsingGraphSweeps = 32;
+
+struct IsingCtx {
+    bool ready = false;
+    IsingGeo g{};
+    Key key{};
+    double beta = 0.0;
+    uint32_t T4 = 0, T8 = 0;
+    int8_t *S = nullptr;
+    uint32_t *d_sweep = nullptr;
+    unsigned long long *d_acc = nullptr;   // accepted flips
+    unsigned long long *d_sums = nullptr;  // observables
+    uint64_t sweep = 0;
+    hipGraphExec_t graph1 = nullptr, graphN = nullptr;
+};
+
+IsingCtx I;
+char ierr[512] = "no error";
+
+int ifail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(ierr, sizeof ierr, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define ITRY(expr)                                                                        \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            return ifail(SU2_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
+    } while (0)
+
+void ising_release()
+{
+    if (I.ready) hipDeviceSynchronize();
+    if (I.graph1) hipGraphExecDestroy(I.graph1);
+    if (I.graphN) hipGraphExecDestroy(I.graphN);
+    void *ptrs[] = { I.S, I.d_sweep, I.d_acc, I.d_sums };
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    I = IsingCtx{};
+}
+
+uint32_t groups() { return (I.g.half + 3u) / 4u; }
+uint32_t blocks_of(uint64_t n) { return (uint32_t)((n + kIsingBlock - 1) / kIsingBlock); }
+
+int build_sweep_graph(int nsweeps, hipGraphExec_t *out)
+{
+    hipGraph_t graph;
+    ITRY(hipGraphCreate(&graph, 0));
+    hipGraphNode_t prev = nullptr;
+    int rc = SU2_OK;
+    int8_t *S = I.S;
+    IsingGeo g = I.g;
+    Key key = I.key;
+    const uint32_t *sp = I.d_sweep;
+    uint32_t *spw = I.d_sweep;
+    uint32_t T4 = I.T4, T8 = I.T8;
+    unsigned long long *acc = I.d_acc;
+    uint32_t colours[2] = { 0u, 1u };
+    auto add = [&](const void *func, dim3 grid, void **args) -> int {
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void *>(func);
+        kp.gridDim = grid;
+        kp.blockDim = dim3(func == reinterpret_cast<const void *>(&k_ising_tick) ? 1 : kIsingBlock);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) return ifail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+        prev = node;
+        return (int)SU2_OK;
+    };
+    for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
+        for (int c = 0; c < 2 && rc == SU2_OK; ++c) {
+            void *args[] = { &S, &g, &key, &colours[c], &sp, &T4, &T8, &acc };
+            rc = add(reinterpret_cast<const void *>(&k_ising_pass), dim3(blocks_of(groups())), args);
+        }
+        if (rc == SU2_OK) {
+            void *targs[] = { &spw };
+            rc = add(reinterpret_cast<const void *>(&k_ising_tick), dim3(1), targs);
+        }
+    }
+    if (rc == SU2_OK) {
+        hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = ifail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    hipGraphDestroy(graph);
+    return rc;
+}
+
+int ising_ready()
+{
+    if (!I.ready) return ifail(SU2_ESTATE, "no Ising lattice: call ising_init first");
+    return SU2_OK;
+}
+
+}  // namespace
+}  // namespace su2
+
+using namespace su2;
+
+extern "C" {
+
+int ising_init(const int32_t dims[2], double beta, uint64_t seed, int32_t start)
+{
+    if (!dims) return ifail(SU2_EINVAL, "dims is NULL");
+    if (dims[0] < 2 || dims[1] < 2 || (dims[0] & 1) || (dims[1] & 1))
+        return ifail(SU2_EINVAL, "extents must be even and >= 2");
+    const uint64_t N = (uint64_t)dims[0] * (uint64_t)dims[1];
+    if (N >= (1ull << 32)) return ifail(SU2_EINVAL, "lattice volume must be below 2^32");
+    if (!std::isfinite(beta) || beta < 0.0) return ifail(SU2_EINVAL, "beta must be finite and >= 0");
+    if (start != SU2_COLD && start != SU2_HOT) return ifail(SU2_EINVAL, "start must be 0 or 1");
+    ising_release();
+    I.g.L0 = (uint32_t)dims[0];
+    I.g.L1 = (uint32_t)dims[1];
+    I.g.H0 = I.g.L0 / 2u;
+    I.g.half = (uint32_t)(N / 2);
+    I.g.dH0 = make_fastdiv(I.g.H0);
+    I.key = Key{ (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
+    I.beta = beta;
+    I.T4 = (uint32_t)std::floor(std::exp(-4.0 * beta) * 16777216.0);
+    I.T8 = (uint32_t)std::floor(std::exp(-8.0 * beta) * 16777216.0);
+    if (hipMalloc(&I.S, (size_t)N) != hipSuccess || hipMalloc(&I.d_sweep, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&I.d_acc, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&I.d_sums, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        hipGetLastError();
+        ising_release();
+        return ifail(SU2_ENOMEM, "cannot allocate the Ising lattice");
+    }
+    I.ready = true;
+    ITRY(hipMemset(I.d_sweep, 0, sizeof(uint32_t)));
+    ITRY(hipMemset(I.d_acc, 0, sizeof(unsigned long long)));
+    hipLaunchKernelGGL(k_ising_init, dim3(blocks_of(groups()), 2), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
+                       I.key, start == SU2_HOT);
+    ITRY(hipGetLastError());
+    ITRY(hipDeviceSynchronize());
+    return SU2_OK;
+}
+
+int ising_sweep(int32_t n)
+{
+    int rc = ising_ready();
+    if (rc) return rc;
+    if (n < 0) return ifail(SU2_EINVAL, "n must be >= 0");
+    if (I.sweep + (uint64_t)n > 0xffffffffull) return ifail(SU2_EINVAL, "sweep index would pass 2^32 - 1");
+    int32_t left = n;
+    if (left >= kIsingGraphSweeps && !I.graphN) {
+        rc = build_sweep_graph(kIsingGraphSweeps, &I.graphN);
+        if (rc) return rc;
+    }
+    while (left >= kIsingGraphSweeps) {
+        ITRY(hipGraphLaunch(I.graphN, nullptr));
+        left -= kIsingGraphSweeps;
+    }
+    if (left > 0 && !I.graph1) {
+        rc = build_sweep_graph(1, &I.graph1);
+        if (rc) return rc;
+    }
+    while (left-- > 0) ITRY(hipGraphLaunch(I.graph1, nullptr));
+    I.sweep += (uint64_t)n;
+    return SU2_OK;
+}
+
+int ising_observables(double out[2])
+{
+    int rc = ising_ready();
+    if (rc) return rc;
+    if (!out) return ifail(SU2_EINVAL, "out is NULL");
+    ITRY(hipMemsetAsync(I.d_sums, 0, 2 * sizeof(unsigned long long), nullptr));
+    hipLaunchKernelGGL(k_ising_obs, dim3(blocks_of(2ull * I.g.half)), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
+                       I.d_sums);
+    ITRY(hipGetLastError());
+    unsigned long long h[2];
+    ITRY(hipMemcpy(h, I.d_sums, sizeof h, hipMemcpyDeviceToHost));
+    const double N = 2.0 * (double)I.g.half;
+    out[0] = -(double)(long long)h[0] / N;
+    out[1] = (double)(long long)h[1] / N;
+    return SU2_OK;
+}
+
+int ising_spins(int8_t *host_out, size_t n)
+{
+    int rc = ising_ready();
+    if (rc) return rc;
+    if (!host_out || n != 2ull * I.g.half) return ifail(SU2_EINVAL, "n must be L0 * L1");
+    int8_t *stage = nullptr;
+    if (hipMalloc(&stage, n) != hipSuccess) {
+        hipGetLastError();
+        return ifail(SU2_ENOMEM, "cannot allocate the staging buffer");
+    }
+    hipLaunchKernelGGL(k_ising_pack, dim3(blocks_of(n)), dim3(kIsingBlock), 0, nullptr, I.S, I.g, stage);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpy(host_out, stage, n, hipMemcpyDeviceToHost);
+    hipFree(stage);
+    if (e != hipSuccess) return ifail(SU2_EDEVICE, "ising_spins: %s", hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int ising_set_spins(const int8_t *host_in, size_t n, uint64_t sweep_index)
+{
+    int rc = ising_ready();
+    if (rc) return rc;
+    if (!host_in || n != 2ull * I.g.half) return ifail(SU2_EINVAL, "n must be L0 * L1");
+    if (sweep_index > 0xffffffffull) return ifail(SU2_EINVAL, "sweep index must be below 2^32");
+    for (size_t i = 0; i < n; ++i)
+        if (host_in[i] != 1 && host_in[i] != -1) return ifail(SU2_EINVAL, "spin %zu is not +1 or -1", i);
+    int8_t *stage = nullptr;
+    if (hipMalloc(&stage, n) != hipSuccess) {
+        hipGetLastError();
+        return ifail(SU2_ENOMEM, "cannot allocate the staging buffer");
+    }
+    hipError_t e = hipMemcpy(stage, host_in, n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_ising_unpack, dim3(blocks_of(n)), dim3(kIsingBlock), 0, nullptr, I.S, I.g, stage);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipFree(stage);
+    if (e != hipSuccess) return ifail(SU2_EDEVICE, "ising_set_spins: %s", hipGetErrorString(e));
+    const uint32_t s32 = (uint32_t)sweep_index;
+    ITRY(hipMemcpy(I.d_sweep, &s32, sizeof s32, hipMemcpyHostToDevice));
+    I.sweep = sweep_index;
+    return SU2_OK;
+}
+
+int ising_sweep_index(uint64_t *out)
+{
+    int rc = ising_ready();
+    if (rc) return rc;
+    if (!out) return ifail(SU2_EINVAL, "out is NULL");
+    *out = I.sweep;
+    return SU2_OK;
+}
+
+int ising_accepted(uint64_t *out)
+{
+    int rc = ising_ready();
+    if (rc) return rc;
+    if (!out) return ifail(SU2_EINVAL, "out is NULL");
+    unsigned long long h = 0;
+    ITRY(hipMemcpy(&h, I.d_acc, sizeof h, hipMemcpyDeviceToHost));
+    *out = h;
+    return SU2_OK;
+}
+
+const char *ising_last_error(void) { return ierr; }
+
+void ising_finalize(void) { ising_release(); }
+
+}  // extern "C"

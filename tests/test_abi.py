@@ -16,7 +16,7 @@ def _declared():
     names = set()
     for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
         text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names |= set(re.findall(r"\b(su2_\w+)\s*\(", text))
+        names |= set(re.findall(r"\b((?:su2|ising)_\w+)\s*\(", text))
     return names
 
 
@@ -37,8 +37,23 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_binding_lists_every_declared_symbol():
-    from paper_0903_3053_amd import su2
-    assert _declared() == set(su2.EXPORTS)
+    from paper_0903_3053_amd import ising, su2
+    assert _declared() == set(su2.EXPORTS) | set(ising.EXPORTS)
+
+
+def test_ising_errors_without_device_work(lib):
+    from paper_0903_3053_amd import ising, su2
+    lib = ising.load()
+    lib.ising_finalize()
+    assert lib.ising_sweep(1) == su2.SU2_ESTATE
+    out = (ctypes.c_double * 2)()
+    assert lib.ising_observables(out) == su2.SU2_ESTATE
+    assert b"ising_init" in lib.ising_last_error()
+    for dims, beta, start in [((3, 4), 0.4, 0), ((4, 0), 0.4, 0), ((4, 4), -1.0, 0),
+                              ((4, 4), float("inf"), 0), ((4, 4), 0.4, 2)]:
+        d = np.asarray(dims, dtype=np.int32)
+        assert lib.ising_init(d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), beta, 1, start) == su2.SU2_EINVAL
+    assert lib.ising_init(None, 0.4, 1, 0) == su2.SU2_EINVAL
 
 
 def test_state_errors_before_init(lib):

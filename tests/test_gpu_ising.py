@@ -1,0 +1,87 @@
+"""The 2-D Ising workload (Sec. 2.3, Eq. (1)) through the C ABI against the
+oracle: the Metropolis decisions are integer comparisons on both sides, so
+spins, accepted-flip counts and observables must agree exactly after any
+number of sweeps, also on the paper's 1024 x 512 lattice; plus Onsager's energy
+and Yang's magnetisation on a larger lattice from GPU chains."""
+import numpy as np
+import pytest
+
+import oracle.ising as oising
+from paper_0903_3053_amd.stats import gamma_method
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    from paper_0903_3053_amd import ising
+    ising.load()
+    yield ising
+    ising.ising_finalize()
+
+
+CASES = [((8, 8), 0.44, 1, 1, 40), ((16, 6), 0.2, 2, 1, 40), ((6, 10), 1.0, 3, 0, 40), ((2, 2), 0.3, 4, 1, 40),
+         ((10, 4), 0.0, 5, 1, 10), ((1024, 512), 0.44, 1, 1, 20)]
+
+
+@pytest.mark.parametrize("dims,beta,seed,start,n", CASES)
+def test_ising_bit_identical_to_oracle(lib, dims, beta, seed, start, n):
+    s = oising.init(dims, seed, start)
+    lib.ising_init(dims, beta, seed, start)
+    assert np.array_equal(lib.ising_spins(), s)
+    acc = oising.sweep(dims, s, beta, seed, 0, n // 2)
+    lib.ising_sweep(n // 2)
+    acc += oising.sweep(dims, s, beta, seed, n // 2, n - n // 2)
+    lib.ising_sweep(n - n // 2)
+    got = lib.ising_spins()
+    print(f"Ising {dims} beta {beta}: {n} sweeps, {acc} flips, spins differing {int(np.sum(got != s))}")
+    assert np.array_equal(got, s)
+    assert lib.ising_accepted() == acc
+    assert lib.ising_sweep_index() == n
+    assert lib.ising_observables() == oising.observables(dims, s)
+
+
+def test_ising_resume_and_errors(lib):
+    dims, beta, seed = (12, 8), 0.4, 9
+    s = oising.init(dims, seed, 1)
+    oising.sweep(dims, s, beta, seed, 0, 7)
+    lib.ising_init(dims, beta, seed, 0)
+    lib.ising_set_spins(s, 7)
+    oising.sweep(dims, s, beta, seed, 7, 5)
+    lib.ising_sweep(5)
+    assert np.array_equal(lib.ising_spins(), s) and lib.ising_sweep_index() == 12
+    with pytest.raises(lib.IsingError):
+        lib.ising_set_spins(np.zeros(96, dtype=np.int8), 0)  # not +-1
+    with pytest.raises(lib.IsingError):
+        lib.ising_set_spins(np.ones(95, dtype=np.int8), 0)   # wrong size
+    with pytest.raises(lib.IsingError):
+        lib.ising_sweep(-1)
+
+
+def test_ising_onsager_and_yang_on_gpu(lib):
+    from scipy import special
+    L = (256, 256)
+    lib.ising_init(L, 0.3, 11, 1)
+    lib.ising_sweep(200)
+    E = []
+    for _ in range(1000):
+        lib.ising_sweep(1)
+        E.append(lib.ising_observables()[0])
+    m, s, t, _, _ = gamma_method(np.asarray(E))
+    b = 0.3
+    k = 2 * np.sinh(2 * b) / np.cosh(2 * b) ** 2
+    ex = -1 / np.tanh(2 * b) * (1 + 2 / np.pi * (2 * np.tanh(2 * b) ** 2 - 1) * special.ellipk(k * k))
+    print(f"256^2 beta 0.3: E {m:.6f}+-{s:.6f}, Onsager {ex:.6f}")
+    assert abs(m - ex) < 4 * s
+    lib.ising_init(L, 0.6, 12, 0)
+    lib.ising_sweep(200)
+    M = []
+    for _ in range(1000):
+        lib.ising_sweep(1)
+        M.append(abs(lib.ising_observables()[1]))
+    m, s, t, _, _ = gamma_method(np.asarray(M))
+    ex = (1 - np.sinh(1.2) ** -4) ** 0.125
+    print(f"256^2 beta 0.6: |m| {m:.6f}+-{s:.6f}, Yang {ex:.6f}")
+    assert abs(m - ex) < 4 * s + 1e-4

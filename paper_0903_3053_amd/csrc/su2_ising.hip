@@ -25,6 +25,9 @@ namespace {
 constexpr int kIsingBlock = 256;
 constexpr int kIsingWave = 64;
 constexpr uint32_t kPurposeIsing = 4u, kPurposeIsingHot = 5u;
+// accepted-flip counters, one per slot of waves: a single counter for every
+// wave of a pass serialises in L2 (one address), 4096 spread the adds
+constexpr uint32_t kAccSlots = 4096;
 
 struct IsingGeo {
     uint32_t L0, L1, H0, half;  // H0 = L0/2, half = N/2
@@ -67,23 +70,29 @@ __global__ __launch_bounds__(kIsingBlock) void k_ising_pass(int8_t *__restrict__
     if (4u * grp < g.half) {
         int8_t *own = S + (size_t)c * g.half;
         const int8_t *oth = S + (size_t)(c ^ 1u) * g.half;
+        // every load of the four sites goes out before any store (a store
+        // could otherwise be taken to alias a later load and serialise them)
+        int sv[4], nb[4];
+#pragma unroll
+        for (uint32_t k = 0; k < 4u; ++k) {
+            const uint32_t h = min(4u * grp + k, g.half - 1u);
+            uint32_t x, y;
+            ising_site(g, c, h, x, y);
+            const uint32_t xp = x + 1u == g.L0 ? 0u : x + 1u, xm = x == 0u ? g.L0 - 1u : x - 1u;
+            const uint32_t yp = y + 1u == g.L1 ? 0u : y + 1u, ym = y == 0u ? g.L1 - 1u : y - 1u;
+            nb[k] = oth[(xp >> 1) + g.H0 * y] + oth[(xm >> 1) + g.H0 * y] + oth[(x >> 1) + g.H0 * yp] +
+                    oth[(x >> 1) + g.H0 * ym];
+            sv[k] = own[h];
+        }
         const uint4 r = philox(make_uint4(grp, c | (kPurposeIsing << 8), *sweep_ptr, 0u), key);
         const uint32_t w[4] = { r.x, r.y, r.z, r.w };
 #pragma unroll
         for (uint32_t k = 0; k < 4u; ++k) {
             const uint32_t h = 4u * grp + k;
-            if (h >= g.half) break;
-            uint32_t x, y;
-            ising_site(g, c, h, x, y);
-            const uint32_t xp = x + 1u == g.L0 ? 0u : x + 1u, xm = x == 0u ? g.L0 - 1u : x - 1u;
-            const uint32_t yp = y + 1u == g.L1 ? 0u : y + 1u, ym = y == 0u ? g.L1 - 1u : y - 1u;
-            const int nb = oth[(xp >> 1) + g.H0 * y] + oth[(xm >> 1) + g.H0 * y] +
-                           oth[(x >> 1) + g.H0 * yp] + oth[(x >> 1) + g.H0 * ym];
-            const int s = own[h];
-            const int dE = 2 * s * nb;
+            const int dE = 2 * sv[k] * nb[k];
             const bool flip = dE <= 0 || (w[k] >> 8) < (dE == 4 ? T4 : T8);
-            if (flip) {
-                own[h] = (int8_t)-s;  // same-colour sites are never neighbours
+            if (h < g.half && flip) {
+                own[h] = (int8_t)-sv[k];  // same-colour sites are never neighbours
                 ++flips;
             }
         }
@@ -92,7 +101,8 @@ __global__ __launch_bounds__(kIsingBlock) void k_ising_pass(int8_t *__restrict__
     unsigned long long n = flips;
 #pragma unroll
     for (int off = kIsingWave / 2; off > 0; off >>= 1) n += __shfl_xor(n, off);
-    if ((threadIdx.x & (kIsingWave - 1)) == 0 && n) atomicAdd(accepted, n);
+    if ((threadIdx.x & (kIsingWave - 1)) == 0 && n)
+        atomicAdd(&accepted[(blockIdx.x * (kIsingBlock / kIsingWave) + threadIdx.x / kIsingWave) % kAccSlots], n);
 }
 
 __global__ void k_ising_tick(uint32_t *sweep_ptr)
@@ -122,8 +132,10 @@ __global__ __launch_bounds__(kIsingBlock) void k_ising_obs(const int8_t *__restr
         mag += __shfl_xor(mag, off);
     }
     if ((threadIdx.x & (kIsingWave - 1)) == 0) {
-        atomicAdd(&sums[0], (unsigned long long)bonds);  // two's complement: exact modulo 2^64
-        atomicAdd(&sums[1], (unsigned long long)mag);
+        // two's complement adds: exact modulo 2^64; spread over kAccSlots pairs
+        const uint32_t slot = (blockIdx.x * (kIsingBlock / kIsingWave) + threadIdx.x / kIsingWave) % kAccSlots;
+        atomicAdd(&sums[2 * slot], (unsigned long long)bonds);
+        atomicAdd(&sums[2 * slot + 1], (unsigned long long)mag);
     }
 }
 
@@ -159,8 +171,8 @@ struct IsingCtx {
     uint32_t T4 = 0, T8 = 0;
     int8_t *S = nullptr;
     uint32_t *d_sweep = nullptr;
-    unsigned long long *d_acc = nullptr;   // accepted flips
-    unsigned long long *d_sums = nullptr;  // observables
+    unsigned long long *d_acc = nullptr;   // accepted flips, kAccSlots partial counts
+    unsigned long long *d_sums = nullptr;  // observables, kAccSlots (bonds, spins) partial sums
     uint64_t sweep = 0;
     hipGraphExec_t graph1 = nullptr, graphN = nullptr;
 };
@@ -276,15 +288,15 @@ int ising_init(const int32_t dims[2], double beta, uint64_t seed, int32_t start)
     I.T4 = (uint32_t)std::floor(std::exp(-4.0 * beta) * 16777216.0);
     I.T8 = (uint32_t)std::floor(std::exp(-8.0 * beta) * 16777216.0);
     if (hipMalloc(&I.S, (size_t)N) != hipSuccess || hipMalloc(&I.d_sweep, sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&I.d_acc, sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&I.d_sums, 2 * sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc(&I.d_acc, kAccSlots * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&I.d_sums, 2 * kAccSlots * sizeof(unsigned long long)) != hipSuccess) {
         hipGetLastError();
         ising_release();
         return ifail(SU2_ENOMEM, "cannot allocate the Ising lattice");
     }
     I.ready = true;
     ITRY(hipMemset(I.d_sweep, 0, sizeof(uint32_t)));
-    ITRY(hipMemset(I.d_acc, 0, sizeof(unsigned long long)));
+    ITRY(hipMemset(I.d_acc, 0, kAccSlots * sizeof(unsigned long long)));
     hipLaunchKernelGGL(k_ising_init, dim3(blocks_of(groups()), 2), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
                        I.key, start == SU2_HOT);
     ITRY(hipGetLastError());
@@ -321,15 +333,20 @@ int ising_observables(double out[2])
     int rc = ising_ready();
     if (rc) return rc;
     if (!out) return ifail(SU2_EINVAL, "out is NULL");
-    ITRY(hipMemsetAsync(I.d_sums, 0, 2 * sizeof(unsigned long long), nullptr));
+    ITRY(hipMemsetAsync(I.d_sums, 0, 2 * kAccSlots * sizeof(unsigned long long), nullptr));
     hipLaunchKernelGGL(k_ising_obs, dim3(blocks_of(2ull * I.g.half)), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
                        I.d_sums);
     ITRY(hipGetLastError());
-    unsigned long long h[2];
-    ITRY(hipMemcpy(h, I.d_sums, sizeof h, hipMemcpyDeviceToHost));
+    std::vector<unsigned long long> h(2 * kAccSlots);
+    ITRY(hipMemcpy(h.data(), I.d_sums, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    unsigned long long bonds = 0, mag = 0;
+    for (uint32_t i = 0; i < kAccSlots; ++i) {
+        bonds += h[2 * i];
+        mag += h[2 * i + 1];
+    }
     const double N = 2.0 * (double)I.g.half;
-    out[0] = -(double)(long long)h[0] / N;
-    out[1] = (double)(long long)h[1] / N;
+    out[0] = -(double)(long long)bonds / N;
+    out[1] = (double)(long long)mag / N;
     return SU2_OK;
 }
 
@@ -392,9 +409,11 @@ int ising_accepted(uint64_t *out)
     int rc = ising_ready();
     if (rc) return rc;
     if (!out) return ifail(SU2_EINVAL, "out is NULL");
-    unsigned long long h = 0;
-    ITRY(hipMemcpy(&h, I.d_acc, sizeof h, hipMemcpyDeviceToHost));
-    *out = h;
+    std::vector<unsigned long long> h(kAccSlots);
+    ITRY(hipMemcpy(h.data(), I.d_acc, kAccSlots * sizeof(unsigned long long), hipMemcpyDeviceToHost));
+    uint64_t total = 0;
+    for (unsigned long long v : h) total += v;
+    *out = total;
     return SU2_OK;
 }
 

@@ -301,6 +301,33 @@ def overrelaxation(su2, steps=500, n_or=3):
                 "steps": steps}}
 
 
+def ising_2d():
+    """The paper's other workload (Sec. 2.3): 2-D Ising Metropolis on a red-black
+    partition, beta = 0.44 (near the critical point), hot start, on the paper's
+    1024 x 512 lattice and on 16384^2; spin updates/s with the lattice resident
+    on the device.  The paper quotes 630 s for 10^6 sweeps of 1024 x 512 on
+    ATI RV770 (8.3e8 spin updates/s), as context only."""
+    import torch
+    from paper_0903_3053_amd import ising
+    out = {}
+    for dims, n in (((1024, 512), 2000), ((16384, 16384), 50)):
+        ising.ising_init(dims, 0.44, 1, 1)
+        ising.ising_sweep(10)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ising.ising_sweep(n)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        N = dims[0] * dims[1]
+        e, m = ising.ising_observables()
+        out[f"{dims[0]}x{dims[1]}"] = {"spin_updates_per_s": N * n / dt, "us_per_sweep": dt / n * 1e6,
+                                       "sweeps": n, "energy_per_site": e, "magnetisation": m}
+    ising.ising_finalize()
+    out["paper_context"] = {"hardware": "ATI RV770", "lattice": "1024x512",
+                            "seconds_per_1e6_sweeps": 630, "spin_updates_per_s": 524288 * 1e6 / 630}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -414,6 +441,7 @@ def main():
         rec["batched_replicas"] = batched_replicas(su2)
         rec["learned_proposal"] = learned_proposal(su2)
         rec["overrelaxation"] = overrelaxation(su2)
+        rec["ising_2d"] = ising_2d()
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     su2.su2_finalize()

@@ -301,6 +301,39 @@ def overrelaxation(su2, steps=500, n_or=3):
                 "steps": steps}}
 
 
+# Table 1 of the paper (ATI RV770 GPU seconds for its SU(2) runs on L_t x L_s^3)
+TABLE1_GPU_SECONDS = {(4, 8): 5.2, (4, 16): 17.9, (4, 24): 52.8, (4, 32): 120.6,
+                      (8, 16): 32.7, (8, 24): 102.3, (8, 32): 397.4}
+
+
+def paper_table1(su2, therm=1000, meas=1000, every=5, beta=2.3):
+    """The paper's own SU(2) geometries (Table 1), read as 1000 thermalisation
+    sweeps and 1000 measurements 5 sweeps apart (6000 sweeps), hot start, each
+    with its tuned launch plan (tuning not timed): wall seconds here beside the
+    RV770 seconds the paper prints (context, not a target: the paper does not
+    give beta or the exact sweep count)."""
+    import numpy as np
+    import torch
+    out = []
+    for (lt, ls), paper_s in TABLE1_GPU_SECONDS.items():
+        dims = (ls, ls, ls, lt)  # mu = 3 is time
+        su2.su2_init(dims, beta, 1, 1)
+        plan = su2.su2_tune(2)  # on a copy of the links: the chain is untouched
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su2.su2_sweep(therm)
+        hist = su2.su2_sweep_measure(meas * every, every)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out.append({"lattice": f"{lt}x{ls}^3", "seconds": dt, "paper_rv770_seconds": paper_s,
+                    "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]},
+                    "ratio": paper_s / dt, "sweeps": therm + meas * every,
+                    "plaquette": float(np.mean(hist[len(hist) // 5:, 0]))})
+    su2.su2_finalize()
+    return {"beta": beta, "reading": "1000 thermalisation sweeps + 1000 measurements 5 sweeps apart",
+            "runs": out}
+
+
 def ising_2d():
     """The paper's other workload (Sec. 2.3): 2-D Ising Metropolis on a red-black
     partition, beta = 0.44 (near the critical point), hot start, on the paper's
@@ -442,6 +475,7 @@ def main():
         rec["learned_proposal"] = learned_proposal(su2)
         rec["overrelaxation"] = overrelaxation(su2)
         rec["ising_2d"] = ising_2d()
+        rec["paper_table1"] = paper_table1(su2)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
     su2.su2_finalize()

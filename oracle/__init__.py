@@ -72,6 +72,8 @@ def _load():
     lib.oracle_sweep_imh.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                      ctypes.c_int, dp, dp, ctypes.c_int, ctypes.c_double, u64p]
     lib.oracle_sweep_imh.restype = ctypes.c_int
+    lib.oracle_polyakov_field.argtypes = [i32p, dp, dp]
+    lib.oracle_polyakov_field.restype = ctypes.c_int
     lib.oracle_or_pass.argtypes = [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
     lib.oracle_or_pass.restype = ctypes.c_int
     lib.oracle_or_sweep.argtypes = [i32p, ctypes.c_int, dp]
@@ -315,6 +317,29 @@ def polyakov(dims, U):
     if lib.oracle_polyakov(_ptr(d, ctypes.c_int32), _ptr(U, ctypes.c_double), ctypes.byref(out)):
         raise ValueError("bad dims")
     return out.value
+
+
+def polyakov_field(dims, U):
+    """(1/2)Tr of the ordered product of U_3 over t at every spatial site
+    (lex x0 + L0 (x1 + L1 x2)), FP64."""
+    lib = _load()
+    d = _dims(dims)
+    U = _links(U)
+    out = np.empty(int(d[0]) * int(d[1]) * int(d[2]))
+    if lib.oracle_polyakov_field(_ptr(d, ctypes.c_int32), _ptr(U, ctypes.c_double), _ptr(out, ctypes.c_double)):
+        raise ValueError("bad dims")
+    return out
+
+
+def polyakov_correlator(dims, U, rmax):
+    """C(r) = mean over spatial sites xs and the three spatial directions i of
+    L(xs) L(xs + r e_i), r = 0 .. rmax (periodic), from polyakov_field."""
+    L0, L1, L2 = (int(v) for v in dims[:3])
+    F = polyakov_field(dims, U).reshape(L2, L1, L0)
+    out = np.empty(rmax + 1)
+    for r in range(rmax + 1):
+        out[r] = np.mean(F * (np.roll(F, -r, axis=2) + np.roll(F, -r, axis=1) + np.roll(F, -r, axis=0))) / 3.0
+    return out
 
 
 def staple_action(dims, U):

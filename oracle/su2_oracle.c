@@ -647,6 +647,25 @@ int oracle_polyakov(const int dims[4], const double *U, double *out)
     return 0;
 }
 
+/* The Polyakov loop at every spatial site: out[xs] = (1/2)Tr of the ordered
+ * product of U_3(xs, t), t = 0 .. L3-1, xs = x0 + L0 (x1 + L1 x2). */
+int oracle_polyakov_field(const int dims[4], const double *U, double *out)
+{
+    geom_t g;
+    if (geom_init(&g, dims)) return -1;
+    long Vs = (long)g.L[0] * g.L[1] * g.L[2];
+    for (long xs = 0; xs < Vs; ++xs) {
+        double P[4] = { 1.0, 0.0, 0.0, 0.0 };
+        for (int t = 0; t < g.L[3]; ++t) {
+            double r[4];
+            oracle_qmul(P, link(U, xs + Vs * t, 3), r);
+            memcpy(P, r, sizeof P);
+        }
+        out[xs] = P[0];
+    }
+    return 0;
+}
+
 /* Sum over all links of dot(U_mu(x), W_mu(x)) = (1/2)Tr(U W^dag); equals
  * 4 * 6V * plaquette on any configuration (each plaquette has four links). */
 int oracle_staple_action(const int dims[4], const double *U, double *out)

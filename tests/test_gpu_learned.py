@@ -257,3 +257,24 @@ def test_learned_wins_at_strong_coupling(lib, trained):
     assert fails[0] > 0 and fails[1] == 0
     assert acc / prop > 0.85
     assert rate[1] > 1.05 * rate[0]
+
+
+def test_learned_measured_sweeps_fused_plan(lib, trained):
+    """Measured sweeps with the learned proposal under the fused-pair plan:
+    links, proposal counts and heat-bath counters bit-identical to the
+    single-pass plan, the in-sweep plaquettes to 1e-13, on a lattice whose
+    (0, 1) sets take the block walk (64 x 64 planes) and one whose sets fit a
+    workgroup (12^4)."""
+    lib.su2_mlp_set_params(trained[1])
+    lib.su2_mlp_tabulate(31)
+    for dims in ((64, 64, 8, 8), (12, 12, 12, 12)):
+        out = {}
+        for plan in ((0, 0), (lib.FUSED_PAIRS, 0)):
+            lib.su2_init(dims, 2.3, 13, lib.HOT)
+            lib.su2_set_plan(*plan)
+            lib.su2_set_proposal(1)
+            h = lib.su2_sweep_measure(3, 1)
+            out[plan[0]] = (lib.su2_links(), lib.su2_imh_counters(), lib.su2_counters(), h)
+        a, b = out[0], out[lib.FUSED_PAIRS]
+        assert np.array_equal(a[0], b[0]) and a[1] == b[1] and a[2] == b[2], dims
+        np.testing.assert_allclose(b[3], a[3], rtol=0, atol=1e-13)

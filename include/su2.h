@@ -113,6 +113,13 @@ int su2_plaquette_st(double out[3]);
  * U_3(x, t), t = 0..L3-1.  FP32 products, FP64 reduction.  Synchronises. */
 int su2_polyakov(double *out);
 
+/* Polyakov-loop correlator for finite-temperature lattices (L3 = L_t the time
+ * extent, Sec. 2.4 and Table 1): out[r] (r = 0 .. rmax, rmax <= min(L0, L1,
+ * L2) / 2) = mean over spatial sites xs and the three spatial directions i of
+ * L(xs) L(xs + r e_i), L(xs) = (1/2)Tr of the ordered product of U_3(xs, t)
+ * over t (FP32 products, FP64 sums in a fixed order).  Synchronises. */
+int su2_polyakov_correlator(int32_t rmax, double *out);
+
 /* Enqueue the measurements of the current configuration without waiting:
  * dev_out[0..2] = (P, P_s, P_t) as su2_plaquette_st, dev_out[3] = the
  * Polyakov loop.  dev_out is caller-owned DEVICE memory (4 doubles, 8-byte

@@ -19,6 +19,63 @@
 
 using namespace su2;
 
+namespace su2 {
+
+// Polyakov loop at every spatial site xs = x0 + L0 (x1 + L1 x2): (1/2)Tr of the
+// ordered product of U_3(xs, t), t = 0 .. L3-1 (FP32 products), stored in FP64.
+__global__ __launch_bounds__(kBlock) void k_polyakov_field(const float4 *__restrict__ L, Geo g,
+                                                           uint32_t vs, double *__restrict__ field)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= vs) return;
+    const uint32_t x0 = i % g.L[0];
+    const uint32_t r = i / g.L[0];
+    const uint32_t x1 = r % g.L[1];
+    const uint32_t x2 = r / g.L[1];
+    float4 P = make_float4(1.f, 0.f, 0.f, 0.f);
+    for (uint32_t t = 0; t < g.L[3]; ++t) {
+        const uint32_t p = (x0 + x1 + x2 + t) & 1u;
+        const uint32_t h = (x0 >> 1) + x1 * g.st[1] + x2 * g.st[2] + t * g.st[3];
+        P = qmul(P, L[arr(g, 3, p) + h]);
+    }
+    field[i] = (double)P.x;
+}
+
+// partial[r * gridDim.x + b]: workgroup b's sum over its sites xs of
+// L(xs) (L(xs + r e0) + L(xs + r e1) + L(xs + r e2)), r = blockIdx.y
+__global__ __launch_bounds__(kBlock) void k_polyakov_corr(const double *__restrict__ field, Geo g,
+                                                          uint32_t vs, double *__restrict__ partial)
+{
+    const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t rr = blockIdx.y;
+    double acc = 0.0;
+    if (i < vs) {
+        const uint32_t x0 = i % g.L[0];
+        const uint32_t q = i / g.L[0];
+        const uint32_t x1 = q % g.L[1];
+        const uint32_t x2 = q / g.L[1];
+        const uint32_t y0 = (x0 + rr) % g.L[0], y1 = (x1 + rr) % g.L[1], y2 = (x2 + rr) % g.L[2];
+        const double n = field[y0 + g.L[0] * (x1 + g.L[1] * x2)] + field[x0 + g.L[0] * (y1 + g.L[1] * x2)] +
+                         field[x0 + g.L[0] * (x1 + g.L[1] * y2)];
+        acc = field[i] * n;
+    }
+    const double2 s = block_sum2(acc, 0.0);
+    if (threadIdx.x == 0) partial[(size_t)rr * gridDim.x + blockIdx.x] = s.x;
+}
+
+// out[r] = (sum of the nb partials of r, in order) / (3 vs); one workgroup per r
+__global__ __launch_bounds__(kBlock) void k_polyakov_corr_reduce(const double *__restrict__ partial,
+                                                                 uint32_t nb, uint32_t vs,
+                                                                 double *__restrict__ out)
+{
+    double a = 0.0;
+    for (uint32_t j = threadIdx.x; j < nb; j += kBlock) a += partial[(size_t)blockIdx.x * nb + j];
+    const double2 s = block_sum2(a, 0.0);
+    if (threadIdx.x == 0) out[blockIdx.x] = s.x / (3.0 * (double)vs);
+}
+
+}  // namespace su2
+
 namespace {
 
 constexpr int kGraphSweeps = 16;  // sweeps per replay of the large graph
@@ -453,6 +510,38 @@ int su2_polyakov(double *out)
     HIP_TRY(hipMemcpyAsync(o, ctx.d_out, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx.stream));
     HIP_TRY(hipStreamSynchronize(ctx.stream));
     *out = o[0];
+    return SU2_OK;
+}
+
+int su2_polyakov_correlator(int32_t rmax, double *out)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    const uint32_t lmin = std::min({ ctx.g.L[0], ctx.g.L[1], ctx.g.L[2] });
+    if (rmax < 0 || (uint32_t)rmax > lmin / 2)
+        return fail(SU2_EINVAL, "rmax must be in 0 .. min(L0, L1, L2) / 2 = %u", lmin / 2);
+    const uint32_t vs = ctx.g.L[0] * ctx.g.L[1] * ctx.g.L[2];
+    const uint32_t nb = (vs + kBlock - 1) / kBlock, nr = (uint32_t)rmax + 1;
+    double *d_field = nullptr, *d_part = nullptr, *d_res = nullptr;
+    if (hipMalloc(&d_field, (size_t)vs * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_part, (size_t)nb * nr * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_res, nr * sizeof(double)) != hipSuccess) {
+        hipGetLastError();
+        if (d_field) hipFree(d_field);
+        if (d_part) hipFree(d_part);
+        return fail(SU2_ENOMEM, "cannot allocate the Polyakov correlator buffers");
+    }
+    hipLaunchKernelGGL(k_polyakov_field, dim3(nb), dim3(kBlock), 0, ctx.stream, ctx.links, ctx.g, vs, d_field);
+    hipLaunchKernelGGL(k_polyakov_corr, dim3(nb, nr), dim3(kBlock), 0, ctx.stream, d_field, ctx.g, vs, d_part);
+    hipLaunchKernelGGL(k_polyakov_corr_reduce, dim3(nr), dim3(kBlock), 0, ctx.stream, d_part, nb, vs, d_res);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_res, nr * sizeof(double), hipMemcpyDeviceToHost, ctx.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
+    hipFree(d_field);
+    hipFree(d_part);
+    hipFree(d_res);
+    if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_polyakov_correlator: %s", hipGetErrorString(e));
     return SU2_OK;
 }
 

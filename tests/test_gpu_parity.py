@@ -437,3 +437,24 @@ def test_launch_plans_bit_identical(lib):
     assert lib.su2_counters() == c_ref
     with pytest.raises(lib.Su2Error):
         lib.su2_set_plan(3, 0)  # 3 does not divide L2 = 8
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 4, 10), (8, 8, 8, 4), (16, 16, 16, 8)])
+def test_polyakov_correlator_parity(lib, dims):
+    """C(r) of the GPU's configuration against the oracle's on the same links
+    (FP32 ordered products on the GPU, FP64 in the oracle), the cold lattice's
+    C = 1, and the range check on rmax."""
+    lib.su2_init(dims, 2.3, 4, lib.HOT)
+    lib.su2_sweep(3)
+    rmax = min(dims[:3]) // 2
+    got = lib.su2_polyakov_correlator(rmax)
+    U = lib.su2_links().astype(np.float64)
+    want = oracle.polyakov_correlator(dims, U, rmax)
+    print(f"Polyakov correlator {dims}: {np.array2string(got, precision=5)}; max diff {np.max(np.abs(got - want)):.1e}")
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-6)
+    lib.su2_init(dims, 2.3, 4, lib.COLD)
+    np.testing.assert_array_equal(lib.su2_polyakov_correlator(rmax), np.ones(rmax + 1))
+    with pytest.raises(lib.Su2Error):
+        lib.su2_polyakov_correlator(rmax + 1)
+    with pytest.raises(lib.Su2Error):
+        lib.su2_polyakov_correlator(-1)

@@ -47,17 +47,20 @@ def _load():
     lib.oracle_kp_draw.argtypes = [ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                    ctypes.c_int, ctypes.c_uint32, ctypes.c_int, dp, dp, dp]
     lib.oracle_kp_draw.restype = ctypes.c_int
+    lib.oracle_creutz_draw.argtypes = lib.oracle_kp_draw.argtypes
+    lib.oracle_creutz_draw.restype = ctypes.c_int
     lib.oracle_init.argtypes = [i32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, dp]
     lib.oracle_init.restype = ctypes.c_int
     lib.oracle_pass.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
-                                ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, i8p, dp, u64p]
+                                ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, i8p,
+                                dp, u64p]
     lib.oracle_pass.restype = ctypes.c_int
     lib.oracle_update_sites.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
-                                        ctypes.c_int, ctypes.c_int, dp,
+                                        ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
                                         ctypes.POINTER(ctypes.c_int64), ctypes.c_long, dp, i8p, dp]
     lib.oracle_update_sites.restype = ctypes.c_int
     lib.oracle_sweep.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
-                                 ctypes.c_int, dp, u64p]
+                                 ctypes.c_int, ctypes.c_double, dp, u64p]
     lib.oracle_sweep.restype = ctypes.c_int
     lib.oracle_plaquette.argtypes = [i32p, dp, dp]
     lib.oracle_plaquette.restype = ctypes.c_int
@@ -156,15 +159,24 @@ def staple(dims, U, lex, mu):
     return w
 
 
-def kp_draw(alpha, seed, site, mu, sweep, prec32=True):
-    """One capped KP draw.  Returns (attempt index or -1, x0, |a|, margin)."""
-    lib = _load()
+def _draw(fn, alpha, seed, site, mu, sweep, prec32):
     a0 = ctypes.c_double(np.nan)
     am = ctypes.c_double(np.nan)
     m = ctypes.c_double(np.nan)
-    t = lib.oracle_kp_draw(float(alpha), ctypes.c_uint64(seed), int(site), int(mu), int(sweep),
-                           int(bool(prec32)), ctypes.byref(a0), ctypes.byref(am), ctypes.byref(m))
+    t = fn(float(alpha), ctypes.c_uint64(seed), int(site), int(mu), int(sweep),
+           int(bool(prec32)), ctypes.byref(a0), ctypes.byref(am), ctypes.byref(m))
     return t, a0.value, am.value, m.value
+
+
+def kp_draw(alpha, seed, site, mu, sweep, prec32=True):
+    """One capped KP draw.  Returns (attempt index or -1, x0, |a|, margin)."""
+    return _draw(_load().oracle_kp_draw, alpha, seed, site, mu, sweep, prec32)
+
+
+def creutz_draw(alpha, seed, site, mu, sweep, prec32=True):
+    """One capped Creutz draw (the heat-bath below the small-alpha switch).
+    Returns (attempt index or -1, x0, |a|, margin)."""
+    return _draw(_load().oracle_creutz_draw, alpha, seed, site, mu, sweep, prec32)
 
 
 class PassResult:
@@ -175,8 +187,9 @@ class PassResult:
         self.failures = failures
 
 
-def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True):
-    """In-place heat-bath pass over links U_mu(x), parity(x) == parity."""
+def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True, creutz_below=0.0):
+    """In-place heat-bath pass over links U_mu(x), parity(x) == parity
+    (Creutz's draw where alpha < creutz_below)."""
     lib = _load()
     d = _dims(dims)
     if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
@@ -186,15 +199,15 @@ def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True):
     margin = np.full(V, np.nan)
     stats = np.zeros(2, dtype=np.uint64)
     rc = lib.oracle_pass(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed), int(sweep),
-                         int(parity), int(mu), int(bool(prec32)), _ptr(U, ctypes.c_double),
-                         _ptr(tries, ctypes.c_int8), _ptr(margin, ctypes.c_double),
+                         int(parity), int(mu), int(bool(prec32)), float(creutz_below),
+                         _ptr(U, ctypes.c_double), _ptr(tries, ctypes.c_int8), _ptr(margin, ctypes.c_double),
                          _ptr(stats, ctypes.c_uint64))
     if rc:
         raise ValueError("oracle_pass rejected its arguments")
     return PassResult(tries, margin, int(stats[0]), int(stats[1]))
 
 
-def update_sites(dims, U, beta, seed, sweep_index, mu, sites, prec32=True):
+def update_sites(dims, U, beta, seed, sweep_index, mu, sites, prec32=True, creutz_below=0.0):
     """New values of U_mu at the listed sites (one parity) as a pass at
     sweep_index would write them; U is not modified.  Returns (links [n,4],
     tries [n], margin [n])."""
@@ -207,7 +220,7 @@ def update_sites(dims, U, beta, seed, sweep_index, mu, sites, prec32=True):
     tries = np.full(n, -1, dtype=np.int8)
     margin = np.full(n, np.nan)
     rc = lib.oracle_update_sites(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
-                                 int(sweep_index), int(mu), int(bool(prec32)),
+                                 int(sweep_index), int(mu), int(bool(prec32)), float(creutz_below),
                                  _ptr(U, ctypes.c_double), _ptr(sites, ctypes.c_int64), n,
                                  _ptr(out, ctypes.c_double), _ptr(tries, ctypes.c_int8),
                                  _ptr(margin, ctypes.c_double))
@@ -260,7 +273,7 @@ def imh_sweep(dims, U, beta, seed, sweep_index, table, alpha_max=40.0, prec32=Tr
     return int(stats[0]), int(stats[1])
 
 
-def sweep(dims, U, beta, seed, sweep_index, prec32=True):
+def sweep(dims, U, beta, seed, sweep_index, prec32=True, creutz_below=0.0):
     """In-place full sweep; returns (attempts, cap failures)."""
     lib = _load()
     d = _dims(dims)
@@ -268,8 +281,8 @@ def sweep(dims, U, beta, seed, sweep_index, prec32=True):
         raise ValueError("U must be a C-contiguous float64 array")
     stats = np.zeros(2, dtype=np.uint64)
     rc = lib.oracle_sweep(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
-                          int(sweep_index), int(bool(prec32)), _ptr(U, ctypes.c_double),
-                          _ptr(stats, ctypes.c_uint64))
+                          int(sweep_index), int(bool(prec32)), float(creutz_below),
+                          _ptr(U, ctypes.c_double), _ptr(stats, ctypes.c_uint64))
     if rc:
         raise ValueError("oracle_sweep rejected its arguments")
     return int(stats[0]), int(stats[1])
@@ -357,11 +370,12 @@ class Chain:
     """A running oracle chain: links + sweep counter, mirroring the library's
     global context (init, sweep(n), plaquette, polyakov, links)."""
 
-    def __init__(self, dims, beta, seed, start, prec32=True):
+    def __init__(self, dims, beta, seed, start, prec32=True, creutz_below=0.0):
         self.dims = tuple(int(x) for x in dims)
         self.beta = float(beta)
         self.seed = int(seed)
         self.prec32 = bool(prec32)
+        self.creutz_below = float(creutz_below)
         self.U = init(dims, seed, start, prec32)
         self.s = 0
         self.attempts = 0
@@ -369,7 +383,7 @@ class Chain:
 
     def sweep(self, n=1):
         for _ in range(n):
-            a, f = sweep(self.dims, self.U, self.beta, self.seed, self.s, self.prec32)
+            a, f = sweep(self.dims, self.U, self.beta, self.seed, self.s, self.prec32, self.creutz_below)
             self.attempts += a
             self.failures += f
             self.s += 1

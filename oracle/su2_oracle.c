@@ -246,6 +246,56 @@ int oracle_kp_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t 
     return -1;
 }
 
+/* ------------------------------------------------------------------------- */
+/* Creutz's draw of x0 from the same density (M. Creutz, Phys. Rev. D 21       */
+/* (1980) 2308), used below a switch in alpha where Kennedy-Pendleton's        */
+/* acceptance collapses; same cap of 8 attempts and same slots, words u0, u1:  */
+/*   y = 1 - (1 - u0)(1 - exp(-2 alpha)) is uniform on [exp(-2 alpha), 1], so  */
+/*   x0 = 1 + ln(y) / alpha has density proportional to exp(alpha x0) on       */
+/*   [-1, 1]; accept iff u1 <= sqrt(1 - x0^2), i.e. u1^2 <= 1 - x0^2.          */
+/* (log1p and expm1 evaluate ln y and 1 - exp(-2 alpha) without cancellation.) */
+/* prec32 takes the decision in FP32 on m = 1 - x0, with 1 - x0^2 = m (2 - m). */
+/* Returns the accepting attempt (0..7) or -1; *margin as in oracle_kp_draw.   */
+/* ------------------------------------------------------------------------- */
+int oracle_creutz_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t sweep,
+                       int prec32, double *a0_out, double *amag_out, double *margin)
+{
+    double mg = INFINITY;
+    for (uint32_t t = 0; t < 8; ++t) {
+        double u[4];
+        draw4(seed, site, mu, PURPOSE_UPDATE, sweep, t, u);
+        double m, lhs, rhs;
+        if (prec32) {
+            float af = (float)alpha;
+            float d = (float)(-expm1(-2.0 * (double)af));
+            float z = -(1.0f - (float)u[0]) * d;
+            float mf = -(float)log1p((double)z) / af;
+            float u1f = (float)u[1];
+            float lf = u1f * u1f;
+            float rf = mf * (2.0f - mf);
+            m = (double)mf;
+            lhs = (double)lf;
+            rhs = (double)rf;
+        } else {
+            const double d = -expm1(-2.0 * alpha);  /* 1 - exp(-2 alpha) */
+            m = -log1p(-(1.0 - u[0]) * d) / alpha;
+            double x0 = 1.0 - m;
+            lhs = u[1] * u[1];
+            rhs = 1.0 - x0 * x0;
+        }
+        double dm = fabs(lhs - rhs);
+        if (dm < mg) mg = dm;
+        if (lhs <= rhs) {
+            *a0_out = 1.0 - m;
+            *amag_out = sqrt(m * (2.0 - m));
+            if (margin) *margin = mg;
+            return (int)t;
+        }
+    }
+    if (margin) *margin = mg;
+    return -1;
+}
+
 /* Uniform direction on S^2 from (u0, u1) of the direction slot
  * (Archimedes: cos(theta) uniform in [-1, 1]). */
 static void direction(uint64_t seed, uint32_t site, int mu, uint32_t sweep, double n[3])
@@ -302,14 +352,16 @@ int oracle_init(const int dims[4], uint64_t seed, int start, int prec32, double 
 /* One link update U_mu(x), written to out[4] (U itself is not modified):     */
 /*   w = staple sum; alpha = beta |w|;                                        */
 /*   alpha == 0: the conditional is Haar, draw it (slot 9);                   */
-/*   else KP for x0; after 8 failures the link is kept;                       */
+/*   else KP for x0 (Creutz's draw when alpha < creutz_below); after 8        */
+/*   failures the link is kept;                                               */
 /*   X = (x0, |a| n), V = w/|w|, U' = X V, normalised (Eqs. (5)-(7)).         */
 /* *tries = attempt that accepted (0..7), 8 after a cap failure, 9 for the    */
-/* Haar branch; *margin = the KP decision margin.                             */
+/* Haar branch; *margin = the smallest margin of the decisions taken (the     */
+/* accept tests and, with the switch on, |alpha - creutz_below|).             */
 /* ------------------------------------------------------------------------- */
 static void update_one(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int mu,
-                       int prec32, const double *U, long lex, double out[4], int *tries,
-                       double *margin)
+                       int prec32, double creutz_below, const double *U, long lex, double out[4],
+                       int *tries, double *margin)
 {
     double w[4];
     oracle_staple(dims, U, lex, mu, w);
@@ -325,7 +377,10 @@ static void update_one(const int dims[4], double beta, uint64_t seed, uint32_t s
         return;
     }
     double a0, amag;
-    int t = oracle_kp_draw(alpha, seed, (uint32_t)lex, mu, sweep, prec32, &a0, &amag, margin);
+    const int creutz = prec32 ? (float)alpha < (float)creutz_below : alpha < creutz_below;
+    int t = creutz ? oracle_creutz_draw(alpha, seed, (uint32_t)lex, mu, sweep, prec32, &a0, &amag, margin)
+                   : oracle_kp_draw(alpha, seed, (uint32_t)lex, mu, sweep, prec32, &a0, &amag, margin);
+    if (creutz_below > 0.0 && fabs(alpha - creutz_below) < *margin) *margin = fabs(alpha - creutz_below);
     if (t < 0) {
         memcpy(out, link(U, lex, mu), 4 * sizeof(double));
         *tries = 8;
@@ -345,11 +400,13 @@ static void update_one(const int dims[4], double beta, uint64_t seed, uint32_t s
  * Per-site outputs (optional, indexed by lex): tries[lex], margin[lex] as in
  * update_one.  stats[0] += KP attempts evaluated, stats[1] += cap failures. */
 int oracle_pass(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int parity,
-                int mu, int prec32, double *U, int8_t *tries, double *margin, uint64_t stats[2])
+                int mu, int prec32, double creutz_below, double *U, int8_t *tries, double *margin,
+                uint64_t stats[2])
 {
     geom_t g;
     if (geom_init(&g, dims)) return -1;
-    if (parity < 0 || parity > 1 || mu < 0 || mu > 3 || !(beta >= 0.0)) return -1;
+    if (parity < 0 || parity > 1 || mu < 0 || mu > 3 || !(beta >= 0.0) || !(creutz_below >= 0.0))
+        return -1;
     uint64_t attempts = 0, failures = 0;
 #pragma omp parallel for schedule(static) reduction(+ : attempts, failures)
     for (long lex = 0; lex < g.V; ++lex) {
@@ -358,7 +415,7 @@ int oracle_pass(const int dims[4], double beta, uint64_t seed, uint32_t sweep, i
         if (((x[0] + x[1] + x[2] + x[3]) & 1) != parity) continue;
         double out[4], m;
         int t;
-        update_one(dims, beta, seed, sweep, mu, prec32, U, lex, out, &t, &m);
+        update_one(dims, beta, seed, sweep, mu, prec32, creutz_below, U, lex, out, &t, &m);
         /* the staples of this pass never read the links it writes (they are
          * U_mu at the other parity, and U_nu with nu != mu), so writing in
          * place is the same as writing to a copy */
@@ -375,19 +432,20 @@ int oracle_pass(const int dims[4], double beta, uint64_t seed, uint32_t sweep, i
 /* The update a pass would give the listed sites (all of one parity), without
  * modifying U: out[i*4 .. i*4+3] for sites[i]; tries/margin optional. */
 int oracle_update_sites(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int mu,
-                        int prec32, const double *U, const int64_t *sites, long n, double *out,
-                        int8_t *tries, double *margin)
+                        int prec32, double creutz_below, const double *U, const int64_t *sites,
+                        long n, double *out, int8_t *tries, double *margin)
 {
     geom_t g;
     if (geom_init(&g, dims)) return -1;
-    if (mu < 0 || mu > 3 || !(beta >= 0.0)) return -1;
+    if (mu < 0 || mu > 3 || !(beta >= 0.0) || !(creutz_below >= 0.0)) return -1;
     for (long i = 0; i < n; ++i)
         if (sites[i] < 0 || sites[i] >= g.V) return -1;
 #pragma omp parallel for schedule(static)
     for (long i = 0; i < n; ++i) {
         double m;
         int t;
-        update_one(dims, beta, seed, sweep, mu, prec32, U, (long)sites[i], out + 4 * i, &t, &m);
+        update_one(dims, beta, seed, sweep, mu, prec32, creutz_below, U, (long)sites[i], out + 4 * i,
+                   &t, &m);
         if (tries) tries[i] = (int8_t)t;
         if (margin) margin[i] = m;
     }
@@ -436,7 +494,7 @@ static void update_one_imh(const int dims[4], double beta, uint64_t seed, uint32
     double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
     double alpha = beta * k;
     if (alpha == 0.0 || alpha > alpha_max) {
-        update_one(dims, beta, seed, sweep, mu, prec32, U, lex, out, res, margin);
+        update_one(dims, beta, seed, sweep, mu, prec32, 0.0, U, lex, out, res, margin);
         return;
     }
     double y[33];
@@ -538,11 +596,12 @@ int oracle_sweep_imh(const int dims[4], double beta, uint64_t seed, uint32_t swe
 /* One sweep (Sec. 2.4): odd sites for mu = 0..3, then even sites for
  * mu = 0..3; the Philox sweep index is `sweep` for all eight passes. */
 int oracle_sweep(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int prec32,
-                 double *U, uint64_t stats[2])
+                 double creutz_below, double *U, uint64_t stats[2])
 {
     for (int parity = 1; parity >= 0; --parity)
         for (int mu = 0; mu < 4; ++mu)
-            if (oracle_pass(dims, beta, seed, sweep, parity, mu, prec32, U, NULL, NULL, stats))
+            if (oracle_pass(dims, beta, seed, sweep, parity, mu, prec32, creutz_below, U, NULL, NULL,
+                            stats))
                 return -1;
     return 0;
 }

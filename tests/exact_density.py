@@ -59,3 +59,18 @@ def kp_accept_probability(alpha, n=400000):
     val, _ = integrate.quad(lambda s: np.sqrt(1.0 - s) * g.pdf(2.0 * alpha * s) * 2.0 * alpha,
                             0.0, 1.0, limit=400)
     return val
+
+
+def creutz_accept_probability(alpha):
+    """Probability that one Creutz attempt is accepted: the target's mass
+    pi I1(alpha) / alpha over the proposal's 2 sinh(alpha) / alpha."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    return np.pi * special.ive(1, alpha) / -np.expm1(-2.0 * alpha)
+
+
+def kp_accept_closed_form(alpha):
+    """The same for Kennedy-Pendleton in closed form: the accepted mass
+    (pi / 2) I1(alpha) e^-alpha / alpha over the Gamma(3/2) proposal's
+    Gamma(3/2) / (sqrt(2) alpha^(3/2)), i.e. sqrt(2 pi alpha) I1(alpha) e^-alpha."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    return np.sqrt(2.0 * np.pi * alpha) * special.ive(1, alpha)

@@ -334,6 +334,50 @@ def paper_table1(su2, therm=1000, meas=1000, every=5, beta=2.3):
             "runs": out}
 
 
+def strong_coupling(su2, therm=100, timed=200, meas=400, switch=1.6847376):
+    """Small beta on 32^4, hot start: plain Kennedy-Pendleton against the
+    heat-bath with Creutz's draw below alpha = switch (su2_set_creutz), each
+    with its tuned launch plan: link updates/s, attempts and cap failures per
+    update, and <P> beside the strong-coupling series u + 4 u^5, u =
+    I2(beta) / I1(beta).  KP's acceptance collapses as alpha -> 0; capped
+    updates keep their link."""
+    import numpy as np
+    import torch
+    from scipy import special
+    from paper_0903_3053_amd.stats import gamma_method
+    dims = (32, 32, 32, 32)
+    n_upd = 4 * int(np.prod(dims))
+    out = {"lattice": "32x32x32x32", "switch": switch}
+    for beta in (0.25, 0.5, 1.0):
+        u = special.iv(2, beta) / special.iv(1, beta)
+        row = {"series_plaquette": u + 4 * u ** 5}
+        for name, sw in (("kennedy_pendleton", 0.0), ("with_creutz_switch", switch)):
+            su2.su2_init(dims, beta, 1, 1)
+            su2.su2_set_creutz(sw)
+            plan = su2.su2_tune(2)
+            su2.su2_sweep(therm)
+            c0 = su2.su2_counters()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            su2.su2_sweep(timed)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c1 = su2.su2_counters()
+            hist = su2.su2_sweep_measure(meas, 1)
+            m, e, tau, _, _ = gamma_method(hist[:, 0])
+            row[name] = {"link_updates_per_s": n_upd * timed / dt,
+                         "attempts_per_update": (c1[0] - c0[0]) / (n_upd * timed),
+                         "cap_failures_per_update": (c1[1] - c0[1]) / (n_upd * timed),
+                         "plaquette": m, "plaquette_err": e,
+                         "z_vs_series": (m - row["series_plaquette"]) / e,
+                         "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}}
+        row["speedup"] = (row["with_creutz_switch"]["link_updates_per_s"]
+                          / row["kennedy_pendleton"]["link_updates_per_s"])
+        out[f"beta_{beta}"] = row
+    su2.su2_finalize()
+    return out
+
+
 def ising_2d():
     """The paper's other workload (Sec. 2.3): 2-D Ising Metropolis on a red-black
     partition, beta = 0.44 (near the critical point), hot start, on the paper's
@@ -474,6 +518,7 @@ def main():
         rec["batched_replicas"] = batched_replicas(su2)
         rec["learned_proposal"] = learned_proposal(su2)
         rec["overrelaxation"] = overrelaxation(su2)
+        rec["strong_coupling"] = strong_coupling(su2)
         rec["ising_2d"] = ising_2d()
         rec["paper_table1"] = paper_table1(su2)
     if not args.no_cpu_baseline:

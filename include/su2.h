@@ -16,7 +16,8 @@
  *     component 0 the identity part, 1..3 the i*sigma_j parts (Eq. (4)).
  *   - Random numbers: Philox-4x32-10, key = (seed mod 2^32, seed >> 32),
  *     counter = (lex, mu | purpose << 8, sweep index, slot); purpose 0 = heat
- *     bath (slots 0..7 attempts, 8 direction, 9 Haar draw at alpha = 0),
+ *     bath (slots 0..7 attempts -- Kennedy-Pendleton, or Creutz below the
+ *     su2_set_creutz switch -- 8 direction, 9 Haar draw at alpha = 0),
  *     1 = hot start, 2 = learned independence-Metropolis proposal.
  *
  * State: one global lattice context (no handle), created by su2_init /
@@ -239,6 +240,21 @@ const char *su2_mlp_last_error(void);
  * update) with the heat-bath for alpha = 0 and alpha above 40.  Kind 1 copies
  * the current knot table into the lattice context.  su2_init resets to 0. */
 int su2_set_proposal(int32_t kind);
+
+/* Small-alpha switch of the heat-bath (proposal 0): an update with 0 < alpha <
+ * alpha_below draws x0 by Creutz's method (Phys. Rev. D 21 (1980) 2308)
+ * instead of Kennedy-Pendleton's, with the same cap of 8 attempts and the same
+ * Philox slots: attempt t uses words (u0, u1) of slot t, m = -ln(1 - (1 - u0)
+ * (1 - exp(-2 alpha))) / alpha, x0 = 1 - m, accepted iff u1^2 <= m (2 - m);
+ * direction and rotation as before.  Kennedy-Pendleton's acceptance falls
+ * towards 0 as alpha -> 0 (at alpha = 0.25 about 35% of updates hit the cap
+ * and keep their link), Creutz's rises towards pi/4; the two accept equally
+ * often at alpha = 1.6847 (71%), the suggested switch.  alpha_below in [0, 4]
+ * (0 = off); su2_init resets it to 0; it applies to proposal 0 only (the
+ * learned proposal covers small alpha itself); a fused-pair plan sweeps as
+ * eight single passes while it is on.  Results stay a pure function of the
+ * inputs. */
+int su2_set_creutz(double alpha_below);
 
 /* Learned-proposal updates proposed and accepted since su2_set_proposal(1). */
 int su2_imh_counters(uint64_t out[2]);

@@ -107,6 +107,7 @@ struct Context {
     uint32_t *d_order = nullptr;        // device tile-order table of the plan
     int32_t order_kind = 0;
     int32_t proposal = 0;               // 0 heat-bath, 1 learned independence-Metropolis
+    float creutz_below = 0.0f;          // heat-bath: Creutz's draw for alpha below this
     float *d_table = nullptr;           // this lattice's copy of the knot table
     unsigned long long *d_imh_stats = nullptr;  // per wave: (proposals, accepts)
 };
@@ -810,7 +811,9 @@ int su2_set_proposal(int32_t kind)
         ctx.proposal = 0;
         ctx.plan.learned = false;
         ctx.plan.imh = ImhTable{};
+        ctx.plan.imh.creutz_below = ctx.creutz_below;
         ctx.plan.imh_lds_bytes = 0;
+        ctx.meas_fresh = false;  // the partials' layout follows pair_sweep(plan)
         release_graphs();
         return SU2_OK;
     }
@@ -845,8 +848,23 @@ int su2_set_proposal(int32_t kind)
     t.stats = ctx.d_imh_stats;
     ctx.proposal = 1;
     ctx.plan.learned = true;
-    ctx.plan.imh = t;
+    ctx.plan.imh = t;  // the Creutz switch is off under the learned proposal
     ctx.plan.imh_lds_bytes = kImhLdsBytes;
+    ctx.meas_fresh = false;
+    release_graphs();
+    return SU2_OK;
+}
+
+int su2_set_creutz(double alpha_below)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!(alpha_below >= 0.0 && alpha_below <= 4.0))
+        return fail(SU2_EINVAL, "the Creutz switch must lie in [0, 4]");
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    ctx.creutz_below = (float)alpha_below;
+    if (!ctx.plan.learned) ctx.plan.imh.creutz_below = ctx.creutz_below;
+    ctx.meas_fresh = false;  // the partials' layout follows pair_sweep(plan)
     release_graphs();
     return SU2_OK;
 }

@@ -395,9 +395,16 @@ static const void *pair_func(uint32_t mu, bool off32, bool measure, bool imh, bo
                    : pair_func_4<2, 3, false, false>(off32, imh, small);
 }
 
+// The pair kernels carry no Creutz draw: with the switch on, a fused plan's
+// sweep runs as eight k_pass launches in identity order.
+bool pair_sweep(const PassPlan &plan)
+{
+    return plan.fused && !(plan.imh.creutz_below > 0.0f);
+}
+
 uint32_t meas_partials(const Geo &g, const PassPlan &plan)
 {
-    return plan.fused ? plan.pg01.n_wg + plan.pg23.n_wg : 3u * pass_blocks(g);
+    return pair_sweep(plan) ? plan.pg01.n_wg + plan.pg23.n_wg : 3u * pass_blocks(g);
 }
 
 std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, float beta,
@@ -407,7 +414,7 @@ std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, flo
     std::vector<PassLaunch> out;
     // Sec. 2.4: odd sites for every direction, then even sites
     for (int p = 1; p >= 0; --p) {
-        if (!plan.fused) {
+        if (!pair_sweep(plan)) {
             for (uint32_t mu = 0; mu < 4; ++mu)
                 out.push_back(pass_launch(links, g, key, beta, (uint32_t)p, mu, sweep_ptr, counters,
                                           meas_out, plan));

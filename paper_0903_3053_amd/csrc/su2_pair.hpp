@@ -169,7 +169,7 @@ __device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, b
     before_update();
     const TileStaples in = staples_of(ld);
     double m = 0.0;
-    const float4 un = update_link<MU, OFF32, MEAS, IMH, true>(c.L, c.g, c.key, c.beta, c.p, c.s, h, valid,
+    const float4 un = update_link<MU, OFF32, MEAS, IMH, true, false>(c.L, c.g, c.key, c.beta, c.p, c.s, h, valid,
                                                               c.slot, in, c.counters, c.imh, m);
     acc_s += m;  // MU = 2: spatial planes (0, 2), (1, 2)
     return un;
@@ -253,7 +253,7 @@ __device__ __forceinline__ void pair_update2(const PairCtx &c, uint32_t pos, boo
         t.uold = IMH ? ld4<OFF32>(c.L + arr(g, NU, c.p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     double m = 0.0;
-    update_link<NU, OFF32, MEAS, IMH, false>(c.L, g, c.key, c.beta, c.p, c.s, h, valid, c.slot,
+    update_link<NU, OFF32, MEAS, IMH, false, false>(c.L, g, c.key, c.beta, c.p, c.s, h, valid, c.slot,
                                              staples_of(t), c.counters, c.imh, m);
     if (NU == 3u) acc_t += m; else acc_s += m;
 }

@@ -22,6 +22,10 @@ struct ImhTable {
     uint32_t G = 0;
     float alpha_max = 0.0f;
     float inv_step = 0.0f;                 // (G - 1) / alpha_max
+    // not part of the table: the plain heat-bath's switch to Creutz's draw
+    // (alpha below it; 0 = Kennedy-Pendleton throughout), carried here
+    // because every pass kernel receives this descriptor
+    float creutz_below = 0.0f;
     unsigned long long *stats = nullptr;   // per wave: (proposals, accepts)
 };
 
@@ -88,6 +92,26 @@ __device__ __forceinline__ bool kp_accept(float u3, float lam2)
 {
 #pragma clang fp contract(off)
     return u3 * u3 <= 1.0f - lam2;
+}
+
+// Creutz's draw (Phys. Rev. D 21 (1980) 2308), the better heat-bath at small
+// alpha: y uniform on [exp(-2 alpha), 1] makes x0 = 1 + ln(y) / alpha
+// distributed as exp(alpha x0) on [-1, 1], and the attempt is accepted with
+// probability sqrt(1 - x0^2).  Returns m = 1 - x0 = -ln(y) / alpha (so m / 2
+// plays the part of lambda^2) from y = 1 - (1 - u) (1 - exp(-2 alpha)),
+// written with expm1 and log1p so that m stays accurate as alpha -> 0.
+__device__ __forceinline__ float creutz_m(float u, float alpha)
+{
+#pragma clang fp contract(off)
+    const float d = -expm1f(-2.0f * alpha);
+    return -log1pf(-(1.0f - u) * d) / alpha;
+}
+
+// u1 <= sqrt(1 - x0^2) with 1 - x0^2 = m (2 - m)
+__device__ __forceinline__ bool creutz_accept(float u1, float m)
+{
+#pragma clang fp contract(off)
+    return u1 * u1 <= m * (2.0f - m);
 }
 
 // Block-level FP64 sum of two values: wave butterflies, then waves in order
@@ -247,8 +271,9 @@ __device__ __forceinline__ TileStaples staples_of(const TileLoad &in)
 // staple_nu) summed over nu < MU: over the three even passes this counts every
 // plaquette of the final configuration exactly once (planes (nu, MU), nu < MU),
 // so the plaquette of the sweep's result comes out of the sweep itself.  With
-// IMH the caller has made the staged knot table visible (a barrier).
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool KEEP>
+// IMH the caller has made the staged knot table visible (a barrier).  With
+// CREUTZ, lanes whose alpha is below imh.creutz_below draw Creutz's way.
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool KEEP, bool CREUTZ = true>
 __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo &g, Key key,
                                               float beta, uint32_t p, uint32_t s, uint32_t h,
                                               bool valid, uint32_t counter_slot,
@@ -272,6 +297,8 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
     bool imh_lane = false;
     if constexpr (IMH) imh_lane = valid && !haar_branch && alpha <= imh.alpha_max;
     bool done = !valid || haar_branch || imh_lane;
+    // below the switch the attempts draw Creutz's way (same cap, same slots)
+    const bool creutz = CREUTZ && alpha < imh.creutz_below;
     float lam2 = 0.0f;
     unsigned long long attempts = 0;
     for (uint32_t t = 0; t < 8u; ++t) {
@@ -280,10 +307,18 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
         attempts += __popcll(pending);
         if (!done) {
             const uint4 r = draw(key, lex, MU, kPurposeUpdate, s, t);
-            const float l = kp_lambda2(unit24(r.x), unit24(r.y), unit24(r.z), alpha);
-            if (kp_accept(unit24(r.w), l)) {
-                done = true;
-                lam2 = l;
+            if (creutz) {
+                const float m = creutz_m(unit24(r.x), alpha);
+                if (creutz_accept(unit24(r.y), m)) {
+                    done = true;
+                    lam2 = 0.5f * m;
+                }
+            } else {
+                const float l = kp_lambda2(unit24(r.x), unit24(r.y), unit24(r.z), alpha);
+                if (kp_accept(unit24(r.w), l)) {
+                    done = true;
+                    lam2 = l;
+                }
             }
         }
     }
@@ -383,8 +418,8 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
 
 // The updates of one tile (256 half-sites) of a pass; meas_out receives the
 // tile's FP64 plaquette partial (spatial planes, MU = 1, 2, in .x; temporal
-// planes, MU = 3, in .y).
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH>
+// planes, MU = 3, in .y).  CREUTZ as in update_link.
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool CREUTZ = true>
 __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g, Key key,
                                             float beta, uint32_t p, uint32_t s, uint32_t tile,
                                             const TileStaples &in,
@@ -394,8 +429,8 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
     const uint32_t h = tile * kBlock + threadIdx.x;
     if constexpr (IMH) __syncthreads();  // the staged table is complete
     double acc = 0.0;
-    update_link<MU, OFF32, MEASURE, IMH, false>(L, g, key, beta, p, s, h, h < g.half, h / kWave, in,
-                                                counters, imh, acc);
+    update_link<MU, OFF32, MEASURE, IMH, false, CREUTZ>(L, g, key, beta, p, s, h, h < g.half, h / kWave,
+                                                        in, counters, imh, acc);
     if constexpr (MEASURE) {
         const double2 r = block_sum2(acc, 0.0);
         if (threadIdx.x == 0)
@@ -405,8 +440,9 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
 
 
 // One tile of a pass: its loads, then its updates (the single-tile kernels and
-// the batched-replica kernels).
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH = false>
+// the batched-replica kernels, which take the heat-bath without the Creutz
+// switch).
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH = false, bool CREUTZ = true>
 __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, Key key,
                                           float beta, uint32_t p, uint32_t s, uint32_t tile,
                                           unsigned long long *__restrict__ counters,
@@ -415,8 +451,8 @@ __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, 
 {
     const TileLoad in = load_tile<MU, OFF32, IMH>(L, g, p, tile);
     if constexpr (IMH) stage_table(imh);
-    update_tile<MU, OFF32, MEASURE, IMH>(L, g, key, beta, p, s, tile, staples_of(in), counters,
-                                         meas_out, imh);
+    update_tile<MU, OFF32, MEASURE, IMH, CREUTZ>(L, g, key, beta, p, s, tile, staples_of(in), counters,
+                                                 meas_out, imh);
 }
 
 }  // namespace su2

@@ -17,6 +17,9 @@ LIBPATH = os.path.join(HERE, "libsu2.so")
 SU2_OK, SU2_EINVAL, SU2_ESTATE, SU2_ENOMEM, SU2_EDEVICE = 0, -1, -2, -3, -4
 COLD, HOT = 0, 1
 FUSED_PAIRS = 300  # su2_set_plan order kind: each parity as two fused launches
+# su2_set_creutz switch at which Kennedy-Pendleton and Creutz attempts are
+# accepted equally often (71%): sqrt(2 pi a) e^-a I1(a) = pi I1(a) / (2 sinh a)
+CREUTZ_SWITCH = 1.6847376
 
 # every symbol include/su2.h declares
 EXPORTS = (
@@ -29,7 +32,7 @@ EXPORTS = (
     "su2_batch_sweep_index", "su2_batch_last_error", "su2_batch_finalize",
     "su2_cdf_knots", "su2_mlp_set_params", "su2_mlp_get_params", "su2_mlp_forward",
     "su2_mlp_loss_grad", "su2_mlp_train", "su2_mlp_tabulate", "su2_mlp_table",
-    "su2_mlp_last_error", "su2_set_proposal", "su2_imh_counters",
+    "su2_mlp_last_error", "su2_set_proposal", "su2_set_creutz", "su2_imh_counters",
 )
 
 
@@ -108,6 +111,7 @@ def load():
         "su2_mlp_table": ([fp, ctypes.c_size_t], ctypes.c_int),
         "su2_mlp_last_error": ([], ctypes.c_char_p),
         "su2_set_proposal": ([ctypes.c_int32], ctypes.c_int),
+        "su2_set_creutz": ([ctypes.c_double], ctypes.c_int),
         "su2_imh_counters": ([u64p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -436,6 +440,11 @@ def su2_mlp_table():
 
 def su2_set_proposal(kind):
     _check(load().su2_set_proposal(int(kind)))
+
+
+def su2_set_creutz(alpha_below=CREUTZ_SWITCH):
+    """Heat-bath updates with alpha below alpha_below draw Creutz's way (0 = off)."""
+    _check(load().su2_set_creutz(float(alpha_below)))
 
 
 def su2_imh_counters():

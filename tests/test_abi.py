@@ -122,3 +122,4 @@ def test_extension_entry_points_reject_bad_arguments(lib):
     # the lattice is gone after su2_finalize: proposal selection is a state error
     lib.su2_finalize()
     assert lib.su2_set_proposal(1) == su2.SU2_ESTATE
+    assert lib.su2_set_creutz(ctypes.c_double(1.0)) == su2.SU2_ESTATE

@@ -251,9 +251,8 @@ int su2_set_proposal(int32_t kind);
  * and keep their link), Creutz's rises towards pi/4; the two accept equally
  * often at alpha = 1.6847 (71%), the suggested switch.  alpha_below in [0, 4]
  * (0 = off); su2_init resets it to 0; it applies to proposal 0 only (the
- * learned proposal covers small alpha itself); a fused-pair plan sweeps as
- * eight single passes while it is on.  Results stay a pure function of the
- * inputs. */
+ * learned proposal covers small alpha itself) and to every launch plan except
+ * the batched replicas'.  Results stay a pure function of the inputs. */
 int su2_set_creutz(double alpha_below);
 
 /* Learned-proposal updates proposed and accepted since su2_set_proposal(1). */

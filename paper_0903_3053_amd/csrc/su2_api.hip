@@ -813,7 +813,6 @@ int su2_set_proposal(int32_t kind)
         ctx.plan.imh = ImhTable{};
         ctx.plan.imh.creutz_below = ctx.creutz_below;
         ctx.plan.imh_lds_bytes = 0;
-        ctx.meas_fresh = false;  // the partials' layout follows pair_sweep(plan)
         release_graphs();
         return SU2_OK;
     }
@@ -850,7 +849,6 @@ int su2_set_proposal(int32_t kind)
     ctx.plan.learned = true;
     ctx.plan.imh = t;  // the Creutz switch is off under the learned proposal
     ctx.plan.imh_lds_bytes = kImhLdsBytes;
-    ctx.meas_fresh = false;
     release_graphs();
     return SU2_OK;
 }
@@ -864,7 +862,6 @@ int su2_set_creutz(double alpha_below)
     HIP_TRY(hipStreamSynchronize(ctx.stream));
     ctx.creutz_below = (float)alpha_below;
     if (!ctx.plan.learned) ctx.plan.imh.creutz_below = ctx.creutz_below;
-    ctx.meas_fresh = false;  // the partials' layout follows pair_sweep(plan)
     release_graphs();
     return SU2_OK;
 }

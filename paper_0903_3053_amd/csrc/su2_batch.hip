@@ -89,10 +89,10 @@ __device__ __forceinline__ void run_item(const BatchDev &b, const Rep &rep, uint
         const uint32_t tile = it * k + j;
         if (tile >= rep.tiles) break;  // uniform: the whole workgroup leaves together
         switch (mu) {
-        case 0: pass_tile<0, true, false, false, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
-        case 1: pass_tile<1, true, false, false, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
-        case 2: pass_tile<2, true, false, false, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
-        default: pass_tile<3, true, false, false, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
+        case 0: pass_tile<0, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
+        case 1: pass_tile<1, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
+        case 2: pass_tile<2, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
+        default: pass_tile<3, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{}); break;
         }
     }
 }

@@ -41,8 +41,9 @@ __global__ __launch_bounds__(kBlock) void k_init(float4 *__restrict__ links, Geo
 
 // One heat-bath pass over U_MU(x), parity(x) = p; each workgroup runs one tile.
 // A table can reorder tiles so that the workgroups the hardware sends to one
-// XCD share their neighbour data in L2.
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH>
+// XCD share their neighbour data in L2.  CREUTZ: the heat-bath with the
+// small-alpha switch (its own kernels, so the plain ones stay as they are).
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool CREUTZ>
 __global__ __launch_bounds__(kBlock) void k_pass(
     float4 *__restrict__ L, Geo g, Key key, float beta, uint32_t p,
     const uint32_t *__restrict__ sweep_ptr, unsigned long long *__restrict__ counters,
@@ -50,8 +51,8 @@ __global__ __launch_bounds__(kBlock) void k_pass(
     ImhTable imh)
 {
     const uint32_t tile = order ? order[blockIdx.x] : blockIdx.x;
-    pass_tile<MU, OFF32, MEASURE, IMH>(L, g, key, beta, p, *sweep_ptr, tile, counters, meas_out,
-                                       imh);
+    pass_tile<MU, OFF32, MEASURE, IMH, CREUTZ>(L, g, key, beta, p, *sweep_ptr, tile, counters, meas_out,
+                                               imh);
 }
 
 // One overrelaxation pass over U_MU(x), parity(x) = p: U -> V U^dag V with
@@ -250,27 +251,31 @@ hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_
 
 bool use_off32(const Geo &g) { return (uint64_t)g.half * 16u <= 0xffffffffull; }
 
-template <uint32_t MU, bool MEASURE, bool IMH>
-static const void *pass_func_3(bool off32)
+template <uint32_t MU, bool MEASURE, bool IMH, bool CREUTZ>
+static const void *pass_func_4(bool off32)
 {
-    return off32 ? reinterpret_cast<const void *>(&k_pass<MU, true, MEASURE, IMH>)
-                 : reinterpret_cast<const void *>(&k_pass<MU, false, MEASURE, IMH>);
+    return off32 ? reinterpret_cast<const void *>(&k_pass<MU, true, MEASURE, IMH, CREUTZ>)
+                 : reinterpret_cast<const void *>(&k_pass<MU, false, MEASURE, IMH, CREUTZ>);
 }
 
+// the learned proposal runs with the Creutz switch off
 template <uint32_t MU>
-static const void *pass_func_mu(bool off32, bool measure, bool imh)
+static const void *pass_func_mu(bool off32, bool measure, bool imh, bool creutz)
 {
-    if (imh) return measure ? pass_func_3<MU, true, true>(off32) : pass_func_3<MU, false, true>(off32);
-    return measure ? pass_func_3<MU, true, false>(off32) : pass_func_3<MU, false, false>(off32);
+    if (imh)
+        return measure ? pass_func_4<MU, true, true, false>(off32) : pass_func_4<MU, false, true, false>(off32);
+    if (creutz)
+        return measure ? pass_func_4<MU, true, false, true>(off32) : pass_func_4<MU, false, false, true>(off32);
+    return measure ? pass_func_4<MU, true, false, false>(off32) : pass_func_4<MU, false, false, false>(off32);
 }
 
-const void *pass_func(uint32_t mu, bool off32, bool measure, bool imh)
+const void *pass_func(uint32_t mu, bool off32, bool measure, bool imh, bool creutz)
 {
     switch (mu) {
-    case 0: return pass_func_mu<0>(off32, false, imh);  // no plaquette plane has nu < 0
-    case 1: return pass_func_mu<1>(off32, measure, imh);
-    case 2: return pass_func_mu<2>(off32, measure, imh);
-    default: return pass_func_mu<3>(off32, measure, imh);
+    case 0: return pass_func_mu<0>(off32, false, imh, creutz);  // no plaquette plane has nu < 0
+    case 1: return pass_func_mu<1>(off32, measure, imh, creutz);
+    case 2: return pass_func_mu<2>(off32, measure, imh, creutz);
+    default: return pass_func_mu<3>(off32, measure, imh, creutz);
     }
 }
 
@@ -330,7 +335,8 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
     pl.lds = plan.learned ? std::max(plan.lds_bytes, plan.imh_lds_bytes) : plan.lds_bytes;
     pl.order = plan.order;
     const bool measure = meas_out != nullptr && p == 0u && mu >= 1u;
-    pl.func = pass_func(mu, use_off32(g), measure, plan.learned);
+    pl.func = pass_func(mu, use_off32(g), measure, plan.learned,
+                        !plan.learned && plan.imh.creutz_below > 0.0f);
     pl.imh = plan.imh;
     pl.grid = dim3(pass_blocks(g));
     pl.block = dim3(kBlock);
@@ -368,43 +374,43 @@ bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo 
     return true;
 }
 
-template <uint32_t MU, uint32_t NU, bool MEAS1, bool MEAS2, bool OFF32, bool IMH>
-static const void *pair_func_6(bool small)
+template <uint32_t MU, uint32_t NU, bool MEAS1, bool MEAS2, bool OFF32, bool IMH, bool CREUTZ>
+static const void *pair_func_7(bool small)
 {
-    return small ? reinterpret_cast<const void *>(&k_pair_small<MU, NU, OFF32, MEAS1, MEAS2, IMH>)
-                 : reinterpret_cast<const void *>(&k_pair<MU, NU, OFF32, MEAS1, MEAS2, IMH>);
+    return small ? reinterpret_cast<const void *>(&k_pair_small<MU, NU, OFF32, MEAS1, MEAS2, IMH, CREUTZ>)
+                 : reinterpret_cast<const void *>(&k_pair<MU, NU, OFF32, MEAS1, MEAS2, IMH, CREUTZ>);
 }
 
+// The Creutz draw costs the pair kernels registers (their carried links are
+// live across the first update's attempts), so it gets kernels of its own:
+// the heat-bath ones without it stay as they are.  The learned proposal runs
+// with the switch off.
 template <uint32_t MU, uint32_t NU, bool MEAS1, bool MEAS2>
-static const void *pair_func_4(bool off32, bool imh, bool small)
+static const void *pair_func_4(bool off32, bool imh, bool creutz, bool small)
 {
     if (imh)
-        return off32 ? pair_func_6<MU, NU, MEAS1, MEAS2, true, true>(small)
-                     : pair_func_6<MU, NU, MEAS1, MEAS2, false, true>(small);
-    return off32 ? pair_func_6<MU, NU, MEAS1, MEAS2, true, false>(small)
-                 : pair_func_6<MU, NU, MEAS1, MEAS2, false, false>(small);
+        return off32 ? pair_func_7<MU, NU, MEAS1, MEAS2, true, true, false>(small)
+                     : pair_func_7<MU, NU, MEAS1, MEAS2, false, true, false>(small);
+    if (creutz)
+        return off32 ? pair_func_7<MU, NU, MEAS1, MEAS2, true, false, true>(small)
+                     : pair_func_7<MU, NU, MEAS1, MEAS2, false, false, true>(small);
+    return off32 ? pair_func_7<MU, NU, MEAS1, MEAS2, true, false, false>(small)
+                 : pair_func_7<MU, NU, MEAS1, MEAS2, false, false, false>(small);
 }
 
 // (0, 1) measures through its U_1 updates; (2, 3) through both passes
-static const void *pair_func(uint32_t mu, bool off32, bool measure, bool imh, bool small)
+static const void *pair_func(uint32_t mu, bool off32, bool measure, bool imh, bool creutz, bool small)
 {
     if (mu == 0u)
-        return measure ? pair_func_4<0, 1, false, true>(off32, imh, small)
-                       : pair_func_4<0, 1, false, false>(off32, imh, small);
-    return measure ? pair_func_4<2, 3, true, true>(off32, imh, small)
-                   : pair_func_4<2, 3, false, false>(off32, imh, small);
-}
-
-// The pair kernels carry no Creutz draw: with the switch on, a fused plan's
-// sweep runs as eight k_pass launches in identity order.
-bool pair_sweep(const PassPlan &plan)
-{
-    return plan.fused && !(plan.imh.creutz_below > 0.0f);
+        return measure ? pair_func_4<0, 1, false, true>(off32, imh, creutz, small)
+                       : pair_func_4<0, 1, false, false>(off32, imh, creutz, small);
+    return measure ? pair_func_4<2, 3, true, true>(off32, imh, creutz, small)
+                   : pair_func_4<2, 3, false, false>(off32, imh, creutz, small);
 }
 
 uint32_t meas_partials(const Geo &g, const PassPlan &plan)
 {
-    return pair_sweep(plan) ? plan.pg01.n_wg + plan.pg23.n_wg : 3u * pass_blocks(g);
+    return plan.fused ? plan.pg01.n_wg + plan.pg23.n_wg : 3u * pass_blocks(g);
 }
 
 std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, float beta,
@@ -414,7 +420,7 @@ std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, flo
     std::vector<PassLaunch> out;
     // Sec. 2.4: odd sites for every direction, then even sites
     for (int p = 1; p >= 0; --p) {
-        if (!pair_sweep(plan)) {
+        if (!plan.fused) {
             for (uint32_t mu = 0; mu < 4; ++mu)
                 out.push_back(pass_launch(links, g, key, beta, (uint32_t)p, mu, sweep_ptr, counters,
                                           meas_out, plan));
@@ -429,7 +435,8 @@ std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, flo
             pl.lds = plan.learned ? std::max(plan.lds_bytes, plan.imh_lds_bytes) : plan.lds_bytes;
             pl.order = nullptr;
             const bool small = pg.n_t <= kPairLanes;
-            pl.func = pair_func(mu, use_off32(g), measure, plan.learned, small);
+            pl.func = pair_func(mu, use_off32(g), measure, plan.learned,
+                                !plan.learned && plan.imh.creutz_below > 0.0f, small);
             pl.imh = plan.imh;
             pl.grid = dim3(pg.n_wg);
             pl.block = dim3(small ? (pg.n_t + kWave - 1u) / kWave * kWave : kBlock);

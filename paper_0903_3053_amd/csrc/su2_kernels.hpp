@@ -84,15 +84,12 @@ constexpr int kFusedPairs = 300;
 // lattice does not fit them (L0 > 256).
 bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo &pg23);
 // The launches of one sweep in order (odd parity, then even): eight k_pass,
-// or four k_pair when pair_sweep(plan).  meas_out != nullptr: the even-parity
+// or four k_pair when plan.fused.  meas_out != nullptr: the even-parity
 // launches leave their plaquette partials in meas_out (meas_partials of them).
 std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, float beta,
                                        const uint32_t *sweep_ptr, unsigned long long *counters,
                                        double2 *meas_out, const PassPlan &plan);
 uint32_t meas_partials(const Geo &g, const PassPlan &plan);
-// Whether sweep_launches gives k_pair launches (a fused plan with the Creutz
-// switch off).
-bool pair_sweep(const PassPlan &plan);
 // One overrelaxation pass (parity p, direction mu) with the plan's tile order
 // and LDS reservation (the identity order under the fused-pair plan).
 PassLaunch or_launch(float4 *links, const Geo &g, uint32_t p, uint32_t mu, const PassPlan &plan);

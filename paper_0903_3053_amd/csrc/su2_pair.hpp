@@ -157,7 +157,7 @@ __device__ __forceinline__ void carry_of(const TileLoad &ld, PairCarry &cr)
 // returns the new link and adds the plaquette terms it measures to acc_s.
 // before_update(), called by every lane once the update's loads are issued,
 // may stage the knot table and wait for it (the loads stay in flight).
-template <uint32_t MU, bool OFF32, bool MEAS, bool IMH, bool CARRY, typename Hook>
+template <uint32_t MU, bool OFF32, bool MEAS, bool IMH, bool CARRY, bool CREUTZ, typename Hook>
 __device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, bool valid, double &acc_s,
                                                Hook before_update, PairCarry &carry)
 {
@@ -169,7 +169,7 @@ __device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, b
     before_update();
     const TileStaples in = staples_of(ld);
     double m = 0.0;
-    const float4 un = update_link<MU, OFF32, MEAS, IMH, true, false>(c.L, c.g, c.key, c.beta, c.p, c.s, h, valid,
+    const float4 un = update_link<MU, OFF32, MEAS, IMH, true, CREUTZ>(c.L, c.g, c.key, c.beta, c.p, c.s, h, valid,
                                                               c.slot, in, c.counters, c.imh, m);
     acc_s += m;  // MU = 2: spatial planes (0, 2), (1, 2)
     return un;
@@ -225,7 +225,7 @@ __device__ __forceinline__ StapleLinks plane_carried(const PairCtx &c, uint32_t 
 // The U_NU update at position pos; fresh(q) is the new U_MU at position q;
 // carry (one lane per site) holds the links the U_MU update at pos loaded
 // that this one reads again.
-template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS, bool IMH, bool CARRY, typename Fresh>
+template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS, bool IMH, bool CARRY, bool CREUTZ, typename Fresh>
 __device__ __forceinline__ void pair_update2(const PairCtx &c, uint32_t pos, bool valid, Fresh fresh,
                                              double &acc_s, double &acc_t, const PairCarry &carry)
 {
@@ -253,7 +253,7 @@ __device__ __forceinline__ void pair_update2(const PairCtx &c, uint32_t pos, boo
         t.uold = IMH ? ld4<OFF32>(c.L + arr(g, NU, c.p), h) : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     double m = 0.0;
-    update_link<NU, OFF32, MEAS, IMH, false, false>(c.L, g, c.key, c.beta, c.p, c.s, h, valid, c.slot,
+    update_link<NU, OFF32, MEAS, IMH, false, CREUTZ>(c.L, g, c.key, c.beta, c.p, c.s, h, valid, c.slot,
                                              staples_of(t), c.counters, c.imh, m);
     if (NU == 3u) acc_t += m; else acc_s += m;
 }
@@ -303,7 +303,7 @@ __device__ __forceinline__ void stage_table_any(const ImhTable &imh)
 // every U_MU update, one barrier, every U_NU update.
 constexpr uint32_t kPairLanes = 1024;
 
-template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS1, bool MEAS2, bool IMH>
+template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS1, bool MEAS2, bool IMH, bool CREUTZ>
 __global__ __launch_bounds__(kPairLanes) void k_pair_small(
     float4 *__restrict__ L, Geo g, PairGeo pg, Key key, float beta, uint32_t p,
     const uint32_t *__restrict__ sweep_ptr, unsigned long long *__restrict__ counters,
@@ -321,7 +321,7 @@ __global__ __launch_bounds__(kPairLanes) void k_pair_small(
     // the knot table's copy goes out behind the first pass's loads; the links
     // both updates of a site read stay in registers
     PairCarry carry;
-    const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, true>(c, pos, valid, acc_s, [&] {
+    const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, true, CREUTZ>(c, pos, valid, acc_s, [&] {
         if constexpr (IMH) {
             stage_table_any(imh);
             __syncthreads();
@@ -329,8 +329,8 @@ __global__ __launch_bounds__(kPairLanes) void k_pair_small(
     }, carry);
     if (valid) buf[pos] = un;
     __syncthreads();
-    pair_update2<MU, NU, OFF32, MEAS2, IMH, true>(c, valid ? pos : 0u, valid,
-                                                  [&](uint32_t q) { return buf[q]; }, acc_s, acc_t, carry);
+    pair_update2<MU, NU, OFF32, MEAS2, IMH, true, CREUTZ>(c, valid ? pos : 0u, valid,
+                                                          [&](uint32_t q) { return buf[q]; }, acc_s, acc_t, carry);
     if constexpr (MEAS1 || MEAS2) {
         const double2 r = block_sum2_any(acc_s, acc_t);
         if (threadIdx.x == 0) meas_out[w] = r;
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(kPairLanes) void k_pair_small(
 
 // Larger sets, block by block with 256 threads: the U_NU updates trail the
 // U_MU updates by `lag` positions.
-template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS1, bool MEAS2, bool IMH>
+template <uint32_t MU, uint32_t NU, bool OFF32, bool MEAS1, bool MEAS2, bool IMH, bool CREUTZ>
 __global__ __launch_bounds__(kBlock) void k_pair(
     float4 *__restrict__ L, Geo g, PairGeo pg, Key key, float beta, uint32_t p,
     const uint32_t *__restrict__ sweep_ptr, unsigned long long *__restrict__ counters,
@@ -360,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(
         if (b < pg.nblk) {
             const uint32_t pos = b * kBlock + threadIdx.x;
             // block 0: the knot table's copy goes out behind its loads
-            const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, false>(c, pos, pos < pg.n_t, acc_s, [&] {
+            const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, false, CREUTZ>(c, pos, pos < pg.n_t, acc_s, [&] {
                 if constexpr (IMH) {
                     if (b == 0u) {
                         stage_table(imh);
@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_pair(
         // the NU pass on positions [b * kBlock - lag, (b + 1) * kBlock - lag)
         const int ipos = (int)(b * kBlock + threadIdx.x) - (int)pg.lag;
         const bool valid = ipos >= 0 && (uint32_t)ipos < pg.n_t;
-        pair_update2<MU, NU, OFF32, MEAS2, IMH, false>(c, valid ? (uint32_t)ipos : 0u, valid, [&](uint32_t q) {
+        pair_update2<MU, NU, OFF32, MEAS2, IMH, false, CREUTZ>(c, valid ? (uint32_t)ipos : 0u, valid, [&](uint32_t q) {
             const uint32_t blk = q / kBlock;
             return buf[(blk == b || blk + 1u == b) ? (blk & 1u) * kBlock + q % kBlock
                                                    : 2u * kBlock + q % kBlock];

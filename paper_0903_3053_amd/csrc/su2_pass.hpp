@@ -273,7 +273,7 @@ __device__ __forceinline__ TileStaples staples_of(const TileLoad &in)
 // so the plaquette of the sweep's result comes out of the sweep itself.  With
 // IMH the caller has made the staged knot table visible (a barrier).  With
 // CREUTZ, lanes whose alpha is below imh.creutz_below draw Creutz's way.
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool KEEP, bool CREUTZ = true>
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool KEEP, bool CREUTZ = false>
 __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo &g, Key key,
                                               float beta, uint32_t p, uint32_t s, uint32_t h,
                                               bool valid, uint32_t counter_slot,
@@ -419,7 +419,7 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
 // The updates of one tile (256 half-sites) of a pass; meas_out receives the
 // tile's FP64 plaquette partial (spatial planes, MU = 1, 2, in .x; temporal
 // planes, MU = 3, in .y).  CREUTZ as in update_link.
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool CREUTZ = true>
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH, bool CREUTZ = false>
 __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g, Key key,
                                             float beta, uint32_t p, uint32_t s, uint32_t tile,
                                             const TileStaples &in,
@@ -442,7 +442,7 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
 // One tile of a pass: its loads, then its updates (the single-tile kernels and
 // the batched-replica kernels, which take the heat-bath without the Creutz
 // switch).
-template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH = false, bool CREUTZ = true>
+template <uint32_t MU, bool OFF32, bool MEASURE, bool IMH = false, bool CREUTZ = false>
 __device__ __forceinline__ void pass_tile(float4 *__restrict__ L, const Geo &g, Key key,
                                           float beta, uint32_t p, uint32_t s, uint32_t tile,
                                           unsigned long long *__restrict__ counters,

@@ -3,7 +3,7 @@ same cap and Philox slots) through the C ABI against the oracle: single
 passes element by element (<= 1e-5 per component, flips only where the oracle
 reports a decision margin below 1e-5, which includes alpha within 1e-5 of the
 switch), counters exact without flips; sweeps from the oracle's state; the
-fused-pair plan, which sweeps as single passes while the switch is on; and a
+fused-pair kernels' Creutz variants, bit-identical to the single passes; and a
 strong-coupling chain on the GPU against <P> = u + 4 u^5, u = I2/I1."""
 import numpy as np
 import pytest
@@ -89,30 +89,33 @@ def test_sweeps_from_oracle_state(lib):
     assert abs(att_g - att_o) <= 8 * off
 
 
-@pytest.mark.parametrize("dims", [(8, 6, 10, 4), (16, 16, 16, 16)])
+@pytest.mark.parametrize("dims", [(8, 6, 10, 4), (2, 4, 2, 6), (16, 16, 16, 16), (32, 8, 6, 10)])
 def test_fused_plan_with_switch(lib, dims):
-    """Under the fused-pair plan the switch runs the sweep as eight single
-    passes: links and counters bit-identical to plan 0 with the switch, the
-    measured sweep's plaquette equal to the plaquette kernel's; switching it
-    off again brings the fused launches back (bit-identical to plan 0)."""
+    """The fused-pair kernels' Creutz variants against the single passes with
+    the switch: links and counters bit-identical after three sweeps (the last
+    measured), the in-sweep plaquette to 1e-13 and to the plaquette kernel;
+    with the switch off again the fused heat-bath kernels are back
+    (bit-identical to the single passes)."""
     beta, seed, sw = 0.8, 12, 1.6847376
     lib.su2_init(dims, beta, seed, lib.HOT)
     lib.su2_set_creutz(sw)
     lib.su2_sweep(2)
+    m_ref = lib.su2_sweep_measure(1, 1)
     ref, c_ref = lib.su2_links(), lib.su2_counters()
     lib.su2_init(dims, beta, seed, lib.HOT)
     lib.su2_set_plan(lib.FUSED_PAIRS, 0)
     lib.su2_set_creutz(sw)
-    lib.su2_sweep(1)
+    lib.su2_sweep(2)
     m = lib.su2_sweep_measure(1, 1)
     assert np.array_equal(lib.su2_links(), ref)
     assert lib.su2_counters() == c_ref
+    np.testing.assert_allclose(m, m_ref, rtol=0, atol=1e-13)
     np.testing.assert_allclose(lib.su2_plaquette_st(), m[0], rtol=0, atol=2e-6)
     lib.su2_set_creutz(0.0)
     lib.su2_sweep(1)
     after_fused = lib.su2_links()
     lib.su2_set_plan(0, 0)
-    lib.su2_set_links(ref, 2)
+    lib.su2_set_links(ref, 3)
     lib.su2_sweep(1)
     assert np.array_equal(lib.su2_links(), after_fused)
 

@@ -384,24 +384,33 @@ def strong_coupling(su2, therm=100, timed=200, meas=400, switch=1.6847376):
 def ising_2d():
     """The paper's other workload (Sec. 2.3): 2-D Ising Metropolis on a red-black
     partition, beta = 0.44 (near the critical point), hot start, on the paper's
-    1024 x 512 lattice and on 16384^2; spin updates/s with the lattice resident
-    on the device.  The paper quotes 630 s for 10^6 sweeps of 1024 x 512 on
-    ATI RV770 (8.3e8 spin updates/s), as context only."""
+    1024 x 512 lattice and on 16384^2, in both device layouts (a byte per spin;
+    1-bit spins, 32 per word, the default where L0 % 64 == 0 and N >= 2^20); spin updates/s
+    with the lattice resident on the device (both layouts run the same chain).
+    Algorithmic bytes per spin update: 3 (bytes: own colour read and written,
+    other colour read) or 3/8 (bits).  The paper quotes 630 s for 10^6 sweeps
+    of 1024 x 512 on ATI RV770 (8.3e8 spin updates/s), as context only."""
     import torch
     from paper_0903_3053_amd import ising
     out = {}
     for dims, n in (((1024, 512), 2000), ((16384, 16384), 50)):
-        ising.ising_init(dims, 0.44, 1, 1)
-        ising.ising_sweep(10)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ising.ising_sweep(n)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        N = dims[0] * dims[1]
-        e, m = ising.ising_observables()
-        out[f"{dims[0]}x{dims[1]}"] = {"spin_updates_per_s": N * n / dt, "us_per_sweep": dt / n * 1e6,
-                                       "sweeps": n, "energy_per_site": e, "magnetisation": m}
+        row = {}
+        for name, layout, bytes_per in (("bytes", ising.LAYOUT_BYTES, 3.0), ("bits", ising.LAYOUT_BITS, 0.375)):
+            ising.ising_init(dims, 0.44, 1, 1, layout)
+            ising.ising_sweep(10)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ising.ising_sweep(n)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            N = dims[0] * dims[1]
+            e, m = ising.ising_observables()
+            rate = N * n / dt
+            row[name] = {"spin_updates_per_s": rate, "us_per_sweep": dt / n * 1e6, "sweeps": n,
+                         "energy_per_site": e, "magnetisation": m,
+                         "algorithmic_GBps": rate * bytes_per / 1e9}
+        row["bits_over_bytes"] = row["bits"]["spin_updates_per_s"] / row["bytes"]["spin_updates_per_s"]
+        out[f"{dims[0]}x{dims[1]}"] = row
     ising.ising_finalize()
     out["paper_context"] = {"hardware": "ATI RV770", "lattice": "1024x512",
                             "seconds_per_1e6_sweeps": 630, "spin_updates_per_s": 524288 * 1e6 / 630}

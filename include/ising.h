@@ -27,9 +27,25 @@
 extern "C" {
 #endif
 
+/* Device layout of the spins (results do not depend on it): bytes = one int8
+ * per spin, one array per colour indexed by h; bits = the paper's 1-bit spins
+ * (Sec. 2.3), bit b of word w of a colour holding half index h = 32 w + b
+ * (set = spin -1), 16x less memory, updated 32 sites per lane with bitwise
+ * arithmetic; needs L0 a multiple of 64.  Auto takes bits where they fit
+ * and the lattice holds at least 2^20 spins (below that both run at the
+ * ~9 us launch floor per sweep and bytes fill the device better). */
+enum { ISING_LAYOUT_AUTO = 0, ISING_LAYOUT_BYTES = 1, ISING_LAYOUT_BITS = 2 };
+
 /* dims = {L0, L1}: each even and >= 2, L0 * L1 < 2^32; beta finite and >= 0;
- * start 0 = cold, 1 = hot.  Sweep index 0, acceptance counter 0. */
+ * start 0 = cold, 1 = hot.  Sweep index 0, acceptance counter 0.  Layout
+ * auto. */
 int ising_init(const int32_t dims[2], double beta, uint64_t seed, int32_t start);
+
+/* ising_init with a chosen layout (SU2_EINVAL for bits unless L0 % 64 == 0). */
+int ising_init_ex(const int32_t dims[2], double beta, uint64_t seed, int32_t start, int32_t layout);
+
+/* The layout in use (ISING_LAYOUT_BYTES or ISING_LAYOUT_BITS). */
+int ising_layout(int32_t *out);
 
 /* n >= 0 Metropolis sweeps (replayed from a hipGraph); the sweep index
  * advances by n (SU2_EINVAL if it would pass 2^32 - 1). */

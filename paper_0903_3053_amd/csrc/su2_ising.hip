@@ -1,14 +1,16 @@
 // su2_ising.hip -- the 2-D Ising workload (Sec. 2.3, Eq. (1)): Metropolis on a
 // red-black partition of an L0 x L1 periodic lattice, behind include/ising.h.
 //
-// Layout: one int8 array per colour, N/2 bytes each, indexed by the half index
-// h = x/2 + (L0/2) y (a row of one colour is contiguous).  The paper packs
-// 1-bit spins of a "direct-dual" cell into four-component registers
-// (Sec. 2.3, Fig. 2) to save fetches on RV770; on MI355X a byte per spin is
-// already far below what the random numbers cost, so spins stay plain bytes.
-// Each lane updates four consecutive half-sites of one colour from one
-// Philox-4x32-10 call (one 32-bit word each), so the generator's output is
-// used whole.
+// Two layouts, chosen at init.  Bytes: one int8 array per colour, N/2 bytes
+// each, indexed by the half index h = x/2 + (L0/2) y (a row of one colour is
+// contiguous); each lane updates four consecutive half-sites from one
+// Philox-4x32-10 call (one 32-bit word each).  Bits (L0 a multiple of 64): the
+// paper's 1-bit spins (Sec. 2.3), 32 same-colour spins of a row per 32-bit
+// word, bit b of word w of a colour holding half index h = 32 w + b (set = spin
+// -1); a lane updates a word with bitwise arithmetic -- the four neighbour
+// words, the anti-aligned count per bit as bit masks -- and eight Philox calls.
+// Both layouts draw the same words for the same sites, so they give the same
+// chain bit for bit.
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -31,7 +33,8 @@ constexpr uint32_t kAccSlots = 4096;
 
 struct IsingGeo {
     uint32_t L0, L1, H0, half;  // H0 = L0/2, half = N/2
-    FastDiv dH0;
+    uint32_t W, nw;             // bit layout: words per row of one colour (H0/32), words per colour
+    FastDiv dH0, dW;
 };
 
 // site (x, y) of colour c at half index h
@@ -105,6 +108,151 @@ __global__ __launch_bounds__(kIsingBlock) void k_ising_pass(int8_t *__restrict__
         atomicAdd(&accepted[(blockIdx.x * (kIsingBlock / kIsingWave) + threadIdx.x / kIsingWave) % kAccSlots], n);
 }
 
+// ---------------------------------------------------------------------------
+// Bit layout
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kIsingBlock) void k_ising_init_bits(uint32_t *__restrict__ P, IsingGeo g, Key key,
+                                                                 int hot)
+{
+    const uint32_t w = blockIdx.x * kIsingBlock + threadIdx.x;  // word of colour c: half indices 32 w ..
+    const uint32_t c = blockIdx.y;
+    if (w >= g.nw) return;
+    uint32_t bits = 0u;
+    if (hot) {
+#pragma unroll
+        for (uint32_t q = 0; q < 8u; ++q) {
+            const uint4 r = philox(make_uint4(8u * w + q, c | (kPurposeIsingHot << 8), 0u, 0u), key);
+            bits |= ((r.x >> 31) | ((r.y >> 31) << 1) | ((r.z >> 31) << 2) | ((r.w >> 31) << 3)) << (4u * q);
+        }
+    }
+    P[(size_t)c * g.nw + w] = bits;
+}
+
+// The four neighbour words of word w of colour c (row y, word k of the row):
+// the other colour's spins at the same half index in rows y - 1, y, y + 1,
+// and the row's other horizontal neighbour, one half index to the left
+// ((c + y) even: x = 2 j, neighbours x +- 1 at j and j - 1) or to the right
+// ((c + y) odd: at j and j + 1), shifted in from the next word.
+struct BitNbrs {
+    uint32_t mid, side, up, dn;
+};
+
+__device__ __forceinline__ BitNbrs bit_neighbours(const uint32_t *__restrict__ oth, const IsingGeo &g,
+                                                  uint32_t c, uint32_t w)
+{
+    const uint32_t y = fdiv(w, g.dW), k = w - y * g.W;
+    const uint32_t yp = y + 1u == g.L1 ? 0u : y + 1u, ym = y == 0u ? g.L1 - 1u : y - 1u;
+    const bool right = ((c + y) & 1u) != 0u;
+    const uint32_t kn = right ? (k + 1u == g.W ? 0u : k + 1u) : (k == 0u ? g.W - 1u : k - 1u);
+    BitNbrs n;
+    n.mid = oth[w];
+    const uint32_t nb = oth[y * g.W + kn];
+    n.up = oth[yp * g.W + k];
+    n.dn = oth[ym * g.W + k];
+    n.side = right ? (n.mid >> 1) | (nb << 31) : (n.mid << 1) | (nb >> 31);
+    return n;
+}
+
+// One colour, one word (32 sites) per lane.  With n the number of
+// anti-aligned neighbours of a site, dE = 8 - 4 n: n >= 2 always flips, n = 1
+// flips iff its word is below T4, n = 0 iff below T8.
+__global__ __launch_bounds__(kIsingBlock) void k_ising_pass_bits(uint32_t *__restrict__ P, IsingGeo g, Key key,
+                                                                 uint32_t c, const uint32_t *__restrict__ sweep_ptr,
+                                                                 uint32_t T4, uint32_t T8,
+                                                                 unsigned long long *__restrict__ accepted)
+{
+    const uint32_t w = blockIdx.x * kIsingBlock + threadIdx.x;
+    uint32_t flips = 0;
+    if (w < g.nw) {
+        uint32_t *own = P + (size_t)c * g.nw;
+        const uint32_t *oth = P + (size_t)(c ^ 1u) * g.nw;
+        const BitNbrs n = bit_neighbours(oth, g, c, w);
+        const uint32_t s = own[w];
+        const uint32_t a1 = s ^ n.mid, a2 = s ^ n.side, a3 = s ^ n.up, a4 = s ^ n.dn;
+        const uint32_t any = a1 | a2 | a3 | a4;
+        const uint32_t ge2 = (a1 & a2) | (a3 & a4) | ((a1 | a2) & (a3 | a4));
+        const uint32_t one = any & ~ge2, zero = ~any;
+        const uint32_t sweep = *sweep_ptr;
+        uint32_t m4 = 0u, m8 = 0u;
+#pragma unroll
+        for (uint32_t q = 0; q < 8u; ++q) {
+            const uint4 r = philox(make_uint4(8u * w + q, c | (kPurposeIsing << 8), sweep, 0u), key);
+            const uint32_t u[4] = { r.x >> 8, r.y >> 8, r.z >> 8, r.w >> 8 };
+#pragma unroll
+            for (uint32_t i = 0; i < 4u; ++i) {
+                m4 |= (uint32_t)(u[i] < T4) << (4u * q + i);
+                m8 |= (uint32_t)(u[i] < T8) << (4u * q + i);
+            }
+        }
+        const uint32_t flip = ge2 | (one & m4) | (zero & m8);
+        if (flip) own[w] = s ^ flip;  // same-colour sites are never neighbours
+        flips = __popc(flip);
+    }
+    unsigned long long cnt = flips;
+#pragma unroll
+    for (int off = kIsingWave / 2; off > 0; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if ((threadIdx.x & (kIsingWave - 1)) == 0 && cnt)
+        atomicAdd(&accepted[(blockIdx.x * (kIsingBlock / kIsingWave) + threadIdx.x / kIsingWave) % kAccSlots], cnt);
+}
+
+// Exact integer sums: every bond has one end of colour 0, so the bond sum is
+// the sum over colour-0 sites of s times its four neighbours, 4 - 2 n per
+// site; the magnetisation counts the set bits of both colours.
+__global__ __launch_bounds__(kIsingBlock) void k_ising_obs_bits(const uint32_t *__restrict__ P, IsingGeo g,
+                                                                unsigned long long *__restrict__ sums)
+{
+    const uint32_t w = blockIdx.x * kIsingBlock + threadIdx.x;
+    long long bonds = 0, mag = 0;
+    if (w < g.nw) {
+        const uint32_t *oth = P + g.nw;
+        const BitNbrs n = bit_neighbours(oth, g, 0u, w);
+        const uint32_t s = P[w];
+        // (__popc is unsigned: take the counts as signed before subtracting)
+        const int anti = (int)(__popc(s ^ n.mid) + __popc(s ^ n.side) + __popc(s ^ n.up) + __popc(s ^ n.dn));
+        const int down = (int)(__popc(s) + __popc(n.mid));
+        bonds = 128 - 2 * anti;
+        mag = 64 - 2 * down;
+    }
+#pragma unroll
+    for (int off = kIsingWave / 2; off > 0; off >>= 1) {
+        bonds += __shfl_xor(bonds, off);
+        mag += __shfl_xor(mag, off);
+    }
+    if ((threadIdx.x & (kIsingWave - 1)) == 0) {
+        const uint32_t slot = (blockIdx.x * (kIsingBlock / kIsingWave) + threadIdx.x / kIsingWave) % kAccSlots;
+        atomicAdd(&sums[2 * slot], (unsigned long long)bonds);
+        atomicAdd(&sums[2 * slot + 1], (unsigned long long)mag);
+    }
+}
+
+// lex order <-> bit layout: one lane per site out, one lane per word in
+__global__ __launch_bounds__(kIsingBlock) void k_ising_pack_bits(const uint32_t *__restrict__ P, IsingGeo g,
+                                                                 int8_t *__restrict__ out)
+{
+    const uint32_t lex = blockIdx.x * kIsingBlock + threadIdx.x;
+    if (lex >= 2u * g.half) return;
+    const uint32_t y = lex / g.L0, x = lex - y * g.L0;
+    const uint32_t h = (x >> 1) + g.H0 * y;
+    const uint32_t word = P[(size_t)((x + y) & 1u) * g.nw + h / 32u];
+    out[lex] = ((word >> (h % 32u)) & 1u) ? (int8_t)-1 : (int8_t)1;
+}
+
+__global__ __launch_bounds__(kIsingBlock) void k_ising_unpack_bits(uint32_t *__restrict__ P, IsingGeo g,
+                                                                   const int8_t *__restrict__ in)
+{
+    const uint32_t w = blockIdx.x * kIsingBlock + threadIdx.x;  // over both colours
+    if (w >= 2u * g.nw) return;
+    const uint32_t c = w >= g.nw ? 1u : 0u, wc = w - c * g.nw;
+    const uint32_t y = fdiv(wc, g.dW), k = wc - y * g.W;
+    const uint32_t x0 = (c + y) & 1u;
+    uint32_t bits = 0u;
+    for (uint32_t b = 0; b < 32u; ++b) {
+        const uint32_t x = 2u * (32u * k + b) + x0;
+        bits |= (uint32_t)(in[x + g.L0 * y] < 0) << b;
+    }
+    P[w] = bits;
+}
+
 __global__ void k_ising_tick(uint32_t *sweep_ptr)
 {
     if (threadIdx.x == 0) *sweep_ptr += 1u;
@@ -169,7 +317,9 @@ struct IsingCtx {
     Key key{};
     double beta = 0.0;
     uint32_t T4 = 0, T8 = 0;
+    bool bits = false;        // layout: 1-bit words (P) or bytes (S)
     int8_t *S = nullptr;
+    uint32_t *P = nullptr;
     uint32_t *d_sweep = nullptr;
     unsigned long long *d_acc = nullptr;   // accepted flips, kAccSlots partial counts
     unsigned long long *d_sums = nullptr;  // observables, kAccSlots (bonds, spins) partial sums
@@ -201,7 +351,7 @@ void ising_release()
     if (I.ready) hipDeviceSynchronize();
     if (I.graph1) hipGraphExecDestroy(I.graph1);
     if (I.graphN) hipGraphExecDestroy(I.graphN);
-    void *ptrs[] = { I.S, I.d_sweep, I.d_acc, I.d_sums };
+    void *ptrs[] = { I.S, I.P, I.d_sweep, I.d_acc, I.d_sums };
     for (void *p : ptrs)
         if (p) hipFree(p);
     I = IsingCtx{};
@@ -217,6 +367,7 @@ int build_sweep_graph(int nsweeps, hipGraphExec_t *out)
     hipGraphNode_t prev = nullptr;
     int rc = SU2_OK;
     int8_t *S = I.S;
+    uint32_t *P = I.P;
     IsingGeo g = I.g;
     Key key = I.key;
     const uint32_t *sp = I.d_sweep;
@@ -239,8 +390,13 @@ int build_sweep_graph(int nsweeps, hipGraphExec_t *out)
     };
     for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
         for (int c = 0; c < 2 && rc == SU2_OK; ++c) {
-            void *args[] = { &S, &g, &key, &colours[c], &sp, &T4, &T8, &acc };
-            rc = add(reinterpret_cast<const void *>(&k_ising_pass), dim3(blocks_of(groups())), args);
+            if (I.bits) {
+                void *args[] = { &P, &g, &key, &colours[c], &sp, &T4, &T8, &acc };
+                rc = add(reinterpret_cast<const void *>(&k_ising_pass_bits), dim3(blocks_of(g.nw)), args);
+            } else {
+                void *args[] = { &S, &g, &key, &colours[c], &sp, &T4, &T8, &acc };
+                rc = add(reinterpret_cast<const void *>(&k_ising_pass), dim3(blocks_of(groups())), args);
+            }
         }
         if (rc == SU2_OK) {
             void *targs[] = { &spw };
@@ -268,7 +424,7 @@ using namespace su2;
 
 extern "C" {
 
-int ising_init(const int32_t dims[2], double beta, uint64_t seed, int32_t start)
+int ising_init_ex(const int32_t dims[2], double beta, uint64_t seed, int32_t start, int32_t layout)
 {
     if (!dims) return ifail(SU2_EINVAL, "dims is NULL");
     if (dims[0] < 2 || dims[1] < 2 || (dims[0] & 1) || (dims[1] & 1))
@@ -277,17 +433,28 @@ int ising_init(const int32_t dims[2], double beta, uint64_t seed, int32_t start)
     if (N >= (1ull << 32)) return ifail(SU2_EINVAL, "lattice volume must be below 2^32");
     if (!std::isfinite(beta) || beta < 0.0) return ifail(SU2_EINVAL, "beta must be finite and >= 0");
     if (start != SU2_COLD && start != SU2_HOT) return ifail(SU2_EINVAL, "start must be 0 or 1");
+    if (layout < ISING_LAYOUT_AUTO || layout > ISING_LAYOUT_BITS)
+        return ifail(SU2_EINVAL, "layout must be 0 (auto), 1 (bytes) or 2 (bits)");
+    const bool bits_fit = dims[0] % 64 == 0;
+    if (layout == ISING_LAYOUT_BITS && !bits_fit) return ifail(SU2_EINVAL, "the bit layout needs L0 % 64 == 0");
     ising_release();
+    // below 2^20 spins both layouts run at the launch floor (~9 us per sweep)
+    // and the byte layout's four sites per lane fill the device better
+    I.bits = layout == ISING_LAYOUT_BITS || (layout == ISING_LAYOUT_AUTO && bits_fit && N >= (1ull << 20));
     I.g.L0 = (uint32_t)dims[0];
     I.g.L1 = (uint32_t)dims[1];
     I.g.H0 = I.g.L0 / 2u;
     I.g.half = (uint32_t)(N / 2);
     I.g.dH0 = make_fastdiv(I.g.H0);
+    I.g.W = I.g.H0 / 32u;
+    I.g.nw = I.g.half / 32u;
+    I.g.dW = make_fastdiv(I.bits ? I.g.W : 1u);
     I.key = Key{ (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32) };
     I.beta = beta;
     I.T4 = (uint32_t)std::floor(std::exp(-4.0 * beta) * 16777216.0);
     I.T8 = (uint32_t)std::floor(std::exp(-8.0 * beta) * 16777216.0);
-    if (hipMalloc(&I.S, (size_t)N) != hipSuccess || hipMalloc(&I.d_sweep, sizeof(uint32_t)) != hipSuccess ||
+    const hipError_t ea = I.bits ? hipMalloc(&I.P, (size_t)N / 8) : hipMalloc(&I.S, (size_t)N);
+    if (ea != hipSuccess || hipMalloc(&I.d_sweep, sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&I.d_acc, kAccSlots * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&I.d_sums, 2 * kAccSlots * sizeof(unsigned long long)) != hipSuccess) {
         hipGetLastError();
@@ -297,10 +464,28 @@ int ising_init(const int32_t dims[2], double beta, uint64_t seed, int32_t start)
     I.ready = true;
     ITRY(hipMemset(I.d_sweep, 0, sizeof(uint32_t)));
     ITRY(hipMemset(I.d_acc, 0, kAccSlots * sizeof(unsigned long long)));
-    hipLaunchKernelGGL(k_ising_init, dim3(blocks_of(groups()), 2), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
-                       I.key, start == SU2_HOT);
+    if (I.bits)
+        hipLaunchKernelGGL(k_ising_init_bits, dim3(blocks_of(I.g.nw), 2), dim3(kIsingBlock), 0, nullptr, I.P, I.g,
+                           I.key, start == SU2_HOT);
+    else
+        hipLaunchKernelGGL(k_ising_init, dim3(blocks_of(groups()), 2), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
+                           I.key, start == SU2_HOT);
     ITRY(hipGetLastError());
     ITRY(hipDeviceSynchronize());
+    return SU2_OK;
+}
+
+int ising_init(const int32_t dims[2], double beta, uint64_t seed, int32_t start)
+{
+    return ising_init_ex(dims, beta, seed, start, ISING_LAYOUT_AUTO);
+}
+
+int ising_layout(int32_t *out)
+{
+    int rc = ising_ready();
+    if (rc) return rc;
+    if (!out) return ifail(SU2_EINVAL, "out is NULL");
+    *out = I.bits ? ISING_LAYOUT_BITS : ISING_LAYOUT_BYTES;
     return SU2_OK;
 }
 
@@ -334,8 +519,12 @@ int ising_observables(double out[2])
     if (rc) return rc;
     if (!out) return ifail(SU2_EINVAL, "out is NULL");
     ITRY(hipMemsetAsync(I.d_sums, 0, 2 * kAccSlots * sizeof(unsigned long long), nullptr));
-    hipLaunchKernelGGL(k_ising_obs, dim3(blocks_of(2ull * I.g.half)), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
-                       I.d_sums);
+    if (I.bits)
+        hipLaunchKernelGGL(k_ising_obs_bits, dim3(blocks_of(I.g.nw)), dim3(kIsingBlock), 0, nullptr, I.P, I.g,
+                           I.d_sums);
+    else
+        hipLaunchKernelGGL(k_ising_obs, dim3(blocks_of(2ull * I.g.half)), dim3(kIsingBlock), 0, nullptr, I.S, I.g,
+                           I.d_sums);
     ITRY(hipGetLastError());
     std::vector<unsigned long long> h(2 * kAccSlots);
     ITRY(hipMemcpy(h.data(), I.d_sums, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost));
@@ -360,7 +549,10 @@ int ising_spins(int8_t *host_out, size_t n)
         hipGetLastError();
         return ifail(SU2_ENOMEM, "cannot allocate the staging buffer");
     }
-    hipLaunchKernelGGL(k_ising_pack, dim3(blocks_of(n)), dim3(kIsingBlock), 0, nullptr, I.S, I.g, stage);
+    if (I.bits)
+        hipLaunchKernelGGL(k_ising_pack_bits, dim3(blocks_of(n)), dim3(kIsingBlock), 0, nullptr, I.P, I.g, stage);
+    else
+        hipLaunchKernelGGL(k_ising_pack, dim3(blocks_of(n)), dim3(kIsingBlock), 0, nullptr, I.S, I.g, stage);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpy(host_out, stage, n, hipMemcpyDeviceToHost);
     hipFree(stage);
@@ -383,7 +575,11 @@ int ising_set_spins(const int8_t *host_in, size_t n, uint64_t sweep_index)
     }
     hipError_t e = hipMemcpy(stage, host_in, n, hipMemcpyHostToDevice);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_ising_unpack, dim3(blocks_of(n)), dim3(kIsingBlock), 0, nullptr, I.S, I.g, stage);
+        if (I.bits)
+            hipLaunchKernelGGL(k_ising_unpack_bits, dim3(blocks_of(2ull * I.g.nw)), dim3(kIsingBlock), 0, nullptr,
+                               I.P, I.g, stage);
+        else
+            hipLaunchKernelGGL(k_ising_unpack, dim3(blocks_of(n)), dim3(kIsingBlock), 0, nullptr, I.S, I.g, stage);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipDeviceSynchronize();

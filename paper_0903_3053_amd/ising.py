@@ -8,9 +8,10 @@ import numpy as np
 from . import su2
 
 # every symbol include/ising.h declares
-EXPORTS = ("ising_init", "ising_sweep", "ising_observables", "ising_spins", "ising_set_spins",
-           "ising_sweep_index", "ising_accepted", "ising_last_error", "ising_finalize")
+EXPORTS = ("ising_init", "ising_init_ex", "ising_layout", "ising_sweep", "ising_observables", "ising_spins",
+           "ising_set_spins", "ising_sweep_index", "ising_accepted", "ising_last_error", "ising_finalize")
 COLD, HOT = 0, 1
+LAYOUT_AUTO, LAYOUT_BYTES, LAYOUT_BITS = 0, 1, 2
 
 _ready = False
 
@@ -25,6 +26,9 @@ def load():
         dp = ctypes.POINTER(ctypes.c_double)
         sig = {
             "ising_init": ([i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32], ctypes.c_int),
+            "ising_init_ex": ([i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int32],
+                              ctypes.c_int),
+            "ising_layout": ([i32p], ctypes.c_int),
             "ising_sweep": ([ctypes.c_int32], ctypes.c_int),
             "ising_observables": ([dp], ctypes.c_int),
             "ising_spins": ([i8p, ctypes.c_size_t], ctypes.c_int),
@@ -56,13 +60,27 @@ def _check(rc):
         raise IsingError(rc, load().ising_last_error().decode())
 
 
-def ising_init(dims, beta, seed, start):
+def ising_init(dims, beta, seed, start, layout=None):
+    """layout None calls ising_init (auto); 0/1/2 call ising_init_ex."""
     d = np.ascontiguousarray(np.asarray(dims, dtype=np.int32))
     if d.shape != (2,):
         raise ValueError("dims must have 2 entries")
-    _check(load().ising_init(d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), float(beta),
-                             ctypes.c_uint64(seed), int(start)))
+    dp = d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    if layout is None:
+        _check(load().ising_init(dp, float(beta), ctypes.c_uint64(seed), int(start)))
+    else:
+        _check(load().ising_init_ex(dp, float(beta), ctypes.c_uint64(seed), int(start), int(layout)))
     _shape["n"] = int(d[0]) * int(d[1])
+
+
+def ising_init_ex(dims, beta, seed, start, layout):
+    ising_init(dims, beta, seed, start, layout)
+
+
+def ising_layout():
+    out = ctypes.c_int32(0)
+    _check(load().ising_layout(ctypes.byref(out)))
+    return out.value
 
 
 def ising_sweep(n=1):

@@ -54,6 +54,12 @@ def test_ising_errors_without_device_work(lib):
         d = np.asarray(dims, dtype=np.int32)
         assert lib.ising_init(d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), beta, 1, start) == su2.SU2_EINVAL
     assert lib.ising_init(None, 0.4, 1, 0) == su2.SU2_EINVAL
+    lay = ctypes.c_int32(-1)
+    assert lib.ising_layout(ctypes.byref(lay)) == su2.SU2_ESTATE
+    for dims, layout in [((96, 4), ising.LAYOUT_BITS), ((64, 4), 3), ((64, 4), -1)]:
+        d = np.asarray(dims, dtype=np.int32)
+        assert lib.ising_init_ex(d.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), 0.4, 1, 0,
+                                 layout) == su2.SU2_EINVAL
 
 
 def test_state_errors_before_init(lib):

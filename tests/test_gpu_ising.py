@@ -1,8 +1,9 @@
 """The 2-D Ising workload (Sec. 2.3, Eq. (1)) through the C ABI against the
 oracle: the Metropolis decisions are integer comparisons on both sides, so
 spins, accepted-flip counts and observables must agree exactly after any
-number of sweeps, also on the paper's 1024 x 512 lattice; plus Onsager's energy
-and Yang's magnetisation on a larger lattice from GPU chains."""
+number of sweeps, in both device layouts (a byte per spin; the paper's 1-bit
+spins, 32 per word), also on the paper's 1024 x 512 lattice; plus Onsager's
+energy and Yang's magnetisation on a larger lattice from GPU chains."""
 import numpy as np
 import pytest
 
@@ -24,12 +25,23 @@ def lib():
 
 CASES = [((8, 8), 0.44, 1, 1, 40), ((16, 6), 0.2, 2, 1, 40), ((6, 10), 1.0, 3, 0, 40), ((2, 2), 0.3, 4, 1, 40),
          ((10, 4), 0.0, 5, 1, 10), ((1024, 512), 0.44, 1, 1, 20)]
+# shapes the bit layout takes (L0 % 64 == 0): one word per row, odd word
+# counts, two rows, wrap of the side word
+BIT_CASES = [((64, 2), 0.44, 6, 1, 40), ((64, 6), 0.3, 7, 1, 40), ((128, 10), 0.7, 8, 0, 40),
+             ((192, 4), 0.44, 9, 1, 40), ((64, 64), 0.1, 10, 1, 20), ((320, 18), 0.0, 11, 1, 10),
+             ((1024, 512), 0.44, 1, 1, 20)]
 
 
-@pytest.mark.parametrize("dims,beta,seed,start,n", CASES)
-def test_ising_bit_identical_to_oracle(lib, dims, beta, seed, start, n):
+@pytest.mark.parametrize("layout", ["bytes", "bits"])
+@pytest.mark.parametrize("dims,beta,seed,start,n", CASES + BIT_CASES[:-1])
+def test_ising_bit_identical_to_oracle(lib, dims, beta, seed, start, n, layout):
+    if layout == "bits" and dims[0] % 64:
+        with pytest.raises(lib.IsingError):
+            lib.ising_init(dims, beta, seed, start, lib.LAYOUT_BITS)
+        return
     s = oising.init(dims, seed, start)
-    lib.ising_init(dims, beta, seed, start)
+    lib.ising_init(dims, beta, seed, start, lib.LAYOUT_BITS if layout == "bits" else lib.LAYOUT_BYTES)
+    assert lib.ising_layout() == (lib.LAYOUT_BITS if layout == "bits" else lib.LAYOUT_BYTES)
     assert np.array_equal(lib.ising_spins(), s)
     acc = oising.sweep(dims, s, beta, seed, 0, n // 2)
     lib.ising_sweep(n // 2)
@@ -41,6 +53,21 @@ def test_ising_bit_identical_to_oracle(lib, dims, beta, seed, start, n):
     assert lib.ising_accepted() == acc
     assert lib.ising_sweep_index() == n
     assert lib.ising_observables() == oising.observables(dims, s)
+
+
+def test_layouts_same_chain(lib):
+    """4096 x 1024 at beta 0.44 from a hot start, 60 sweeps: the two layouts
+    give the same spins, flip counts and observables; auto picks bits."""
+    dims = (4096, 1024)
+    out = {}
+    for layout in (lib.LAYOUT_BYTES, lib.LAYOUT_BITS, None):
+        lib.ising_init(dims, 0.44, 21, 1, layout)
+        lib.ising_sweep(60)
+        out[layout] = (lib.ising_spins(), lib.ising_accepted(), lib.ising_observables(), lib.ising_layout())
+    b, p, a = out[lib.LAYOUT_BYTES], out[lib.LAYOUT_BITS], out[None]
+    assert np.array_equal(b[0], p[0]) and np.array_equal(b[0], a[0])
+    assert b[1] == p[1] == a[1] and b[2] == p[2] == a[2]
+    assert a[3] == lib.LAYOUT_BITS
 
 
 def test_ising_resume_and_errors(lib):
@@ -58,6 +85,17 @@ def test_ising_resume_and_errors(lib):
         lib.ising_set_spins(np.ones(95, dtype=np.int8), 0)   # wrong size
     with pytest.raises(lib.IsingError):
         lib.ising_sweep(-1)
+    # the same in the bit layout
+    dims = (128, 6)
+    s = oising.init(dims, seed, 1)
+    oising.sweep(dims, s, beta, seed, 0, 7)
+    lib.ising_init(dims, beta, seed, 0, lib.LAYOUT_BITS)
+    lib.ising_set_spins(s, 7)
+    oising.sweep(dims, s, beta, seed, 7, 5)
+    lib.ising_sweep(5)
+    assert np.array_equal(lib.ising_spins(), s) and lib.ising_sweep_index() == 12
+    with pytest.raises(lib.IsingError):
+        lib.ising_init(dims, beta, seed, 0, 3)
 
 
 def test_ising_onsager_and_yang_on_gpu(lib):

@@ -33,7 +33,7 @@ BYTES_PER_UPDATE = 128  # one lattice streamed per (parity, mu) pass: 4N links x
 # committed traffic counters (taken with that plan) applicable.
 WORKLOADS = {
     64: dict(name="su2_64x64x64x64_b2.4_hot", dims=(64, 64, 64, 64), beta=2.4, seed=1, start=1,
-             plan=(108, 32768)),
+             plan=(1108, 32768)),
     32: dict(name="su2_32x32x32x32_b2.3_hot", dims=(32, 32, 32, 32), beta=2.3, seed=1, start=1,
              plan=None),
 }

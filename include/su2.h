@@ -168,6 +168,10 @@ int su2_set_stream(void *hip_stream);
  * (x2, x3) step (-1, +1) times one x0 row), so the second pass reads the
  * first one's results from LDS (only for L0 <= 256, else SU2_EINVAL; the
  * single-pass entry su2_pass is unaffected);
+ * 1000 + K (K one of the kinds 0..299 above) = order K for the passes mu = 0
+ * and 2 of each parity and the same order backwards for mu = 1 and 3, so a pass
+ * starts on the tiles the previous one finished with, whose data is still in
+ * the Infinity Cache;
  * lds_bytes (0..65536) of local memory reserved per workgroup to cap the
  * workgroups resident on a compute unit.  Links and counters are
  * bit-identical for every plan, only the speed changes; the plaquette of a
@@ -175,8 +179,9 @@ int su2_set_stream(void *hip_stream);
  * differences). */
 int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
 
-/* Time each plan in {order 0, 4, 8, 16, 108, 208, 300} x {LDS 0, 16, 24, 32, 40 KiB} on a
- * scratch copy of the links (reps measured sweeps each, in three rounds over
+/* Time each plan in {order 0, 4, 8, 16, 108, 208, 1000, 1008, 1108, 1208, 300}
+ * x {LDS 0, 16, 24, 32, 40 KiB} on a scratch copy of the links (reps measured
+ * sweeps each, in three rounds over
  * all plans; the lattice, sweep index and all counters are untouched) and
  * install the plan with the smallest median; out (nullable) receives
  * {order_kind, lds_bytes}.  The plan is timed with the proposal installed at

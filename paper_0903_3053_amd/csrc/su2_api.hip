@@ -299,6 +299,7 @@ int set_plan(int32_t kind, uint32_t lds)
                           hipMemcpyHostToDevice));
     }
     ctx.plan.order = ctx.d_order;
+    ctx.plan.alternate = kind >= kAlternate;
     ctx.plan.lds_bytes = lds;
     ctx.plan.fused = fused;
     ctx.plan.pg01 = pg01;
@@ -729,7 +730,8 @@ int su2_tune(int32_t reps, int32_t out[2])
     // measured sweeps (as su2_sweep_measured runs them) of a copy of the links,
     // in three rounds over all candidates; the median of its rounds ranks it,
     // so slow drifts of the clock or of the cache state do not pick the plan.
-    const int32_t kinds[] = { 0, 4, 8, 16, 108, 208, kFusedPairs };
+    const int32_t kinds[] = { 0, 4, 8, 16, 108, 208, kAlternate, kAlternate + 8, kAlternate + 108,
+                              kAlternate + 208, kFusedPairs };
     const uint32_t ldss[] = { 0u, 16384u, 24576u, 32768u, 40960u };
     constexpr int kRounds = 3;
     std::vector<int32_t> cand_kind;

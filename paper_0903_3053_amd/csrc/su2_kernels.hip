@@ -296,6 +296,13 @@ uint32_t pass_blocks(const Geo &g) { return blocks_for(g.half); }
 bool make_order(const Geo &g, int kind, std::vector<uint32_t> &order)
 {
     const uint32_t n = pass_blocks(g);
+    if (kind >= kAlternate) {
+        // order kind - kAlternate, then the same backwards for the odd passes
+        if (kind - kAlternate >= kAlternate || !make_order(g, kind - kAlternate, order)) return false;
+        order.resize(2u * (size_t)n);
+        for (uint32_t w = 0; w < n; ++w) order[n + w] = order[n - 1u - w];
+        return true;
+    }
     order.resize(n);
     for (uint32_t w = 0; w < n; ++w) order[w] = w;
     if (kind <= 0) return true;
@@ -421,9 +428,15 @@ std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, flo
     // Sec. 2.4: odd sites for every direction, then even sites
     for (int p = 1; p >= 0; --p) {
         if (!plan.fused) {
-            for (uint32_t mu = 0; mu < 4; ++mu)
-                out.push_back(pass_launch(links, g, key, beta, (uint32_t)p, mu, sweep_ptr, counters,
-                                          meas_out, plan));
+            for (uint32_t mu = 0; mu < 4; ++mu) {
+                PassLaunch pl = pass_launch(links, g, key, beta, (uint32_t)p, mu, sweep_ptr, counters,
+                                            meas_out, plan);
+                // odd passes of the sweep walk the tiles backwards: a pass starts
+                // where the previous one ended, on data still in the Infinity Cache
+                if (plan.alternate && (mu & 1u)) pl.order = plan.order + pass_blocks(g);
+                pl.bind();
+                out.push_back(pl);
+            }
             continue;
         }
         for (uint32_t mu = 0; mu < 4; mu += 2) {

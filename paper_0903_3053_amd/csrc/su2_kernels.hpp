@@ -15,6 +15,7 @@ namespace su2 {
 struct PassPlan {
     const uint32_t *order = nullptr;
     uint32_t lds_bytes = 0;
+    bool alternate = false;         // odd passes use the table's second half (the order backwards)
     bool fused = false;             // a sweep as four k_pair launches (U_0,U_1 and U_2,U_3 per parity)
     PairGeo pg01, pg23;             // their workgroup sets (valid when fused)
     bool learned = false;           // learned proposal (imh) or heat-bath only
@@ -80,6 +81,9 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
 bool make_order(const Geo &g, int kind, std::vector<uint32_t> &order);
 // Tile order kind of the fused-pair sweep (k_pair with XCD-chunked workgroups).
 constexpr int kFusedPairs = 300;
+// kAlternate + K: order K for the even passes of a sweep, the same backwards for
+// the odd ones (the table holds both)
+constexpr int kAlternate = 1000;
 // The workgroup sets of the two k_pair launches of a parity; false if the
 // lattice does not fit them (L0 > 256).
 bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo &pg23);

@@ -145,8 +145,9 @@ def test_sweep_parity_per_sweep(lib):
 
 def test_full_size_64x64x64x64_sweep(lib):
     """The benchmark workload at full size and in the benchmark's launch
-    configuration (64^4, beta 2.4, hot start seed 1, tile order 108 with 32
-    KiB of LDS, measured sweep): the hot start equals the oracle's, and after one
+    configuration (64^4, beta 2.4, hot start seed 1, tile order 1108 -- order
+    108, every second pass walked backwards -- with 32 KiB of LDS, measured
+    sweep): the hot start equals the oracle's, and after one
     sweep every link agrees with the oracle's sweep to 1e-5 except near the
     few accept decisions that flip at FP32 rounding (the same per-update rate
     as the 4^4 per-sweep test allows), the fused plaquette to 2e-6."""
@@ -154,7 +155,7 @@ def test_full_size_64x64x64x64_sweep(lib):
     n_upd = 4 * 64**4
     U = oracle.init(dims, seed, oracle.HOT)
     lib.su2_init(dims, beta, seed, lib.HOT)
-    lib.su2_set_plan(108, 32768)
+    lib.su2_set_plan(1108, 32768)
     assert np.max(np.abs(lib.su2_links() - U)) <= 1e-6
     hist = lib.su2_sweep_measure(1, 1)
     gpu = lib.su2_links()
@@ -225,7 +226,7 @@ def test_fused_pairs_full_size_64x64x64x64(lib):
     sweep leaves every link bit-identical to the benchmark plan's sweep."""
     dims, beta, seed = (64, 64, 64, 64), 2.4, 1
     lib.su2_init(dims, beta, seed, lib.HOT)
-    lib.su2_set_plan(108, 32768)
+    lib.su2_set_plan(1108, 32768)
     h_ref = lib.su2_sweep_measure(1, 1)
     ref, c_ref = lib.su2_links(), lib.su2_counters()
     lib.su2_init(dims, beta, seed, lib.HOT)
@@ -414,7 +415,7 @@ def test_launch_plans_bit_identical(lib):
     ref = lib.su2_links()
     c_ref = lib.su2_counters()
     for kind, lds in [(0, 0), (4, 0), (8, 32768), (4, 40960), (0, 16384), (108, 0), (104, 24576), (204, 0),
-                      (lib.FUSED_PAIRS, 0), (lib.FUSED_PAIRS, 24576)]:
+                      (lib.FUSED_PAIRS, 0), (lib.FUSED_PAIRS, 24576), (1000, 0), (1108, 32768), (1204, 0)]:
         lib.su2_init(dims, 2.3, 5, lib.HOT)
         lib.su2_set_plan(kind, lds)
         lib.su2_sweep(2)
@@ -429,7 +430,7 @@ def test_launch_plans_bit_identical(lib):
     lib.su2_sweep(1)
     before = lib.su2_links()
     plan = lib.su2_tune(1)
-    assert plan[0] in (0, 4, 8, 16, 108, 208, lib.FUSED_PAIRS)
+    assert plan[0] in (0, 4, 8, 16, 108, 208, 1000, 1008, 1108, 1208, lib.FUSED_PAIRS)
     assert np.array_equal(lib.su2_links(), before)
     assert lib.su2_sweep_index() == 1
     lib.su2_sweep(2)
@@ -437,6 +438,10 @@ def test_launch_plans_bit_identical(lib):
     assert lib.su2_counters() == c_ref
     with pytest.raises(lib.Su2Error):
         lib.su2_set_plan(3, 0)  # 3 does not divide L2 = 8
+    with pytest.raises(lib.Su2Error):
+        lib.su2_set_plan(1003, 0)
+    with pytest.raises(lib.Su2Error):
+        lib.su2_set_plan(2000, 0)
 
 
 @pytest.mark.parametrize("dims", [(8, 6, 4, 10), (8, 8, 8, 4), (16, 16, 16, 8)])

@@ -255,6 +255,11 @@ int build_or_graph(hipGraphExec_t *out)
     for (int p = 1; p >= 0 && rc == SU2_OK; --p)
         for (uint32_t mu = 0; mu < 4 && rc == SU2_OK; ++mu) {
             PassLaunch pl = or_launch(ctx.links, ctx.g, (uint32_t)p, mu, ctx.plan);
+            // as in the heat-bath sweep: odd passes walk the tile order backwards
+            if (ctx.plan.alternate && !ctx.plan.fused && (mu & 1u)) {
+                pl.order = ctx.plan.order + pass_blocks(ctx.g);
+                pl.bind();
+            }
             hipKernelNodeParams kp{};
             kp.func = const_cast<void *>(pl.func);
             kp.gridDim = pl.grid;

@@ -67,7 +67,7 @@ def test_overrelax_conserves_plaquette_and_undoes_itself(lib):
 def test_overrelax_same_for_every_plan(lib):
     dims = (64, 64, 8, 8)
     ref = None
-    for plan in [(0, 0), (108, 32768), (lib.FUSED_PAIRS, 0)]:
+    for plan in [(0, 0), (108, 32768), (1108, 32768), (lib.FUSED_PAIRS, 0)]:
         lib.su2_init(dims, 2.3, 6, lib.HOT)
         lib.su2_set_plan(*plan)
         lib.su2_sweep(1)

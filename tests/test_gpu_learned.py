@@ -142,7 +142,7 @@ def test_learned_sweeps_identical_across_plans(lib):
     for points in (31, 64):
         lib.su2_mlp_tabulate(points)
         ref = None
-        for plan in [(0, 0), (8, 16384), (4, 40960), (lib.FUSED_PAIRS, 0)]:
+        for plan in [(0, 0), (8, 16384), (4, 40960), (1008, 16384), (lib.FUSED_PAIRS, 0)]:
             lib.su2_init(dims, 2.3, 4, lib.HOT)
             lib.su2_set_plan(*plan)
             lib.su2_set_proposal(1)

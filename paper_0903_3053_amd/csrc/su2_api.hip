@@ -59,8 +59,8 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_corr(const double *__restri
                          field[x0 + g.L[0] * (x1 + g.L[1] * y2)];
         acc = field[i] * n;
     }
-    const double2 s = block_sum2(acc, 0.0);
-    if (threadIdx.x == 0) partial[(size_t)rr * gridDim.x + blockIdx.x] = s.x;
+    const double s = block_sum(acc);
+    if (threadIdx.x == 0) partial[(size_t)rr * gridDim.x + blockIdx.x] = s;
 }
 
 // out[r] = (sum of the nb partials of r, in order) / (3 vs); one workgroup per r
@@ -70,8 +70,8 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_corr_reduce(const double *_
 {
     double a = 0.0;
     for (uint32_t j = threadIdx.x; j < nb; j += kBlock) a += partial[(size_t)blockIdx.x * nb + j];
-    const double2 s = block_sum2(a, 0.0);
-    if (threadIdx.x == 0) out[blockIdx.x] = s.x / (3.0 * (double)vs);
+    const double s = block_sum(a);
+    if (threadIdx.x == 0) out[blockIdx.x] = s / (3.0 * (double)vs);
 }
 
 }  // namespace su2

@@ -138,8 +138,8 @@ __global__ __launch_bounds__(kBlock) void k_polyakov(const float4 *__restrict__ 
         }
         acc = (double)P.x;
     }
-    const double2 r = block_sum2(acc, 0.0);
-    if (threadIdx.x == 0) partials[blockIdx.x] = r;
+    const double r = block_sum(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = make_double2(r, 0.0);
 }
 
 // First level of the deterministic reduction: workgroup b sums the partials

@@ -336,8 +336,8 @@ __global__ __launch_bounds__(kBlock) void k_loss(const float *__restrict__ terms
 {
     double a = 0.0;
     for (uint32_t j = threadIdx.x; j < B; j += kBlock) a += terms[j];
-    const double2 r = block_sum2(a, 0.0);
-    if (threadIdx.x == 0) out[step ? *step : 0] = (float)(r.x / ((double)B * kSeg));
+    const double r = block_sum(a);
+    if (threadIdx.x == 0) out[step ? *step : 0] = (float)(r / ((double)B * kSeg));
 }
 
 // Adam (Kingma & Ba) with bias correction and a cosine learning-rate decay

@@ -263,11 +263,8 @@ __device__ __forceinline__ void pair_update2(const PairCtx &c, uint32_t pos, boo
 __device__ __forceinline__ double2 block_sum2_any(double a, double b)
 {
     __shared__ double sh[2][16];
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-    }
+    a = wave_sum(a);
+    b = wave_sum(b);
     const uint32_t wv = threadIdx.x / kWave, nw = blockDim.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
         sh[0][wv] = a;

@@ -114,16 +114,46 @@ __device__ __forceinline__ bool creutz_accept(float u1, float m)
     return u1 * u1 <= m * (2.0f - m);
 }
 
-// Block-level FP64 sum of two values: wave butterflies, then waves in order
-// (fixed structure, so the result does not depend on scheduling).
+// A double moved across lanes by a DPP control (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, true);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, true);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
+// Sum of v over the 64 lanes of a wave (every lane active), the same value in
+// every lane, in a fixed order: DPP moves inside each row of 16 lanes (quad
+// permutations xor 1 and xor 2, half-row mirror, row mirror; each step adds
+// the partner's partial, so every lane of a row ends with the row's sum) and
+// the four row sums read out and added as (0 + 1) + (2 + 3).  Register moves,
+// where shuffles through LDS would cost a dependent round trip per step.
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
+// Block-level FP64 sum of two values: wave sums, then waves in order (fixed
+// structure, so the result does not depend on scheduling).
 __device__ __forceinline__ double2 block_sum2(double a, double b)
 {
     __shared__ double sh[2][kBlock / kWave];
-#pragma unroll
-    for (int off = kWave / 2; off > 0; off >>= 1) {
-        a += __shfl_xor(a, off);
-        b += __shfl_xor(b, off);
-    }
+    a = wave_sum(a);
+    b = wave_sum(b);
     const int wv = threadIdx.x / kWave;
     if ((threadIdx.x & (kWave - 1)) == 0) {
         sh[0][wv] = a;
@@ -137,6 +167,20 @@ __device__ __forceinline__ double2 block_sum2(double a, double b)
             r.y += sh[1][i];
         }
     }
+    return r;
+}
+
+// The same for one value (the result in thread 0).
+__device__ __forceinline__ double block_sum(double a)
+{
+    __shared__ double sh1[kBlock / kWave];
+    a = wave_sum(a);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) sh1[wv] = a;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < kBlock / kWave; ++i) r += sh1[i];
     return r;
 }
 
@@ -432,9 +476,9 @@ __device__ __forceinline__ void update_tile(float4 *__restrict__ L, const Geo &g
     update_link<MU, OFF32, MEASURE, IMH, false, CREUTZ>(L, g, key, beta, p, s, h, h < g.half, h / kWave,
                                                         in, counters, imh, acc);
     if constexpr (MEASURE) {
-        const double2 r = block_sum2(acc, 0.0);
+        const double r = block_sum(acc);
         if (threadIdx.x == 0)
-            meas_out[tile] = MU == 3u ? make_double2(0.0, r.x) : make_double2(r.x, 0.0);
+            meas_out[tile] = MU == 3u ? make_double2(0.0, r) : make_double2(r, 0.0);
     }
 }
 

@@ -135,7 +135,7 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
     for `sweeps` sweeps with the heat-bath and with the learned independence-
     Metropolis step; plaquette measured every sweep, averages after a 20 %
     thermalisation cut with Gamma-method errors and integrated autocorrelation
-    times."""
+    times; updates/s of the two from interleaved timing rounds."""
     import numpy as np
     import torch
     import su2_inputs
@@ -152,32 +152,46 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
     t_train = time.perf_counter() - t0
 
     out = {}
+    plans = {}
     for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
         # each proposal runs with the launch plan tuned for it
         su2.su2_init(dims, beta, seed, 1)
         su2.su2_set_proposal(kind)
         su2.su2_sweep(5)
-        plan = su2.su2_tune(2)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        su2.su2_sweep(200)
-        torch.cuda.synchronize()
-        rate = 4 * V * 200 / (time.perf_counter() - t0)
+        plans[kind] = su2.su2_tune(2)
         su2.su2_init(dims, beta, seed, 1)
-        su2.su2_set_plan(*plan)
+        su2.su2_set_plan(*plans[kind])
         su2.su2_set_proposal(kind)
         h = su2.su2_sweep_measure(sweeps, 1)[:, 0]
         m, e, tau, dtau, _ = gamma_method(h[sweeps // 5:])
-        rec = {"link_updates_per_s": rate, "plaquette": m, "plaquette_err": e,
-               "tau_int_sweeps": tau, "tau_int_err": dtau,
-               "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}}
+        rec = {"plaquette": m, "plaquette_err": e, "tau_int_sweeps": tau, "tau_int_err": dtau,
+               "pass_plan": {"tile_order": plans[kind][0], "lds_bytes": plans[kind][1]}}
         if kind:
             prop, acc = su2.su2_imh_counters()
             rec["acceptance"] = acc / max(prop, 1)
         out[name] = rec
+    # rates: TIMING_ROUNDS rounds alternating the two proposals on the same
+    # equilibrated chain (200 sweeps each, after 2 untimed sweeps that build the
+    # graphs of the switched plan), so clock or cache drifts hit both alike;
+    # the median of each and of the per-round ratios is reported
+    su2.su2_init(dims, beta, seed, 1)
+    su2.su2_sweep(200)
+    rates = {0: [], 1: []}
+    for _ in range(TIMING_ROUNDS):
+        for kind in (0, 1):
+            su2.su2_set_plan(*plans[kind])
+            su2.su2_set_proposal(kind)
+            su2.su2_sweep(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            su2.su2_sweep(200)
+            torch.cuda.synchronize()
+            rates[kind].append(4 * V * 200 / (time.perf_counter() - t0))
+    ratios = [b / a for a, b in zip(rates[0], rates[1])]
+    for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
+        out[name]["link_updates_per_s"] = float(np.median(rates[kind]))
+        out[name]["link_updates_per_s_rounds"] = rates[kind]
     kp, lp = out["kennedy_pendleton"], out["learned_imh"]
-    plans = {0: (kp["pass_plan"]["tile_order"], kp["pass_plan"]["lds_bytes"]),
-             1: (lp["pass_plan"]["tile_order"], lp["pass_plan"]["lds_bytes"])}
     scan = beta_scan(su2, dims, seed, plans)
     su2.su2_finalize()
     return {"workload": f"32^4 beta 2.3 hot seed 1, {sweeps} sweeps, heat-bath vs learned proposal",
@@ -186,13 +200,15 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
                          "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
             **out,
             "z_plaquette": (lp["plaquette"] - kp["plaquette"]) / float(np.hypot(kp["plaquette_err"], lp["plaquette_err"])),
-            "speed_ratio": lp["link_updates_per_s"] / kp["link_updates_per_s"],
+            "speed_ratio": float(np.median(ratios)),
+            "speed_ratio_rounds": ratios,
             # updates/s per integrated autocorrelation time of <P>: independent samples/s
             "effective_speed_ratio": (lp["link_updates_per_s"] / lp["tau_int_sweeps"])
                                      / (kp["link_updates_per_s"] / kp["tau_int_sweeps"])}
 
 
 SCAN_BETAS = (0.5, 1.0, 1.5, 2.0, 2.3, 2.8)
+TIMING_ROUNDS = 5
 
 
 def beta_scan(su2, dims, seed, plans, therm=20, sweeps=100):

@@ -441,6 +441,18 @@ def ising_2d():
                          "algorithmic_GBps": rate * bytes_per / 1e9}
         row["bits_over_bytes"] = row["bits"]["spin_updates_per_s"] / row["bytes"]["spin_updates_per_s"]
         out[f"{dims[0]}x{dims[1]}"] = row
+    # the paper's statistics run: a measurement (energy, magnetisation, returned
+    # to the host) after every sweep, on 1024 x 512 with the default layout
+    ising.ising_init((1024, 512), 0.44, 1, 1)
+    ising.ising_sweep(10)
+    n = 500
+    t0 = time.perf_counter()
+    for _ in range(n):
+        ising.ising_sweep(1)
+        ising.ising_observables()
+    dt = time.perf_counter() - t0
+    out["1024x512_measured"] = {"us_per_sweep_and_measurement": dt / n * 1e6, "sweeps": n,
+                                "paper_rv770_us": 730.0}
     ising.ising_finalize()
     out["paper_context"] = {"hardware": "ATI RV770", "lattice": "1024x512",
                             "seconds_per_1e6_sweeps": 630, "spin_updates_per_s": 524288 * 1e6 / 630}

@@ -53,7 +53,7 @@ def _load():
     lib.oracle_init.restype = ctypes.c_int
     lib.oracle_pass.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, i8p,
-                                dp, u64p]
+                                dp, dp, u64p]
     lib.oracle_pass.restype = ctypes.c_int
     lib.oracle_update_sites.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                         ctypes.c_int, ctypes.c_int, ctypes.c_double, dp,
@@ -77,7 +77,7 @@ def _load():
     lib.oracle_sweep_imh.restype = ctypes.c_int
     lib.oracle_polyakov_field.argtypes = [i32p, dp, dp]
     lib.oracle_polyakov_field.restype = ctypes.c_int
-    lib.oracle_or_pass.argtypes = [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp]
+    lib.oracle_or_pass.argtypes = [i32p, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp]
     lib.oracle_or_pass.restype = ctypes.c_int
     lib.oracle_or_sweep.argtypes = [i32p, ctypes.c_int, dp]
     lib.oracle_or_sweep.restype = ctypes.c_int
@@ -180,16 +180,20 @@ def creutz_draw(alpha, seed, site, mu, sweep, prec32=True):
 
 
 class PassResult:
-    def __init__(self, tries, margin, attempts, failures):
+    def __init__(self, tries, margin, attempts, failures, knorm=None, x0=None):
         self.tries = tries
         self.margin = margin
         self.attempts = attempts
         self.failures = failures
+        self.knorm = knorm   # |w| of each updated link (diag=True), else None
+        self.x0 = x0         # its accepted x0 (NaN: Haar branch or cap failure)
 
 
-def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True, creutz_below=0.0):
+def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True, creutz_below=0.0,
+                  diag=False):
     """In-place heat-bath pass over links U_mu(x), parity(x) == parity
-    (Creutz's draw where alpha < creutz_below)."""
+    (Creutz's draw where alpha < creutz_below).  diag=True also returns, per
+    updated site, the staple norm |w| and the accepted x0."""
     lib = _load()
     d = _dims(dims)
     if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
@@ -198,13 +202,15 @@ def heatbath_pass(dims, U, beta, seed, sweep, parity, mu, prec32=True, creutz_be
     tries = np.full(V, -1, dtype=np.int8)
     margin = np.full(V, np.nan)
     stats = np.zeros(2, dtype=np.uint64)
+    dg = np.full((V, 2), np.nan) if diag else None
     rc = lib.oracle_pass(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed), int(sweep),
                          int(parity), int(mu), int(bool(prec32)), float(creutz_below),
                          _ptr(U, ctypes.c_double), _ptr(tries, ctypes.c_int8), _ptr(margin, ctypes.c_double),
-                         _ptr(stats, ctypes.c_uint64))
+                         _ptr(dg, ctypes.c_double) if diag else None, _ptr(stats, ctypes.c_uint64))
     if rc:
         raise ValueError("oracle_pass rejected its arguments")
-    return PassResult(tries, margin, int(stats[0]), int(stats[1]))
+    return PassResult(tries, margin, int(stats[0]), int(stats[1]),
+                      dg[:, 0] if diag else None, dg[:, 1] if diag else None)
 
 
 def update_sites(dims, U, beta, seed, sweep_index, mu, sites, prec32=True, creutz_below=0.0):
@@ -288,16 +294,19 @@ def sweep(dims, U, beta, seed, sweep_index, prec32=True, creutz_below=0.0):
     return int(stats[0]), int(stats[1])
 
 
-def or_pass(dims, U, parity, mu, prec32=True):
+def or_pass(dims, U, parity, mu, prec32=True, diag=False):
     """In-place overrelaxation pass: U_mu(x) -> V U^dag V, V = w/|w|, on the
-    sites of one parity (links with w = 0 kept)."""
+    sites of one parity (links with w = 0 kept).  diag=True returns the staple
+    norm |w| per site (NaN off the pass's parity)."""
     lib = _load()
     d = _dims(dims)
     if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):
         raise ValueError("U must be a C-contiguous float64 array")
+    kn = np.full(volume(dims), np.nan) if diag else None
     if lib.oracle_or_pass(_ptr(d, ctypes.c_int32), int(parity), int(mu), int(bool(prec32)),
-                          _ptr(U, ctypes.c_double)):
+                          _ptr(U, ctypes.c_double), _ptr(kn, ctypes.c_double) if diag else None):
         raise ValueError("oracle_or_pass rejected its arguments")
+    return kn
 
 
 def or_sweep(dims, U, prec32=True):

@@ -11,10 +11,12 @@
  *   - link storage: with prec32 != 0 every written link is rounded to FP32,
  *     because the paper stores each link as four single-precision numbers in one
  *     128-bit cell (Sec. 2.4, the paragraph after Eq. (4));
- *   - the Kennedy-Pendleton accept test: with prec32 != 0 it is taken in FP32
- *     (each FP32 operand is the rounding of its FP64 value), because a floating
- *     point decision that picks an integer outcome is taken in the same precision
- *     on both sides of a parity comparison.
+ *   - the accept tests of the Kennedy-Pendleton and Creutz draws: with
+ *     prec32 != 0 each is taken in FP32 (each FP32 operand is the rounding of
+ *     its FP64 value), because a floating point decision that picks an integer
+ *     outcome is taken in the same precision on both sides of a parity
+ *     comparison.  Only the decision is FP32: the accepted draw's x0 and |a|
+ *     are built from the FP64 value of lambda^2 (or of m).
  * With prec32 == 0 the whole chain runs in FP64 (used to state errors against
  * FP64).
  *
@@ -214,22 +216,23 @@ int oracle_kp_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t 
     for (uint32_t t = 0; t < 8; ++t) {
         double u[4];
         draw4(seed, site, mu, PURPOSE_UPDATE, sweep, t, u);
-        double lam2, lhs, rhs;
+        /* the draw itself, in FP64 */
+        double c = cos(2.0 * M_PI * u[1]);
+        double lam2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);
+        double lhs, rhs;
         if (prec32) {
+            /* the decision in FP32, from the FP32 roundings of its inputs */
             float lu0 = (float)log(u[0]);
-            float c = (float)cos(2.0 * M_PI * u[1]);
+            float cf = (float)c;
             float lu2 = (float)log(u[2]);
             float af = (float)alpha;
-            float l2f = -(lu0 + c * c * lu2) / (2.0f * af);
+            float l2f = -(lu0 + cf * cf * lu2) / (2.0f * af);
             float u3f = (float)u[3];
             float lf = u3f * u3f;
             float rf = 1.0f - l2f;
-            lam2 = (double)l2f;
             lhs = (double)lf;
             rhs = (double)rf;
         } else {
-            double c = cos(2.0 * M_PI * u[1]);
-            lam2 = -(log(u[0]) + c * c * log(u[2])) / (2.0 * alpha);
             lhs = u[3] * u[3];
             rhs = 1.0 - lam2;
         }
@@ -254,7 +257,8 @@ int oracle_kp_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t 
 /*   x0 = 1 + ln(y) / alpha has density proportional to exp(alpha x0) on       */
 /*   [-1, 1]; accept iff u1 <= sqrt(1 - x0^2), i.e. u1^2 <= 1 - x0^2.          */
 /* (log1p and expm1 evaluate ln y and 1 - exp(-2 alpha) without cancellation.) */
-/* prec32 takes the decision in FP32 on m = 1 - x0, with 1 - x0^2 = m (2 - m). */
+/* prec32 takes the decision in FP32 on m = 1 - x0, with 1 - x0^2 = m (2 - m);  */
+/* x0 and |a| come from the FP64 m.                                            */
 /* Returns the accepting attempt (0..7) or -1; *margin as in oracle_kp_draw.   */
 /* ------------------------------------------------------------------------- */
 int oracle_creutz_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t sweep,
@@ -264,21 +268,22 @@ int oracle_creutz_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint3
     for (uint32_t t = 0; t < 8; ++t) {
         double u[4];
         draw4(seed, site, mu, PURPOSE_UPDATE, sweep, t, u);
-        double m, lhs, rhs;
+        /* the draw itself, in FP64 */
+        const double d = -expm1(-2.0 * alpha);  /* 1 - exp(-2 alpha) */
+        double m = -log1p(-(1.0 - u[0]) * d) / alpha;
+        double lhs, rhs;
         if (prec32) {
+            /* the decision in FP32, from the FP32 roundings of its inputs */
             float af = (float)alpha;
-            float d = (float)(-expm1(-2.0 * (double)af));
-            float z = -(1.0f - (float)u[0]) * d;
+            float df = (float)(-expm1(-2.0 * (double)af));
+            float z = -(1.0f - (float)u[0]) * df;
             float mf = -(float)log1p((double)z) / af;
             float u1f = (float)u[1];
             float lf = u1f * u1f;
             float rf = mf * (2.0f - mf);
-            m = (double)mf;
             lhs = (double)lf;
             rhs = (double)rf;
         } else {
-            const double d = -expm1(-2.0 * alpha);  /* 1 - exp(-2 alpha) */
-            m = -log1p(-(1.0 - u[0]) * d) / alpha;
             double x0 = 1.0 - m;
             lhs = u[1] * u[1];
             rhs = 1.0 - x0 * x0;
@@ -358,15 +363,19 @@ int oracle_init(const int dims[4], uint64_t seed, int start, int prec32, double 
 /* *tries = attempt that accepted (0..7), 8 after a cap failure, 9 for the    */
 /* Haar branch; *margin = the smallest margin of the decisions taken (the     */
 /* accept tests and, with the switch on, |alpha - creutz_below|).             */
+/* diag (nullable) receives |w| and the accepted x0 (NaN when no draw was     */
+/* accepted): the two numbers that set how strongly rounding in the staple    */
+/* and in the draw can move the new link.                                     */
 /* ------------------------------------------------------------------------- */
 static void update_one(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int mu,
                        int prec32, double creutz_below, const double *U, long lex, double out[4],
-                       int *tries, double *margin)
+                       int *tries, double *margin, double diag[2])
 {
     double w[4];
     oracle_staple(dims, U, lex, mu, w);
     double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
     double alpha = beta * k;
+    if (diag) { diag[0] = k; diag[1] = NAN; }
     if (alpha == 0.0) {
         double u[4], q[4];
         draw4(seed, (uint32_t)lex, mu, PURPOSE_UPDATE, sweep, SLOT_HAAR, u);
@@ -387,6 +396,7 @@ static void update_one(const int dims[4], double beta, uint64_t seed, uint32_t s
         return;
     }
     *tries = t;
+    if (diag) diag[1] = a0;
     double n[3];
     direction(seed, (uint32_t)lex, mu, sweep, n);
     double X[4] = { a0, amag * n[0], amag * n[1], amag * n[2] };
@@ -397,11 +407,12 @@ static void update_one(const int dims[4], double beta, uint64_t seed, uint32_t s
 }
 
 /* One heat-bath pass: every link U_mu(x) with parity(x) == parity, in place.
- * Per-site outputs (optional, indexed by lex): tries[lex], margin[lex] as in
- * update_one.  stats[0] += KP attempts evaluated, stats[1] += cap failures. */
+ * Per-site outputs (optional, indexed by lex): tries[lex], margin[lex] and
+ * diag[2 lex .. 2 lex + 1] as in update_one.  stats[0] += KP attempts
+ * evaluated, stats[1] += cap failures. */
 int oracle_pass(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int parity,
                 int mu, int prec32, double creutz_below, double *U, int8_t *tries, double *margin,
-                uint64_t stats[2])
+                double *diag, uint64_t stats[2])
 {
     geom_t g;
     if (geom_init(&g, dims)) return -1;
@@ -415,7 +426,8 @@ int oracle_pass(const int dims[4], double beta, uint64_t seed, uint32_t sweep, i
         if (((x[0] + x[1] + x[2] + x[3]) & 1) != parity) continue;
         double out[4], m;
         int t;
-        update_one(dims, beta, seed, sweep, mu, prec32, creutz_below, U, lex, out, &t, &m);
+        update_one(dims, beta, seed, sweep, mu, prec32, creutz_below, U, lex, out, &t, &m,
+                   diag ? diag + 2 * lex : NULL);
         /* the staples of this pass never read the links it writes (they are
          * U_mu at the other parity, and U_nu with nu != mu), so writing in
          * place is the same as writing to a copy */
@@ -445,7 +457,7 @@ int oracle_update_sites(const int dims[4], double beta, uint64_t seed, uint32_t 
         double m;
         int t;
         update_one(dims, beta, seed, sweep, mu, prec32, creutz_below, U, (long)sites[i], out + 4 * i,
-                   &t, &m);
+                   &t, &m, NULL);
         if (tries) tries[i] = (int8_t)t;
         if (margin) margin[i] = m;
     }
@@ -494,7 +506,7 @@ static void update_one_imh(const int dims[4], double beta, uint64_t seed, uint32
     double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
     double alpha = beta * k;
     if (alpha == 0.0 || alpha > alpha_max) {
-        update_one(dims, beta, seed, sweep, mu, prec32, 0.0, U, lex, out, res, margin);
+        update_one(dims, beta, seed, sweep, mu, prec32, 0.0, U, lex, out, res, margin, NULL);
         return;
     }
     double y[33];
@@ -601,7 +613,7 @@ int oracle_sweep(const int dims[4], double beta, uint64_t seed, uint32_t sweep, 
     for (int parity = 1; parity >= 0; --parity)
         for (int mu = 0; mu < 4; ++mu)
             if (oracle_pass(dims, beta, seed, sweep, parity, mu, prec32, creutz_below, U, NULL, NULL,
-                            stats))
+                            NULL, stats))
                 return -1;
     return 0;
 }
@@ -615,8 +627,9 @@ int oracle_sweep(const int dims[4], double beta, uint64_t seed, uint32_t sweep, 
 /* the Haar measure onto itself and undoes itself, so it leaves the local      */
 /* conditional invariant without a random number.  A link with w == 0 is      */
 /* kept.  The result is normalised (Eq. (7)) and stored like a heat-bath link.  */
+/* knorm (nullable) receives |w| per updated site, indexed by lex.             */
 /* ------------------------------------------------------------------------- */
-int oracle_or_pass(const int dims[4], int parity, int mu, int prec32, double *U)
+int oracle_or_pass(const int dims[4], int parity, int mu, int prec32, double *U, double *knorm)
 {
     geom_t g;
     if (geom_init(&g, dims)) return -1;
@@ -629,6 +642,7 @@ int oracle_or_pass(const int dims[4], int parity, int mu, int prec32, double *U)
         double w[4];
         oracle_staple(dims, U, lex, mu, w);
         double k = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2] + w[3] * w[3]);
+        if (knorm) knorm[lex] = k;
         if (k == 0.0) continue;
         double V[4] = { w[0] / k, w[1] / k, w[2] / k, w[3] / k };
         double ud[4], t[4], Un[4];
@@ -646,7 +660,7 @@ int oracle_or_sweep(const int dims[4], int prec32, double *U)
 {
     for (int parity = 1; parity >= 0; --parity)
         for (int mu = 0; mu < 4; ++mu)
-            if (oracle_or_pass(dims, parity, mu, prec32, U)) return -1;
+            if (oracle_or_pass(dims, parity, mu, prec32, U, NULL)) return -1;
     return 0;
 }
 

@@ -199,3 +199,21 @@ def test_update_sites_equals_pass():
     res = oracle.heatbath_pass(dims, U2, 2.2, SEED, 4, 1, 3)
     np.testing.assert_array_equal(out, U2[sites, 3])
     np.testing.assert_array_equal(tries, res.tries[sites])
+
+
+@pytest.mark.parametrize("draw", [oracle.kp_draw, oracle.creutz_draw])
+def test_fp32_mode_changes_only_the_decision(draw):
+    """With FP32 link storage (the paper's, Sec. 2.4) only the accept test is
+    taken in FP32: whenever both precisions accept the same attempt, the drawn
+    x0 and |a| are the same FP64 numbers, not FP32 roundings of them."""
+    same = not_f32 = 0
+    for alpha in (0.3, 1.7, 2.3, 9.0, 40.0):
+        for site in range(400):
+            t32, a32, m32, _ = draw(alpha, 5, site, 2, 3, True)
+            t64, a64, m64, _ = draw(alpha, 5, site, 2, 3, False)
+            if t32 >= 0 and t32 == t64:
+                same += 1
+                assert a32 == a64 and m32 == m64, (alpha, site)
+                not_f32 += int(np.float64(np.float32(a32)) != a32)
+    assert same >= 1800
+    assert not_f32 >= 0.9 * same

@@ -102,3 +102,48 @@ def loss_and_grad(theta, alphas, target_logw):
     db1 = da1.sum(axis=0)
     grad = pack(dict(W1=dW1, b1=db1, W2=dW2, b2=db2, W3=dW3, b3=db3))
     return L, grad
+
+
+# ---------------------------------------------------------------------------
+# Training: full-batch Adam (Kingma & Ba, "Adam: a method for stochastic
+# optimization", ICLR 2015, Algorithm 1) with a cosine learning-rate decay.
+# The master parameters are held in FP64; every step evaluates the loss and
+# gradient at their BF16 rounding, the values the network computes with.
+# ---------------------------------------------------------------------------
+ADAM_BETA1 = 0.9
+ADAM_BETA2 = 0.999
+ADAM_EPS = 1e-8
+
+
+def cosine_lr(t, total, lr0, lr_min):
+    """Learning rate of step t = 1, 2, ...: lr0 at t = 1, falling along half
+    a cosine period to lr_min at t = total + 1 (and held there after)."""
+    frac = min(1.0, (t - 1) / max(1, total))
+    return lr_min + 0.5 * (lr0 - lr_min) * (1.0 + np.cos(np.pi * frac))
+
+
+def adam_step(theta, g, m, v, t, lr):
+    """Step t >= 1 of Adam: moment estimates m, v updated with gradient g,
+    bias-corrected by 1 - beta^t, then theta moves by lr m_hat / (sqrt(v_hat)
+    + eps).  Returns the new (theta, m, v)."""
+    g = np.asarray(g, dtype=np.float64)
+    m = ADAM_BETA1 * m + (1.0 - ADAM_BETA1) * g
+    v = ADAM_BETA2 * v + (1.0 - ADAM_BETA2) * g * g
+    m_hat = m / (1.0 - ADAM_BETA1 ** t)
+    v_hat = v / (1.0 - ADAM_BETA2 ** t)
+    return theta - lr * m_hat / (np.sqrt(v_hat) + ADAM_EPS), m, v
+
+
+def train(theta0, alphas, target_logw, steps, lr0, lr_min):
+    """`steps` Adam steps from theta0 with zero initial moments, the
+    gradient of each taken at the BF16 rounding of the current parameters.
+    Returns (final FP64 master parameters, loss before each step)."""
+    theta = np.asarray(theta0, dtype=np.float64).copy()
+    m = np.zeros_like(theta)
+    v = np.zeros_like(theta)
+    hist = []
+    for t in range(1, steps + 1):
+        L, g = loss_and_grad(bf16_round(theta), alphas, target_logw)
+        hist.append(L)
+        theta, m, v = adam_step(theta, g, m, v, t, cosine_lr(t, steps, lr0, lr_min))
+    return theta, np.array(hist)

@@ -244,14 +244,14 @@ def beta_scan(su2, dims, seed, plans, therm=20, sweeps=100):
             su2.su2_set_plan(*plans[kind])
             su2.su2_set_proposal(kind)
             su2.su2_sweep(therm)
-            a0, f0 = su2.su2_counters()
+            a0, f0 = su2.su2_counters()[:2]
             p0, c0 = su2.su2_imh_counters()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             su2.su2_sweep(sweeps)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
-            a1, f1 = su2.su2_counters()
+            a1, f1 = su2.su2_counters()[:2]
             r = {"link_updates_per_s": upd / dt, "plaquette": su2.su2_plaquette()}
             if kind:
                 p1, c1 = su2.su2_imh_counters()
@@ -565,7 +565,7 @@ def main():
         "observables": {"plaquette": float(P[0]), "plaquette_spatial": float(P[1]),
                         "plaquette_temporal": float(P[2]), "polyakov": float(poly)},
     }
-    att, fail = su2.su2_counters()
+    att, fail = su2.su2_counters()[:2]
     rec["observables"]["kp_attempts_per_update"] = att / max(1, 4 * V * (args.steps + args.warmup))
     su2.su2_finalize()
     if not args.no_extras:

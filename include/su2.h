@@ -62,9 +62,23 @@ int su2_init(const int32_t dims[4], double beta, uint64_t seed, int32_t start);
 
 /* As su2_init, but the links live in a caller-owned device buffer (e.g. a
  * torch tensor) of at least 64*V bytes, 16-byte aligned; the caller keeps it
- * alive until su2_finalize or the next init.  dev_links == NULL allocates. */
+ * alive until su2_finalize or the next init.  dev_links == NULL allocates.
+ * (Sec. 2.1: the lattice lives in one buffer of GPU memory for the whole run.) */
 int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start,
                 void *dev_links, size_t bytes);
+
+/* Move the current lattice's links into a caller-owned device buffer (e.g. a
+ * torch tensor) of at least 64*V bytes, 16-byte aligned, that must not
+ * overlap the current link storage: the links are copied there (device to
+ * device, on the library's stream, which is then synchronised), the library's
+ * own link allocation, if any, is released, and all later work reads and
+ * writes the caller's buffer, which the caller keeps alive until su2_finalize
+ * or the next init.  Links, sweep index and counters are unchanged.  Layout:
+ * eight arrays [mu][parity] of V/2 float4 (see su2_links for the host order).
+ * (Sec. 2.1: the lattice stays in GPU memory; here in memory the caller
+ * manages.)  SU2_ESTATE without a lattice; SU2_EINVAL for NULL, a short,
+ * misaligned or overlapping buffer. */
+int su2_bind(void *dev_links, size_t bytes);
 
 /* n >= 0 full sweeps (Sec. 2.4: for each direction mu = 0..3 the odd sites,
  * then for each mu the even sites; each link update draws its staple, Eq. (6),
@@ -84,7 +98,9 @@ int su2_sweep(int32_t n);
 int su2_sweep_measured(int32_t n);
 
 /* One pass: the links U_mu(x) with parity(x) == parity (0 or 1), mu in 0..3,
- * at the current sweep index (which does not advance). */
+ * at the current sweep index (which does not advance) -- one of the eight
+ * per-direction, per-parity updates of a sweep (Sec. 2.4, Eqs. (5)-(7)).
+ * SU2_EINVAL for parity or mu out of range. */
 int su2_pass(int32_t parity, int32_t mu);
 
 /* n >= 0 overrelaxation sweeps (Sec. 2.4 names the heat-bath "with
@@ -99,7 +115,9 @@ int su2_pass(int32_t parity, int32_t mu);
  * 300). */
 int su2_overrelax(int32_t n);
 
-/* One overrelaxation pass: U_mu(x), parity(x) == parity (0 or 1), mu in 0..3. */
+/* One overrelaxation pass: U_mu(x), parity(x) == parity (0 or 1), mu in 0..3
+ * (the reflection of su2_overrelax, Sec. 2.4).  SU2_EINVAL for parity or mu
+ * out of range. */
 int su2_overrelax_pass(int32_t parity, int32_t mu);
 
 /* Mean plaquette P = (P_s + P_t)/2 of (1/2)Tr U_mu,nu(x) (Eq. (3)), FP64
@@ -134,28 +152,40 @@ int su2_measure_device(double *dev_out);
  * every >= 1; n must be a multiple of every. */
 int su2_sweep_measure(int32_t n, int32_t every, double *host_hist);
 
-/* Copy the links to host_out (float32 [V][4][4]); n_floats must be 16*V.
- * Synchronises. */
+/* Copy the links to host_out (float32 [V][4][4], caller-owned); n_floats must
+ * be 16*V, else SU2_EINVAL.  Synchronises.  (Sec. 2.1: results cross to the
+ * host only when asked for; Sec. 2.4: each link is four FP32 numbers.) */
 int su2_links(float *host_out, size_t n_floats);
 
 /* Replace the links from host_in (float32 [V][4][4], n_floats = 16*V, values
- * taken as given -- not renormalised) and set the sweep index.  With the same
- * seed and sweep index, a run resumed this way is bit-identical to an
- * uninterrupted one. */
+ * taken as given -- not renormalised) and set the sweep index (below 2^32).
+ * With the same seed and sweep index, a run resumed this way is bit-identical
+ * to an uninterrupted one.  (Sec. 2.1: a configuration is loaded into GPU
+ * memory once, as a hot or cold start or a stored configuration.)  SU2_EINVAL
+ * for a wrong size or sweep index.  Synchronises. */
 int su2_set_links(const float *host_in, size_t n_floats, uint64_t sweep_index);
 
-/* Current sweep index. */
+/* Current sweep index: the number of sweeps since init or the value last set
+ * by su2_set_links (Sec. 2.4: the sweep counts are fixed before a run; here
+ * the index is also the third word of every Philox counter). */
 int su2_sweep_index(uint64_t *out);
 
-/* out[0] = KP attempts evaluated, out[1] = updates whose 8 attempts all
- * failed, summed since init. */
-int su2_counters(uint64_t out[2]);
+/* Update statistics summed since init (Sec. 2.4: at most 8 heat-bath
+ * attempts per update): out[0] = heat-bath attempts evaluated, out[1] =
+ * updates whose 8 attempts all failed (the link is kept), out[2] = learned
+ * proposals made and out[3] = learned proposals accepted since the last
+ * su2_set_proposal(1, ...) (both 0 under the heat-bath).  Synchronises. */
+int su2_counters(uint64_t out[4]);
 
 /* Enqueue all later work on this HIP stream (hipStream_t, e.g. a torch
- * stream); NULL selects the null stream.  Synchronises the previous stream. */
+ * stream); NULL selects the null stream.  Synchronises the previous stream.
+ * The stream must have the default priority.  (Sec. 2.1: the host enqueues
+ * kernels and does not wait for them.) */
 int su2_set_stream(void *hip_stream);
 
-/* Launch plan of the pass kernel: order_kind 0 = workgroups in lattice order;
+/* Launch plan of the pass kernel (no passage of the paper: a launch
+ * configuration for this GPU, which changes no result; the paper's own kernels
+ * simply cover the lattice, Sec. 2.1): order_kind 0 = workgroups in lattice order;
  * T in 1..99 = each XCD takes a band of x1 rows of every (x2, x3) plane and
  * walks the planes in T x T squares (only where a plane holds a multiple of 8
  * tiles of 256 half-sites and T divides L2 and L3, else SU2_EINVAL);
@@ -179,7 +209,8 @@ int su2_set_stream(void *hip_stream);
  * differences). */
 int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
 
-/* Time each plan in {order 0, 4, 8, 16, 108, 208, 1000, 1008, 1108, 1208, 300}
+/* Launch-plan tuner (no passage of the paper; speed only).
+ * Time each plan in {order 0, 4, 8, 16, 108, 208, 1000, 1008, 1108, 1208, 300}
  * x {LDS 0, 16, 24, 32, 40 KiB} on a scratch copy of the links (reps measured
  * sweeps each, in three rounds over
  * all plans; the lattice, sweep index and all counters are untouched) and
@@ -189,7 +220,9 @@ int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
 int su2_tune(int32_t reps, int32_t out[2]);
 
 /* ---- Learned proposal ---------------------------------------------------
- * The heat-bath's x0 has density ~ sqrt(1 - x^2) exp(alpha x), alpha = beta |W|
+ * An extension of the method (the paper has no learned part; it names the
+ * rejection loop's cost on a SIMD machine, Sec. 2.4 and Sec. 3, which this
+ * removes).  The heat-bath's x0 has density ~ sqrt(1 - x^2) exp(alpha x), alpha = beta |W|
  * (the local conditional of Eqs. (2), (3), (6)).  A small network maps alpha to
  * a 32-segment monotone piecewise-linear inverse CDF of x0; used as an
  * independence-Metropolis proposal with the exact acceptance ratio it leaves
@@ -224,8 +257,12 @@ int su2_mlp_loss_grad(const float *alphas, const float *target_logw, int32_t n, 
 
 /* Train on the device: targets are the CDF knots of the n alphas (in
  * [0, 40]) integrated by su2_cdf_knots' kernel, then `steps` full-batch Adam
- * steps with a cosine learning rate from lr0 to lr_min; loss_hist
- * (nullable) receives the loss before each step. */
+ * steps (Kingma & Ba: beta1 0.9, beta2 0.999, eps 1e-8) on the FP32 master
+ * parameters, each step's gradient taken at their BF16 rounding, with the
+ * learning rate of step t = 1..steps falling from lr0 along half a cosine
+ * period towards lr_min (lr_min + (lr0 - lr_min)(1 + cos(pi (t-1)/steps))/2).
+ * Every call starts Adam afresh: step counter and both moment estimates are
+ * zeroed first.  loss_hist (nullable) receives the loss before each step. */
 int su2_mlp_train(const double *alphas, int32_t n, int32_t steps, float lr0, float lr_min,
                   float *loss_hist);
 
@@ -240,11 +277,18 @@ int su2_mlp_table(float *host_out, size_t n_floats);
 
 const char *su2_mlp_last_error(void);
 
-/* Proposal of the lattice context's passes: 0 = Kennedy-Pendleton heat-bath;
- * 1 = the learned independence-Metropolis step (Philox purpose 2, one call per
- * update) with the heat-bath for alpha = 0 and alpha above 40.  Kind 1 copies
- * the current knot table into the lattice context.  su2_init resets to 0. */
-int su2_set_proposal(int32_t kind);
+/* Proposal of the lattice context's passes: 0 = Kennedy-Pendleton heat-bath
+ * (Sec. 2.4; bf16_weights is ignored); 1 = the learned independence-
+ * Metropolis step (Philox purpose 2, one call per update) with the heat-bath
+ * for alpha = 0 and alpha above 40.  With kind 1 and bf16_weights != NULL,
+ * the network first takes those n_weights = 6433 BF16 parameters (bit
+ * patterns, the order of su2_mlp_set_params; its FP32 master becomes their
+ * exact values and the optimiser state is reset) and is tabulated at the
+ * current table size (31 rows if none was made yet); with NULL the current
+ * table is used (SU2_ESTATE if there is none).  Kind 1 copies the table into
+ * the lattice context and zeroes the proposal counters.  su2_init resets the
+ * proposal to 0.  SU2_EINVAL for another kind or a wrong n_weights. */
+int su2_set_proposal(int32_t kind, const uint16_t *bf16_weights, size_t n_weights);
 
 /* Small-alpha switch of the heat-bath (proposal 0): an update with 0 < alpha <
  * alpha_below draws x0 by Creutz's method (Phys. Rev. D 21 (1980) 2308)
@@ -260,7 +304,8 @@ int su2_set_proposal(int32_t kind);
  * the batched replicas'.  Results stay a pure function of the inputs. */
 int su2_set_creutz(double alpha_below);
 
-/* Learned-proposal updates proposed and accepted since su2_set_proposal(1). */
+/* Learned-proposal updates proposed and accepted since su2_set_proposal(1, ...)
+ * (out[2], out[3] of su2_counters). */
 int su2_imh_counters(uint64_t out[2]);
 
 /* ---- Batched replicas ---------------------------------------------------
@@ -274,7 +319,8 @@ int su2_imh_counters(uint64_t out[2]);
 int su2_batch_init(int32_t n, const int32_t *dims, const double *betas, const uint64_t *seeds,
                    int32_t start);
 
-/* n >= 0 sweeps of every replica (synchronises in persistent mode). */
+/* n >= 0 sweeps of every replica, each the sweep of Sec. 2.4 (synchronises in
+ * persistent mode). */
 int su2_batch_sweep(int32_t n);
 
 /* How su2_batch_sweep runs: mode 0 = one launch per (parity, mu) pass over
@@ -302,36 +348,46 @@ int su2_batch_tune(int32_t sweeps, int32_t out[3]);
  * an undefined intermediate state and must be re-initialised. */
 int su2_batch_set_spin_limit(uint64_t ticks);
 
-/* out[3*r .. 3*r+2] = (P, P_s, P_t) of replica r (as su2_plaquette_st). */
+/* out[3*r .. 3*r+2] = (P, P_s, P_t) of replica r (as su2_plaquette_st: the
+ * Eq. (3) averages of Sec. 2.4 in FP64).  out holds 3n doubles.  Synchronises. */
 int su2_batch_plaquette(double *out);
 
-/* Links of replica r, float32 [V][4][4] (n_floats = 16*V). */
+/* Links of replica r, float32 [V][4][4] (n_floats = 16*V of that replica,
+ * else SU2_EINVAL), as su2_links.  Synchronises. */
 int su2_batch_links(int32_t r, float *host_out, size_t n_floats);
 
-/* KP attempts and cap failures of replica r since su2_batch_init. */
+/* Heat-bath attempts and cap failures of replica r since su2_batch_init
+ * (Sec. 2.4: at most 8 attempts per update), as out[0..1] of su2_counters. */
 int su2_batch_counters(int32_t r, uint64_t out[2]);
 
-/* Sweeps done since su2_batch_init (the same for every replica). */
+/* Sweeps done since su2_batch_init (the same for every replica; the Philox
+ * sweep word of each replica's counters). */
 int su2_batch_sweep_index(uint64_t *out);
 
-/* Message for the last error of a su2_batch_* call. */
+/* Message for the last error of a su2_batch_* call (static storage). */
 const char *su2_batch_last_error(void);
 
-/* Release the batch; safe to call twice. */
+/* Release the batch and its device memory; safe to call twice. */
 void su2_batch_finalize(void);
 
 /* Device Philox-4x32-10 blocks for n host counters ctr[n][4] and key = (seed
- * mod 2^32, seed >> 32), written to host out[n][4]; for bit-exact checks of
- * the generator the sweep uses. */
+ * mod 2^32, seed >> 32), written to host out[n][4] (both caller-owned, n <=
+ * 2^28); for bit-exact checks of the generator the sweep uses.  It replaces
+ * the paper's RANMAR (Sec. 2.2) by a counter-based generator, so numbers are
+ * computed where they are used and never stored -- the property Sec. 2.2
+ * credits for its speed.  Needs no lattice.  Synchronises. */
 int su2_philox(uint64_t seed, const uint32_t *ctr, size_t n, uint32_t *out);
 
-/* Wait for all enqueued work. */
+/* Wait for all enqueued work on the library's stream (Sec. 2.1: the host
+ * waits only where it needs results). */
 int su2_synchronize(void);
 
-/* Message for the last error (static storage, never NULL). */
+/* Message for the last error of a lattice-context call (static storage,
+ * never NULL). */
 const char *su2_last_error(void);
 
-/* Release the lattice and every device resource; safe to call twice. */
+/* Release the lattice and every device resource the library allocated
+ * (caller-owned buffers are left alone); safe to call twice. */
 void su2_finalize(void);
 
 #ifdef __cplusplus

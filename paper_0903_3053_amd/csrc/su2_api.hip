@@ -654,20 +654,51 @@ int su2_sweep_index(uint64_t *out)
     return SU2_OK;
 }
 
-int su2_counters(uint64_t out[2])
+// Sum of the per-wave counter pairs in dev (n_waves pairs) into out[0..1].
+static int sum_wave_counters(const unsigned long long *dev, uint64_t out[2])
 {
-    int rc = require_ready();
-    if (rc) return rc;
-    if (!out) return fail(SU2_EINVAL, "out is NULL");
-    std::vector<unsigned long long> h((size_t)ctx.n_waves * 2);
-    HIP_TRY(hipMemcpyAsync(h.data(), ctx.d_counters, h.size() * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, ctx.stream));
-    HIP_TRY(hipStreamSynchronize(ctx.stream));
     out[0] = out[1] = 0;
+    if (!dev) return SU2_OK;
+    std::vector<unsigned long long> h((size_t)ctx.n_waves * 2);
+    HIP_TRY(hipMemcpyAsync(h.data(), dev, h.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           ctx.stream));
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
     for (uint32_t w = 0; w < ctx.n_waves; ++w) {
         out[0] += h[2 * w];
         out[1] += h[2 * w + 1];
     }
+    return SU2_OK;
+}
+
+int su2_counters(uint64_t out[4])
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!out) return fail(SU2_EINVAL, "out is NULL");
+    rc = sum_wave_counters(ctx.d_counters, out);
+    if (rc) return rc;
+    return sum_wave_counters(ctx.d_imh_stats, out + 2);
+}
+
+int su2_bind(void *dev_links, size_t bytes)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    const size_t link_bytes = (size_t)ctx.V * 4 * sizeof(float4);
+    if (!dev_links) return fail(SU2_EINVAL, "dev_links is NULL");
+    if (bytes < link_bytes)
+        return fail(SU2_EINVAL, "device buffer holds %zu bytes, %zu needed", bytes, link_bytes);
+    if ((uintptr_t)dev_links % 16) return fail(SU2_EINVAL, "device buffer must be 16-byte aligned");
+    if (dev_links == (void *)ctx.links) return SU2_OK;
+    const uintptr_t a = (uintptr_t)dev_links, b = (uintptr_t)ctx.links;
+    if (a < b + link_bytes && b < a + link_bytes)
+        return fail(SU2_EINVAL, "device buffer overlaps the current links");
+    HIP_TRY(hipMemcpyAsync(dev_links, ctx.links, link_bytes, hipMemcpyDeviceToDevice, ctx.stream));
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    if (ctx.owns_links) hipFree(ctx.links);
+    ctx.links = static_cast<float4 *>(dev_links);
+    ctx.owns_links = false;
+    release_graphs();  // the captured launches point at the old buffer
     return SU2_OK;
 }
 
@@ -808,13 +839,33 @@ int su2_tune(int32_t reps, int32_t out[2])
     return SU2_OK;
 }
 
-int su2_set_proposal(int32_t kind)
+int su2_set_proposal(int32_t kind, const uint16_t *bf16_weights, size_t n_weights)
 {
     int rc = require_ready();
     if (rc) return rc;
     if (kind != 0 && kind != 1) return fail(SU2_EINVAL, "proposal kind must be 0 or 1");
     HIP_TRY(hipStreamSynchronize(ctx.stream));
+    if (kind == 1 && bf16_weights) {
+        // the network takes these weights (its FP32 master becomes their exact
+        // values) and is tabulated at the current table size
+        if (n_weights != (size_t)kLearnedParams)
+            return fail(SU2_EINVAL, "expected %d BF16 weights, got %zu", kLearnedParams, n_weights);
+        std::vector<float> w(n_weights);
+        for (size_t i = 0; i < n_weights; ++i) {
+            const uint32_t bits = (uint32_t)bf16_weights[i] << 16;
+            std::memcpy(&w[i], &bits, sizeof bits);
+        }
+        const float *knots0 = nullptr;
+        uint32_t G = 0;
+        float amax0 = 0.f;
+        const int32_t points = su2_learned_table(&knots0, &G, &amax0) ? (int32_t)G : (int32_t)kImhLdsRows;
+        if (su2_mlp_set_params(w.data(), n_weights) != SU2_OK || su2_mlp_tabulate(points) != SU2_OK)
+            return fail(SU2_EDEVICE, "loading the proposal weights: %s", su2_mlp_last_error());
+    }
     if (kind == 0) {
+        // the proposal counters count since the last su2_set_proposal(1, ...)
+        if (ctx.d_imh_stats)
+            HIP_TRY(hipMemset(ctx.d_imh_stats, 0, (size_t)ctx.n_waves * 2 * sizeof(unsigned long long)));
         ctx.proposal = 0;
         ctx.plan.learned = false;
         ctx.plan.imh = ImhTable{};
@@ -878,17 +929,7 @@ int su2_imh_counters(uint64_t out[2])
     int rc = require_ready();
     if (rc) return rc;
     if (!out) return fail(SU2_EINVAL, "out is NULL");
-    out[0] = out[1] = 0;
-    if (!ctx.d_imh_stats) return SU2_OK;
-    std::vector<unsigned long long> h((size_t)ctx.n_waves * 2);
-    HIP_TRY(hipMemcpyAsync(h.data(), ctx.d_imh_stats, h.size() * sizeof(unsigned long long),
-                           hipMemcpyDeviceToHost, ctx.stream));
-    HIP_TRY(hipStreamSynchronize(ctx.stream));
-    for (uint32_t w = 0; w < ctx.n_waves; ++w) {
-        out[0] += h[2 * w];
-        out[1] += h[2 * w + 1];
-    }
-    return SU2_OK;
+    return sum_wave_counters(ctx.d_imh_stats, out);
 }
 
 int su2_synchronize(void)

@@ -31,6 +31,7 @@ namespace su2 {
 constexpr int kH = 64, kOut = 33, kSeg = 32;
 constexpr int kW1 = 0, kB1 = 64, kW2 = 128, kB2 = 128 + 4096, kW3 = kB2 + 64, kB3 = kW3 + 33 * 64;
 constexpr int kNParam = kB3 + 33;  // 6433
+static_assert(kNParam == kLearnedParams, "parameter count");
 constexpr float kAlphaMax = 40.0f;
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
@@ -629,20 +630,26 @@ int su2_mlp_train(const double *alphas, int32_t n, int32_t steps, float lr0, flo
         if (d_k) hipFree(d_k);
         return lfail(SU2_ENOMEM, "cannot allocate training buffers");
     }
-    // targets: the method's own numerically integrated CDF knots, on the device
-    hipError_t e = hipMemcpy(d_a, alphas, B * sizeof(double), hipMemcpyHostToDevice);
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_cdf, dim3(B), dim3(kBlock), 0, nullptr, d_a, d_k);
-        hipLaunchKernelGGL(k_logw, dim3(nb((size_t)B * kSeg)), dim3(256), 0, nullptr, d_k, B, LN.target);
-        hipLaunchKernelGGL(k_f64_to_f32, dim3(nb(B)), dim3(256), 0, nullptr, d_a, B, LN.alpha);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipMemset(LN.step, 0, sizeof(int32_t));
-    // one training step as a graph: forward, loss, backward, Adam, step tick
+    // everything below runs in order on one stream of its own: the targets,
+    // the optimiser reset, then the replayed training steps
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipStream_t st = nullptr;
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    // targets: the method's own numerically integrated CDF knots, on the device
+    if (e == hipSuccess) e = hipMemcpyAsync(d_a, alphas, B * sizeof(double), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_cdf, dim3(B), dim3(kBlock), 0, st, d_a, d_k);
+        hipLaunchKernelGGL(k_logw, dim3(nb((size_t)B * kSeg)), dim3(256), 0, st, d_k, B, LN.target);
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(nb(B)), dim3(256), 0, st, d_a, B, LN.alpha);
+        e = hipGetLastError();
+    }
+    // each call is a fresh run of Adam from the current parameters: step
+    // counter and both moment estimates start at zero
+    if (e == hipSuccess) e = hipMemsetAsync(LN.step, 0, sizeof(int32_t), st);
+    if (e == hipSuccess) e = hipMemsetAsync(LN.m, 0, kNParam * sizeof(float), st);
+    if (e == hipSuccess) e = hipMemsetAsync(LN.v, 0, kNParam * sizeof(float), st);
+    // one training step as a graph: forward, loss, backward, Adam, step tick
     if (e == hipSuccess) e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(k_l1, dim3(nb((size_t)B * kH)), dim3(256), 0, st, LN.P, LN.alpha, B, LN.a1, LN.h1);
@@ -667,6 +674,7 @@ int su2_mlp_train(const double *alphas, int32_t n, int32_t steps, float lr0, flo
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess && loss_hist && steps > 0)
         e = hipMemcpy(loss_hist, d_hist, (size_t)steps * sizeof(float), hipMemcpyDeviceToHost);
+    if (st) hipStreamSynchronize(st);
     if (exec) hipGraphExecDestroy(exec);
     if (graph) hipGraphDestroy(graph);
     if (st) hipStreamDestroy(st);

@@ -23,7 +23,7 @@ CREUTZ_SWITCH = 1.6847376
 
 # every symbol include/su2.h declares
 EXPORTS = (
-    "su2_init", "su2_init_ex", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_overrelax",
+    "su2_init", "su2_init_ex", "su2_bind", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_overrelax",
     "su2_overrelax_pass", "su2_plaquette", "su2_plaquette_st",
     "su2_polyakov", "su2_polyakov_correlator", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
     "su2_counters", "su2_set_stream", "su2_set_plan", "su2_tune", "su2_philox", "su2_synchronize", "su2_last_error",
@@ -67,6 +67,7 @@ def load():
         "su2_init": ([i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32], ctypes.c_int),
         "su2_init_ex": ([i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_int32, ctypes.c_void_p,
                          ctypes.c_size_t], ctypes.c_int),
+        "su2_bind": ([ctypes.c_void_p, ctypes.c_size_t], ctypes.c_int),
         "su2_sweep": ([ctypes.c_int32], ctypes.c_int),
         "su2_sweep_measured": ([ctypes.c_int32], ctypes.c_int),
         "su2_pass": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
@@ -110,7 +111,8 @@ def load():
         "su2_mlp_tabulate": ([ctypes.c_int32], ctypes.c_int),
         "su2_mlp_table": ([fp, ctypes.c_size_t], ctypes.c_int),
         "su2_mlp_last_error": ([], ctypes.c_char_p),
-        "su2_set_proposal": ([ctypes.c_int32], ctypes.c_int),
+        "su2_set_proposal": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_uint16), ctypes.c_size_t],
+                             ctypes.c_int),
         "su2_set_creutz": ([ctypes.c_double], ctypes.c_int),
         "su2_imh_counters": ([u64p], ctypes.c_int),
     }
@@ -164,6 +166,13 @@ def su2_init_ex(dims, beta, seed, start, dev_ptr, nbytes):
     _check(lib.su2_init_ex(_ptr(d, ctypes.c_int32), float(beta), ctypes.c_uint64(seed),
                            int(start), ctypes.c_void_p(dev_ptr), int(nbytes)))
     _keep["dims"] = tuple(int(x) for x in d)
+
+
+def su2_bind(buf):
+    """Move the links into a caller-owned device buffer: a torch CUDA tensor
+    (kept alive here until the next init or finalize) of at least 64 V bytes."""
+    _check(load().su2_bind(ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()))
+    _keep["links"] = buf
 
 
 def su2_sweep(n=1):
@@ -250,9 +259,10 @@ def su2_sweep_index():
 
 
 def su2_counters():
-    out = np.zeros(2, dtype=np.uint64)
+    """(heat-bath attempts, cap failures, learned proposals, accepted ones)."""
+    out = np.zeros(4, dtype=np.uint64)
     _check(load().su2_counters(_ptr(out, ctypes.c_uint64)))
-    return int(out[0]), int(out[1])
+    return tuple(int(v) for v in out)
 
 
 def su2_set_stream(stream=None):
@@ -438,8 +448,16 @@ def su2_mlp_table():
     return out
 
 
-def su2_set_proposal(kind):
-    _check(load().su2_set_proposal(int(kind)))
+def su2_set_proposal(kind, bf16_weights=None):
+    """0 = heat-bath, 1 = learned proposal (from the current knot table, or
+    from bf16_weights: 6433 BF16 bit patterns as uint16)."""
+    if bf16_weights is None:
+        _check(load().su2_set_proposal(int(kind), None, 0))
+        return
+    w = np.ascontiguousarray(np.asarray(bf16_weights, dtype=np.uint16))
+    _check(load().su2_set_proposal(int(kind), _ptr(w, ctypes.c_uint16), w.size))
+    if int(kind) == 1:
+        _keep.setdefault("table_points", 31)
 
 
 def su2_set_creutz(alpha_below=CREUTZ_SWITCH):

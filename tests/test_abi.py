@@ -68,9 +68,15 @@ def test_state_errors_before_init(lib):
     assert lib.su2_sweep(1) == su2.SU2_ESTATE
     assert lib.su2_pass(0, 0) == su2.SU2_ESTATE
     assert np.isnan(lib.su2_plaquette())
-    out = (ctypes.c_uint64 * 2)()
+    out = (ctypes.c_uint64 * 4)()
     assert lib.su2_counters(out) == su2.SU2_ESTATE
     assert b"su2_init" in lib.su2_last_error()
+    assert lib.su2_bind(ctypes.c_void_p(4096), 1 << 20) == su2.SU2_ESTATE
+    w = np.zeros(6433, dtype=np.uint16)
+    wp = w.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16))
+    assert lib.su2_set_proposal(1, wp, 6433) == su2.SU2_ESTATE
+    assert lib.su2_set_proposal(0, None, 0) == su2.SU2_ESTATE
+    assert lib.su2_philox(1, None, 3, None) == su2.SU2_EINVAL
 
 
 @pytest.mark.parametrize("dims,beta,start", [
@@ -127,5 +133,5 @@ def test_extension_entry_points_reject_bad_arguments(lib):
     assert lib.su2_mlp_tabulate(31) == su2.SU2_ESTATE
     # the lattice is gone after su2_finalize: proposal selection is a state error
     lib.su2_finalize()
-    assert lib.su2_set_proposal(1) == su2.SU2_ESTATE
+    assert lib.su2_set_proposal(1, None, 0) == su2.SU2_ESTATE
     assert lib.su2_set_creutz(ctypes.c_double(1.0)) == su2.SU2_ESTATE

@@ -232,11 +232,11 @@ def test_imh_pass_beta_zero_takes_the_haar_branch(lib):
 
 
 def test_imh_pass_alpha_above_table_falls_back_to_heat_bath(lib):
-    """beta = 10 on near-identity links: every alpha is above 40, so every
+    """beta = 12 on near-identity links: every alpha is above 40, so every
     update takes the capped Kennedy-Pendleton fallback (no proposals), link
     for link as the oracle's."""
     dims = (12, 12, 12, 12)
-    codes, alphas, flips = _imh_case(lib, dims, su2_inputs.near_identity_links(dims, 23, 0.2), 10.0, 31,
+    codes, alphas, flips = _imh_case(lib, dims, su2_inputs.near_identity_links(dims, 23, 0.2), 12.0, 31,
                                      su2_inputs.mlp_init(5))
     print(f"IMH fallback: alpha in [{alphas.min():.1f}, {alphas.max():.1f}], {flips} flips")
     assert alphas.min() > 40.0 and np.all(codes <= 8)

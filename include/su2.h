@@ -139,6 +139,22 @@ int su2_polyakov(double *out);
  * over t (FP32 products, FP64 sums in a fixed order).  Synchronises. */
 int su2_polyakov_correlator(int32_t rmax, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * correlator as su2_polyakov_correlator, computed by the same kernels in the
+ * same order (bit-identical results), but enqueued on the library's stream
+ * without waiting and without allocating or freeing anything.  dev_out is
+ * caller-owned DEVICE memory of rmax + 1 doubles, 8-byte aligned; it holds
+ * C(0..rmax) once the stream reaches this work.  The field and partial sums
+ * live in a fixed scratch array of 2^19 doubles (4 MiB) per GPU, held until
+ * the process ends: the call needs L0 L1 L2 + ceil(L0 L1 L2 / 256) (rmax + 1)
+ * doubles of it (e.g. a 64^3 spatial volume with rmax = 32) and returns
+ * SU2_EINVAL beyond that, as for a bad rmax or dev_out.  Every scratch value
+ * it reads it has written first in the same call, but all calls on one GPU
+ * share the array: calls that can overlap in time (other streams, other
+ * threads) race and must be serialised by the caller. */
+int su2_polyakov_correlator_noalloc(int32_t rmax, double *dev_out);
+
 /* Enqueue the measurements of the current configuration without waiting:
  * dev_out[0..2] = (P, P_s, P_t) as su2_plaquette_st, dev_out[3] = the
  * Polyakov loop.  dev_out is caller-owned DEVICE memory (4 doubles, 8-byte

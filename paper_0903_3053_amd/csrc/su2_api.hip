@@ -74,6 +74,28 @@ __global__ __launch_bounds__(kBlock) void k_polyakov_corr_reduce(const double *_
     if (threadIdx.x == 0) out[blockIdx.x] = s / (3.0 * (double)vs);
 }
 
+// The correlator's three launches: the Polyakov field (vs doubles) into
+// `field`, the per-workgroup products into `partial` (nb * (rmax + 1)
+// doubles, nb = ceil(vs / 256)), their fixed-order sums into out[0..rmax].
+// Every element of field and partial is written before it is read.
+hipError_t launch_polyakov_correlator(const float4 *links, const Geo &g, uint32_t rmax, double *field,
+                                      double *partial, double *out, hipStream_t st)
+{
+    const uint32_t vs = g.L[0] * g.L[1] * g.L[2];
+    const uint32_t nb = (vs + kBlock - 1) / kBlock, nr = rmax + 1;
+    hipLaunchKernelGGL(k_polyakov_field, dim3(nb), dim3(kBlock), 0, st, links, g, vs, field);
+    hipLaunchKernelGGL(k_polyakov_corr, dim3(nb, nr), dim3(kBlock), 0, st, field, g, vs, partial);
+    hipLaunchKernelGGL(k_polyakov_corr_reduce, dim3(nr), dim3(kBlock), 0, st, partial, nb, vs, out);
+    return hipGetLastError();
+}
+
+// Scratch of su2_polyakov_correlator_noalloc: the field and the partials of
+// one correlator, in device memory that exists as long as the process does
+// (each GPU the library runs on holds its own copy).  Host code uses it only
+// through the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoAllocDoubles = size_t(1) << 19;  // 4 MiB
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
 }  // namespace su2
 
 namespace {
@@ -114,6 +136,12 @@ struct Context {
 
 Context ctx;
 char last_error[512] = "no error";
+
+// Device address of the scratch array on each device, looked up once per
+// device (at the first lattice initialised there) with that device current.
+constexpr int kMaxDevices = 64;
+double *scratch_dev[kMaxDevices] = {};
+int ctx_device = -1;  // device current when the lattice was initialised
 
 int fail(int code, const char *fmt, ...)
 {
@@ -379,6 +407,16 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
         if ((uintptr_t)dev_links % 16)
             return fail(SU2_EINVAL, "device buffer must be 16-byte aligned");
     }
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(SU2_EDEVICE, "device %d: at most %d devices", dev, kMaxDevices);
+    if (!scratch_dev[dev]) {
+        void *p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(su2::scratch));
+        if (e != hipSuccess || !p)
+            return fail(SU2_EDEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        scratch_dev[dev] = static_cast<double *>(p);
+    }
     release_all();
     ctx.g = make_geo(dims, V);
     ctx.V = V;
@@ -421,6 +459,7 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
     ctx.sweep = 0;
     ctx.meas_fresh = false;
     ctx.ready = true;
+    ctx_device = dev;
     return SU2_OK;
 }
 
@@ -539,16 +578,34 @@ int su2_polyakov_correlator(int32_t rmax, double *out)
         if (d_part) hipFree(d_part);
         return fail(SU2_ENOMEM, "cannot allocate the Polyakov correlator buffers");
     }
-    hipLaunchKernelGGL(k_polyakov_field, dim3(nb), dim3(kBlock), 0, ctx.stream, ctx.links, ctx.g, vs, d_field);
-    hipLaunchKernelGGL(k_polyakov_corr, dim3(nb, nr), dim3(kBlock), 0, ctx.stream, d_field, ctx.g, vs, d_part);
-    hipLaunchKernelGGL(k_polyakov_corr_reduce, dim3(nr), dim3(kBlock), 0, ctx.stream, d_part, nb, vs, d_res);
-    hipError_t e = hipGetLastError();
+    hipError_t e = launch_polyakov_correlator(ctx.links, ctx.g, (uint32_t)rmax, d_field, d_part, d_res, ctx.stream);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d_res, nr * sizeof(double), hipMemcpyDeviceToHost, ctx.stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
     hipFree(d_field);
     hipFree(d_part);
     hipFree(d_res);
     if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_polyakov_correlator: %s", hipGetErrorString(e));
+    return SU2_OK;
+}
+
+int su2_polyakov_correlator_noalloc(int32_t rmax, double *dev_out)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (!dev_out || (uintptr_t)dev_out % 8) return fail(SU2_EINVAL, "dev_out must be 8-byte aligned device memory");
+    const uint32_t lmin = std::min({ ctx.g.L[0], ctx.g.L[1], ctx.g.L[2] });
+    if (rmax < 0 || (uint32_t)rmax > lmin / 2)
+        return fail(SU2_EINVAL, "rmax must be in 0 .. min(L0, L1, L2) / 2 = %u", lmin / 2);
+    const size_t vs = (size_t)ctx.g.L[0] * ctx.g.L[1] * ctx.g.L[2];
+    const size_t nb = (vs + kBlock - 1) / kBlock, nr = (size_t)rmax + 1;
+    const size_t need = vs + nb * nr;
+    if (need > kNoAllocDoubles)
+        return fail(SU2_EINVAL, "the correlator needs %zu doubles of scratch (L0 L1 L2 + ceil(L0 L1 L2 / 256) "
+                    "(rmax + 1)); the no-allocation scratch holds %zu", need, kNoAllocDoubles);
+    double *sp = ctx_device >= 0 ? scratch_dev[ctx_device] : nullptr;
+    if (!sp) return fail(SU2_ESTATE, "no scratch address for this device");
+    hipError_t e = launch_polyakov_correlator(ctx.links, ctx.g, (uint32_t)rmax, sp, sp + vs, dev_out, ctx.stream);
+    if (e != hipSuccess) return fail(SU2_EDEVICE, "su2_polyakov_correlator_noalloc: %s", hipGetErrorString(e));
     return SU2_OK;
 }
 

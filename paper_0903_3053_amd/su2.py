@@ -25,7 +25,7 @@ CREUTZ_SWITCH = 1.6847376
 EXPORTS = (
     "su2_init", "su2_init_ex", "su2_bind", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_overrelax",
     "su2_overrelax_pass", "su2_plaquette", "su2_plaquette_st",
-    "su2_polyakov", "su2_polyakov_correlator", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
+    "su2_polyakov", "su2_polyakov_correlator", "su2_polyakov_correlator_noalloc", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
     "su2_counters", "su2_set_stream", "su2_set_plan", "su2_tune", "su2_philox", "su2_synchronize", "su2_last_error",
     "su2_finalize", "su2_batch_init", "su2_batch_sweep", "su2_batch_set_mode", "su2_batch_tune",
     "su2_batch_set_spin_limit", "su2_batch_plaquette", "su2_batch_links", "su2_batch_counters",
@@ -73,6 +73,7 @@ def load():
         "su2_pass": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "su2_overrelax": ([ctypes.c_int32], ctypes.c_int),
         "su2_polyakov_correlator": ([ctypes.c_int32, dp], ctypes.c_int),
+        "su2_polyakov_correlator_noalloc": ([ctypes.c_int32, ctypes.c_void_p], ctypes.c_int),
         "su2_overrelax_pass": ([ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
         "su2_plaquette": ([], ctypes.c_double),
         "su2_plaquette_st": ([dp], ctypes.c_int),
@@ -192,6 +193,13 @@ def su2_polyakov_correlator(rmax):
     out = np.zeros(int(rmax) + 1)
     _check(load().su2_polyakov_correlator(int(rmax), _ptr(out, ctypes.c_double)))
     return out
+
+
+def su2_polyakov_correlator_noalloc(rmax, dev_out):
+    """Enqueue C(0..rmax) into device memory without allocating: dev_out is a
+    torch float64 CUDA tensor (its first rmax + 1 elements) or a raw address."""
+    ptr = dev_out.data_ptr() if hasattr(dev_out, "data_ptr") else int(dev_out)
+    _check(load().su2_polyakov_correlator_noalloc(int(rmax), ctypes.c_void_p(ptr)))
 
 
 def su2_overrelax(n):

@@ -77,6 +77,7 @@ def test_state_errors_before_init(lib):
     assert lib.su2_set_proposal(1, wp, 6433) == su2.SU2_ESTATE
     assert lib.su2_set_proposal(0, None, 0) == su2.SU2_ESTATE
     assert lib.su2_philox(1, None, 3, None) == su2.SU2_EINVAL
+    assert lib.su2_polyakov_correlator_noalloc(1, ctypes.c_void_p(4096)) == su2.SU2_ESTATE
 
 
 @pytest.mark.parametrize("dims,beta,start", [

@@ -208,6 +208,9 @@ static void haar_from_uniforms(const double u[4], double q[4])
 /*   variate over 2 alpha); accept iff u3^2 <= 1 - lambda^2; x0 = 1-2lambda^2.*/
 /* Returns the attempt index that accepted (0..7) or -1 when all 8 failed.   */
 /* *margin receives min |u3^2 - (1 - lambda^2)| over the attempts evaluated.  */
+/* With prec32 the test is taken in FP32 in the form it has multiplied by    */
+/* 2 alpha > 0: 2 alpha (1 - u3^2) + num >= 0, num = ln u0 + cos^2 ln u2      */
+/* (= -2 alpha lambda^2), with one rounding for the last multiply-add.       */
 /* ------------------------------------------------------------------------- */
 int oracle_kp_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t sweep,
                    int prec32, double *a0_out, double *amag_out, double *margin)
@@ -226,12 +229,13 @@ int oracle_kp_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t 
             float cf = (float)c;
             float lu2 = (float)log(u[2]);
             float af = (float)alpha;
-            float l2f = -(lu0 + cf * cf * lu2) / (2.0f * af);
+            float numf = lu0 + cf * cf * lu2;
             float u3f = (float)u[3];
-            float lf = u3f * u3f;
-            float rf = 1.0f - l2f;
-            lhs = (double)lf;
-            rhs = (double)rf;
+            float tf = 1.0f - u3f * u3f;
+            float df = fmaf(2.0f * af, tf, numf);
+            /* accept iff df >= 0; the margin in the units of lambda^2 */
+            lhs = 0.0;
+            rhs = (double)df / (2.0 * (double)af);
         } else {
             lhs = u[3] * u[3];
             rhs = 1.0 - lam2;

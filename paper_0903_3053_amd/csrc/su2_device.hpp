@@ -36,10 +36,11 @@ __device__ __forceinline__ uint4 philox(uint4 c, Key k)
     return c;
 }
 
-// top 24 bits of a word, as a uniform in (0, 1] -- exact in FP32
+// top 24 bits of a word, as a uniform in (0, 1] -- exact in FP32:
+// ((w >> 8) + 1) 2^-24 as one fused multiply-add of exact terms
 __device__ __forceinline__ float unit24(uint32_t w)
 {
-    return (float)((w >> 8) + 1u) * 0x1p-24f;
+    return __builtin_fmaf((float)(w >> 8), 0x1p-24f, 0x1p-24f);
 }
 
 enum : uint32_t { kPurposeUpdate = 0u, kPurposeHot = 1u, kPurposeImh = 2u };
@@ -77,14 +78,23 @@ __device__ __forceinline__ float qdot(float4 a, float4 b)  // (1/2) Re Tr(a b^da
     return __builtin_fmaf(a.x, b.x, __builtin_fmaf(a.y, b.y, __builtin_fmaf(a.z, b.z, a.w * b.w)));
 }
 
-// Reunitarisation, Eq. (7): divide by the norm, summed in FP64.
+// Reunitarisation, Eq. (7): divide by the norm, summed in FP64.  A product
+// of two unit quaternions held in FP32 has n2 = |q|^2 within ~1e-6 of 1, where
+// 1/sqrt(1 + d) = 1 - d/2 + 3d^2/8 - 5d^3/16 + O(d^4) reaches FP64 precision
+// for |d| < 2^-14 (the next term is below 2^-57): three FP64 fused
+// multiply-adds instead of a square root and a division.  Larger d (never
+// produced by the update) takes the square root and the division.
 __device__ __forceinline__ float4 unitize(float4 q)
 {
     const double x = q.x, y = q.y, z = q.z, w = q.w;
     const double n2 = __builtin_fma(x, x, __builtin_fma(y, y, __builtin_fma(z, z, w * w)));
-    const double inv = 1.0 / sqrt(n2);
-    return make_float4((float)(q.x * inv), (float)(q.y * inv), (float)(q.z * inv),
-                       (float)(q.w * inv));
+    const double d = n2 - 1.0;
+    double inv;
+    if (__builtin_fabs(d) < 0x1p-14)
+        inv = __builtin_fma(d, __builtin_fma(d, __builtin_fma(d, -0.3125, 0.375), -0.5), 1.0);
+    else
+        inv = 1.0 / sqrt(n2);
+    return make_float4((float)(x * inv), (float)(y * inv), (float)(z * inv), (float)(w * inv));
 }
 
 // Haar-uniform unit quaternion from three uniforms (Shoemake 1992).

@@ -2,11 +2,14 @@
 
 Workload (default): 64^4 periodic lattice (1.07 GB of FP32 links), beta = 2.4,
 hot start from Philox seed 1, plain Kennedy-Pendleton heat-bath -- the lattice
-on which the HBM-roofline fraction is quoted.  One step = one full sweep (eight
-(parity, mu) passes, Sec. 2.4) followed by the plaquette and Polyakov
-measurements into a device-resident history, i.e. every row of the hot path
-after initialisation.  Inputs (the initialised lattice) are resident in HBM
-before the timed region starts.
+on which the HBM-roofline fraction is quoted.  The chain is first brought to
+equilibrium (--therm sweeps, untimed).  One step = one measured configuration
+of the paper's statistics run (Sec. 2.4: configurations 5 sweeps apart): five
+full sweeps (eight (parity, mu) passes each), the last of which also sums the
+plaquette in its even passes, then the plaquette reduction and the Polyakov
+loop into a device-resident history -- every row of the hot path after
+initialisation.  Inputs (the initialised lattice) are resident in HBM before
+the timed region starts.
 
 Prints one JSON line: throughput in link updates/s, the roofline of the
 dominant kernel (k_pass, measured with HIP events on the library's stream
@@ -38,6 +41,7 @@ WORKLOADS = {
              plan=None),
 }
 FUSED_PAIRS = 300  # the launch plan that runs each parity as two fused-pair launches
+SWEEPS_PER_STEP = 5  # Sec. 2.4: measured configurations are 5 sweeps apart
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0903_3053_amd", "csrc", f)
                   for f in ("su2_kernels.hip", "su2_device.hpp", "su2_pass.hpp")]
@@ -66,6 +70,47 @@ def measured_traffic(workload, plan):
     return rec.get("bytes_per_launch")
 
 
+def cpu_model():
+    """The host CPU's model name and logical core count (this process's affinity)."""
+    name = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, len(os.sched_getaffinity(0))
+
+
+def replica_check(replicas, gpu_hist, sweeps=300, cut=100):
+    """The batched-replica workload's per-replica plaquette against the oracle:
+    each listed replica (same extents, beta, seed, hot start) run by the oracle
+    for `sweeps` sweeps, <P> over the sweeps after `cut`, against the GPU's
+    <P> over its recorded equilibrium history of the same replica; both errors
+    by the Gamma method."""
+    import numpy as np
+    import oracle
+    from paper_0903_3053_amd.stats import gamma_method
+    rows = []
+    t0 = time.perf_counter()
+    for r, h in zip(replicas, gpu_hist):
+        ch = oracle.Chain(r["dims"], r["beta"], r["seed"], oracle.HOT)
+        ph = []
+        for _ in range(sweeps):
+            ch.sweep(1)
+            ph.append(ch.plaquette()[0])
+        mo, eo, to, _, _ = gamma_method(np.asarray(ph[cut:]))
+        mg, eg, tg, _, _ = gamma_method(np.asarray(h))
+        rows.append({"replica": r["index"], "L": r["dims"][0], "beta": r["beta"],
+                     "gpu": {"plaquette": mg, "err": eg, "sweeps": len(h)},
+                     "oracle": {"plaquette": mo, "err": eo, "sweeps": sweeps - cut},
+                     "z": (mg - mo) / float(np.hypot(eg, eo))})
+    return {"replicas": rows, "max_abs_z": max(abs(x["z"]) for x in rows) if rows else None,
+            "oracle_seconds": time.perf_counter() - t0}
+
+
 def cpu_baseline(w, sweeps=8):
     """The oracle (plain C, FP64, OpenMP over sites) on a bounded sample of the
     same workload: the first `sweeps` sweeps of the same lattice from the same
@@ -89,8 +134,9 @@ def cpu_baseline(w, sweeps=8):
     gomp.omp_set_num_threads(cores)
     n1 = U.shape[0] // 2
     del U
+    model, host_cores = cpu_model()
     return {"value": n / dt, "unit": "link updates/s", "cores": cores,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "host_logical_cores": host_cores,
             "sample": f"the first {sweeps} sweeps ({n} link updates) of the same {w['name']} "
                       f"lattice from the same hot start, {dt:.2f} s wall",
             "single_thread": {"value": n1 / dt1, "unit": "link updates/s", "cores": 1,
@@ -130,16 +176,29 @@ def batched_replicas(su2, sweeps=500, compare_sweeps=50):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     P = su2.su2_batch_plaquette()
+    # per-replica plaquette histories at equilibrium (after the timed sweeps),
+    # for the comparison with the oracle's chains of the same replicas
+    check = [dict(t, index=r) for r, t in enumerate(table) if t["dims"][0] == 8][:CHECK_REPLICAS]
+    hist = [[] for _ in check]
+    for _ in range(CHECK_SWEEPS):
+        su2.su2_batch_sweep(1)
+        Pr = su2.su2_batch_plaquette()
+        for j, c in enumerate(check):
+            hist[j].append(float(Pr[c["index"], 0]))
     su2.su2_batch_finalize()
     upd = 4 * V * sweeps
     return {"workload": "64 replicas, L uniform on {8,12,16,20,24}, beta uniform on [1.8,2.8], hot, "
                         f"{sweeps} sweeps", "sites": V, "value": upd / dt, "unit": "link updates/s",
             "seconds": dt, "algorithmic_GBps": upd * BYTES_PER_UPDATE / dt / 1e9,
+            "algorithmic_frac": upd * BYTES_PER_UPDATE / dt / 1e9 / HBM_PEAK_GBS,
+            "_check": (check, hist),
             "mode": {"persistent": bool(chosen[0]), "tiles_per_item": chosen[1], "lds_bytes": chosen[2]},
             "updates_per_s_by_mode": modes,
             "plaquette_range": [float(P[:, 0].min()), float(P[:, 0].max())]}
 
 
+CHECK_REPLICAS = 4   # replicas whose plaquette the cpu_baseline leg compares with the oracle
+CHECK_SWEEPS = 200   # recorded sweeps of each
 TABLE_ROWS = 31
 
 
@@ -219,6 +278,45 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
             # updates/s per integrated autocorrelation time of <P>: independent samples/s
             "effective_speed_ratio": (lp["link_updates_per_s"] / lp["tau_int_sweeps"])
                                      / (kp["link_updates_per_s"] / kp["tau_int_sweeps"])}
+
+
+def couplings_32(su2, therm=100, sweeps=200):
+    """The 32^4 workload (hot start, Philox seed 1, plain heat-bath) at beta in
+    {2.2, 2.3, 2.4, 2.5}, each with the tuned launch plan: `sweeps` sweeps
+    after `therm`, the plaquette reduced in FP64 after every sweep into a
+    device history (su2_sweep_measure), timed on the library's stream.  The
+    lattice (64 MiB) fits the 256 MB Infinity Cache, so the bytes fraction is
+    of the algorithmic traffic, not a measure of HBM."""
+    import numpy as np
+    import torch
+    from paper_0903_3053_amd.stats import gamma_method
+    w = su2_inputs_workload("su2_32x32x32x32_hot")
+    dims = w["dims"]
+    V = int(np.prod(dims))
+    rows = []
+    for beta in w["betas"]:
+        su2.su2_init(dims, beta, w["seed"], w["start"])
+        plan = su2.su2_tune(2)
+        su2.su2_sweep(therm)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h = su2.su2_sweep_measure(sweeps, 1)
+        dt = time.perf_counter() - t0
+        rate = 4 * V * sweeps / dt
+        m, e, tau, _, _ = gamma_method(h[:, 0])
+        rows.append({"beta": beta, "link_updates_per_s": rate,
+                     "algorithmic_GBps": rate * BYTES_PER_UPDATE / 1e9,
+                     "algorithmic_frac": rate * BYTES_PER_UPDATE / 1e9 / HBM_PEAK_GBS,
+                     "plaquette": m, "plaquette_err": e, "tau_int_sweeps": tau,
+                     "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}})
+    su2.su2_finalize()
+    return {"workload": f"32^4 hot seed {w['seed']}, {therm} + {sweeps} sweeps, plaquette every sweep",
+            "points": rows}
+
+
+def su2_inputs_workload(name):
+    import su2_inputs
+    return su2_inputs.WORKLOADS[name]
 
 
 SCAN_BETAS = (0.5, 1.0, 1.5, 2.0, 2.3, 2.8)
@@ -472,6 +570,8 @@ def main():
                     help="pick the pass-kernel launch plan with su2_tune instead of the workload's")
     ap.add_argument("--plan", type=int, nargs=2, metavar=("ORDER", "LDS"), default=None,
                     help="use this pass-kernel launch plan")
+    ap.add_argument("--therm", type=int, default=300,
+                    help="untimed sweeps after the hot start, before the warm-up steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (torch), so that a counter "
                          "profile of this command also holds the copy of known size")
@@ -509,11 +609,15 @@ def main():
     else:
         plan = su2.su2_tune(2)
 
-    # warm-up: sweeps and measurements, graphs built and replayed
+    # thermalisation, then warm-up steps: sweeps and measurements, graphs built
+    # and replayed
+    su2.su2_sweep(args.therm)
     for i in range(args.warmup):
+        su2.su2_sweep(SWEEPS_PER_STEP - 1)
         su2.su2_sweep_measured(1)
         su2.su2_measure_device(hist[i % args.steps])
     torch.cuda.synchronize()
+    c_start = su2.su2_counters()
 
     ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for _ in range(args.steps)]
@@ -524,6 +628,7 @@ def main():
     start_ev.record(stream)
     for i in range(args.steps):
         ev[i][0].record(stream)
+        su2.su2_sweep(SWEEPS_PER_STEP - 1)
         su2.su2_sweep_measured(1)  # eight passes; the even ones also sum the plaquette
         ev[i][1].record(stream)
         su2.su2_measure_device(hist[i])  # reduce those partials + Polyakov loop
@@ -533,7 +638,8 @@ def main():
     total_ms = start_ev.elapsed_time(end_ev)
     sweep_ms = sum(a.elapsed_time(b) for a, b in ev)
     ms_per_step = max(total_ms, wall * 1e3) / args.steps
-    updates = 4 * V * args.steps
+    c_end = su2.su2_counters()
+    updates = 4 * V * SWEEPS_PER_STEP * args.steps
     value = updates / (ms_per_step * args.steps / 1e3)
     h = hist.cpu().numpy()
     P, poly = h[-1, :3], h[-1, 3]
@@ -542,10 +648,15 @@ def main():
     # x 128 B; or, with the fused-pair plan, k_pair, 4 launches of two passes each
     fused = plan[0] == FUSED_PAIRS
     launches = 4 if fused else 8
-    pass_ms = sweep_ms / (launches * args.steps)
+    pass_ms = sweep_ms / (launches * SWEEPS_PER_STEP * args.steps)
     bytes_per_launch = (8 // launches) * (V // 2) * BYTES_PER_UPDATE
     achieved = bytes_per_launch / (pass_ms * 1e-3) / 1e9
     traffic = None if fused else measured_traffic(w["name"], plan)
+    # the whole step against the same roofline: its algorithmic bytes (the
+    # sweeps' 128 B per update plus the Polyakov loop's 16 B per site; the
+    # plaquette is summed from staples the sweep holds) over its wall time
+    step_bytes = updates * BYTES_PER_UPDATE / args.steps + 16 * V
+    step_gbs = step_bytes / (ms_per_step * 1e-3) / 1e9
 
     rec = {
         "metric": METRIC, "value": value, "unit": "link updates/s", "n_gpus": 1,
@@ -554,22 +665,38 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "dims": list(dims), "beta": w["beta"], "seed": w["seed"],
                    "start": "hot", "proposal": "kennedy-pendleton",
-                   "step": ("1 sweep (4 fused-pair launches, plaquette summed in the even ones)" if fused else
-                            "1 sweep (8 passes, plaquette summed in the even passes)")
-                           + " + Polyakov loop, on device",
+                   "step": f"one measured configuration (Sec. 2.4: 5 sweeps apart): {SWEEPS_PER_STEP} sweeps "
+                           + ("(4 fused-pair launches each" if fused else "(8 passes each")
+                           + ", the last sweep's even passes also summing the plaquette) + plaquette "
+                             "reduction + Polyakov loop, on device, at equilibrium",
+                   "thermalisation_sweeps": args.therm,
                    "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": ("stored rocprofv3 FETCH_SIZE + WRITE_SIZE runs (copy-calibrated) "
+                                        "of this kernel source and plan, profiles/k_pass_traffic.json; "
+                                        "not measured in this run") if traffic is not None else
+                                       "none stored for this kernel source and plan",
                      "kernel": "k_pair" if fused else "k_pass", "avg_launch_ms": pass_ms,
-                     "algorithmic_bytes_per_launch": bytes_per_launch},
+                     "algorithmic_bytes_per_launch": bytes_per_launch,
+                     "timing": "HIP events on the library's stream around each step's sweeps "
+                               f"({launches * SWEEPS_PER_STEP} launches + {SWEEPS_PER_STEP} sweep-index ticks)"},
+        "roofline_step": {"achieved": step_gbs, "frac": step_gbs / HBM_PEAK_GBS, "unit": "GB/s",
+                          "algorithmic_bytes_per_step": step_bytes,
+                          "updates_frac": value * BYTES_PER_UPDATE / 1e9 / HBM_PEAK_GBS,
+                          "note": "whole step on its wall clock: sweeps + reductions + Polyakov loop; "
+                                  "updates_frac counts the sweeps' 128 B per update only"},
         "observables": {"plaquette": float(P[0]), "plaquette_spatial": float(P[1]),
                         "plaquette_temporal": float(P[2]), "polyakov": float(poly)},
     }
-    att, fail = su2.su2_counters()[:2]
-    rec["observables"]["kp_attempts_per_update"] = att / max(1, 4 * V * (args.steps + args.warmup))
+    rec["observables"]["kp_attempts_per_update"] = (c_end[0] - c_start[0]) / updates
+    rec["observables"]["kp_cap_failures_per_update"] = (c_end[1] - c_start[1]) / updates
     su2.su2_finalize()
+    check = None
     if not args.no_extras:
         rec["batched_replicas"] = batched_replicas(su2)
+        check = rec["batched_replicas"].pop("_check")
+        rec["couplings_32x32x32x32"] = couplings_32(su2)
         rec["learned_proposal"] = learned_proposal(su2)
         rec["overrelaxation"] = overrelaxation(su2)
         rec["strong_coupling"] = strong_coupling(su2)
@@ -577,6 +704,8 @@ def main():
         rec["paper_table1"] = paper_table1(su2)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
+        if check is not None:
+            rec["cpu_baseline"]["batched_replicas_vs_oracle"] = replica_check(*check)
     su2.su2_finalize()
     print(json.dumps(rec))
 

@@ -155,8 +155,9 @@ __device__ __forceinline__ void carry_of(const TileLoad &ld, PairCarry &cr)
 
 // The U_MU update at position pos (lanes with !valid join the wave-wide steps);
 // returns the new link and adds the plaquette terms it measures to acc_s.
-// before_update(), called by every lane once the update's loads are issued,
-// may stage the knot table and wait for it (the loads stay in flight).
+// before_update(), called by every lane once the staples are formed from the
+// update's loads (so the loaded links no longer hold registers), may wait at
+// a barrier for the knot table, whose copy the caller issued first.
 template <uint32_t MU, bool OFF32, bool MEAS, bool IMH, bool CARRY, bool CREUTZ, typename Hook>
 __device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, bool valid, double &acc_s,
                                                Hook before_update, PairCarry &carry)
@@ -166,8 +167,8 @@ __device__ __forceinline__ float4 pair_update1(const PairCtx &c, uint32_t pos, b
     const uint32_t h = pair_site<MU>(c.g, c.pg, c.j, c.p, valid ? pos : 0u, x);
     const TileLoad ld = load_site<MU, OFF32, IMH>(c.L, c.g, c.p, h, x);
     if constexpr (CARRY) carry_of<MU, NU>(ld, carry);
-    before_update();
     const TileStaples in = staples_of(ld);
+    before_update();
     double m = 0.0;
     const float4 un = update_link<MU, OFF32, MEAS, IMH, true, CREUTZ>(c.L, c.g, c.key, c.beta, c.p, c.s, h, valid,
                                                               c.slot, in, c.counters, c.imh, m);
@@ -315,14 +316,13 @@ __global__ __launch_bounds__(kPairLanes) void k_pair_small(
     double acc_s = 0.0, acc_t = 0.0;
     const uint32_t pos = threadIdx.x;
     const bool valid = pos < pg.n_t;
-    // the knot table's copy goes out behind the first pass's loads; the links
-    // both updates of a site read stay in registers
+    // the knot table's copy goes out ahead of the first pass's loads and is
+    // waited for once their staples are formed; the links both updates of a
+    // site read stay in registers
+    if constexpr (IMH) stage_table_any(imh);
     PairCarry carry;
     const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, true, CREUTZ>(c, pos, valid, acc_s, [&] {
-        if constexpr (IMH) {
-            stage_table_any(imh);
-            __syncthreads();
-        }
+        if constexpr (IMH) __syncthreads();
     }, carry);
     if (valid) buf[pos] = un;
     __syncthreads();
@@ -356,13 +356,14 @@ __global__ __launch_bounds__(kBlock) void k_pair(
         // the MU pass on positions [b * kBlock, (b + 1) * kBlock)
         if (b < pg.nblk) {
             const uint32_t pos = b * kBlock + threadIdx.x;
-            // block 0: the knot table's copy goes out behind its loads
+            // block 0: the knot table's copy goes out ahead of its loads and is
+            // waited for once their staples are formed
+            if constexpr (IMH) {
+                if (b == 0u) stage_table(imh);
+            }
             const float4 un = pair_update1<MU, OFF32, MEAS1, IMH, false, CREUTZ>(c, pos, pos < pg.n_t, acc_s, [&] {
                 if constexpr (IMH) {
-                    if (b == 0u) {
-                        stage_table(imh);
-                        __syncthreads();
-                    }
+                    if (b == 0u) __syncthreads();
                 }
             }, unused);
             buf[(b & 1u) * kBlock + threadIdx.x] = un;

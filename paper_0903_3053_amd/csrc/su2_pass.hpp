@@ -244,26 +244,18 @@ __device__ __forceinline__ bool imh_decide(Ptr r0, float f, float u0, float u1, 
 {
 #pragma clang fp contract(off)
     auto knot = [&](uint32_t j) { return r0[j] + f * (r0[33u + j] - r0[j]); };
-    // segment [y_lo, y_lo+1) of the current value: lo counts the knots
-    // y_1..y_31 at or below xc (for non-decreasing knots, the largest lo with
-    // y_lo <= xc).  Two rounds of independent reads: knots 8, 16 and 24 pick
-    // the stretch of eight segments, then its seven inner knots are read
-    // together with the proposal's two.
-    const float q1 = knot(8u), q2 = knot(16u), q3 = knot(24u);
+    // the proposal's segment and its two knots
     const uint32_t jp = min((uint32_t)(32.0f * u0), 31u);
     const float ya = knot(jp), yb = knot(jp + 1u);
-    const uint32_t b = 8u * ((uint32_t)(xc >= q1) + (uint32_t)(xc >= q2) + (uint32_t)(xc >= q3));
-    float ylo = b == 0u ? -1.0f : b == 8u ? q1 : b == 16u ? q2 : q3;
-    float yhi = b == 0u ? q1 : b == 8u ? q2 : b == 16u ? q3 : 1.0f;
-    float v[7];
+    // segment [y_lo, y_lo+1) of the current value: for non-decreasing knots
+    // the largest lo in 0..31 with y_lo <= xc (y_0 = -1), by a five-step
+    // binary search -- few registers live, which keeps more waves resident
+    uint32_t lo = 0u;
 #pragma unroll
-    for (uint32_t j = 0; j < 7u; ++j) v[j] = knot(b + 1u + j);
-#pragma unroll
-    for (uint32_t j = 0; j < 7u; ++j)
-        if (xc >= v[j]) ylo = v[j];
-#pragma unroll
-    for (int j = 6; j >= 0; --j)
-        if (xc < v[j]) yhi = v[j];
+    for (uint32_t step = 16u; step >= 1u; step >>= 1)
+        if (xc >= knot(lo + step)) lo += step;
+    const float ylo = lo == 0u ? -1.0f : knot(lo);
+    const float yhi = lo == 31u ? 1.0f : knot(lo + 1u);
     const float wc = yhi - ylo;
     xp = ya + (32.0f * u0 - (float)jp) * (yb - ya);
     num = 1.0f - xp * xp;

@@ -68,17 +68,6 @@ __device__ __forceinline__ uint32_t xcc_id()
     return __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 20) & 15u;
 }
 
-// replica r with prefix[r] <= i < prefix[r + 1] (wave-uniform binary search)
-__device__ __forceinline__ uint32_t find_rep(const BatchDev &b, uint32_t i)
-{
-    uint32_t lo = 0, hi = b.n;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (b.prefix[mid] <= i) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 // Run item `it` (tiles it*k .. it*k+k-1) of pass (p, mu) of replica rep.
 __device__ __forceinline__ void run_item(const BatchDev &b, const Rep &rep, uint32_t p,
                                          uint32_t mu, uint32_t s, uint32_t it, uint32_t k)
@@ -97,16 +86,37 @@ __device__ __forceinline__ void run_item(const BatchDev &b, const Rep &rep, uint
     }
 }
 
-// One (parity, mu) pass of every replica; workgroup w runs work item w.
-__global__ __launch_bounds__(kBlock) void k_batch_pass(BatchDev b, uint32_t p, uint32_t mu,
+// One (parity, MU) pass of every replica.  The work items (k tiles each) are
+// laid out replica after replica; workgroup w runs item (w mod 8) chunk +
+// floor(w / 8), or for odd MU the chunk walked backwards.  The hardware hands
+// consecutive workgroups to the eight XCDs in turn, so each XCD works through
+// one contiguous eighth of the items: its replicas (all but the few cut at a
+// chunk boundary) whole, the neighbouring tiles of a tile through its own L2;
+// and every second pass starts on the tiles the previous one ended with,
+// whose links are still in the caches.  item_rep[i] is the replica of item i.
+template <uint32_t MU>
+__global__ __launch_bounds__(kBlock) void k_batch_pass(BatchDev b, uint32_t p,
                                                        const uint32_t *__restrict__ sweep_ptr,
-                                                       uint32_t k)
+                                                       uint32_t k, uint32_t chunk, uint32_t total,
+                                                       const uint32_t *__restrict__ item_rep)
 {
     extern __shared__ float reserve[];  // LDS reservation only (caps resident workgroups)
     (void)reserve;
-    const uint32_t r = find_rep(b, blockIdx.x);
-    const Rep rep = b.reps[r];
-    run_item(b, rep, p, mu, *sweep_ptr, blockIdx.x - b.prefix[r], k);
+    const uint32_t w = blockIdx.x;
+    const uint32_t pos = (MU & 1u) ? chunk - 1u - (w >> 3) : (w >> 3);
+    const uint32_t item = (w & 7u) * chunk + pos;
+    if (item >= total) return;  // the grid is 8 chunk workgroups
+    const uint32_t r = item_rep[item];
+    const Rep &rep = b.reps[r];
+    float4 *L = b.links + rep.link_off;
+    unsigned long long *ctr = b.counters + rep.ctr_off;
+    const uint32_t s = *sweep_ptr;
+    const uint32_t t0 = (item - b.prefix[r]) * k;
+    for (uint32_t j = 0; j < k; ++j) {
+        const uint32_t tile = t0 + j;
+        if (tile >= rep.tiles) break;  // uniform: the whole workgroup leaves together
+        pass_tile<MU, true, false>(L, rep.g, rep.key, rep.beta, p, s, tile, ctr, nullptr, ImhTable{});
+    }
 }
 
 __global__ void k_batch_tick(uint32_t *sweep_ptr, uint32_t n)
@@ -329,6 +339,7 @@ struct Batch {
     std::vector<Rep> reps;          // host copy
     Rep *d_reps = nullptr;
     uint32_t *d_prefix = nullptr;       // item prefix (current k)
+    uint32_t *d_item_rep = nullptr;     // replica of each item (current k)
     uint32_t *d_site_prefix = nullptr;  // plaquette workgroup prefix
     std::vector<uint32_t> site_prefix;
     float4 *links = nullptr;
@@ -389,7 +400,7 @@ void batch_release()
 {
     if (B.ready) hipDeviceSynchronize();
     drop_graphs();
-    void *ptrs[] = { B.d_reps, B.d_prefix, B.d_site_prefix, B.links, B.counters, B.d_sweep,
+    void *ptrs[] = { B.d_reps, B.d_prefix, B.d_item_rep, B.d_site_prefix, B.links, B.counters, B.d_sweep,
                      B.d_done, B.d_next, B.d_err, B.d_xrep, B.d_xpre, B.d_partials, B.d_out };
     for (void *p : ptrs)
         if (p) hipFree(p);
@@ -468,6 +479,17 @@ int set_items(uint32_t k)
     BTRY(hipMemcpy(B.d_reps, B.reps.data(), B.reps.size() * sizeof(Rep), hipMemcpyHostToDevice));
     BTRY(hipMemcpy(B.d_prefix, prefix.data(), prefix.size() * sizeof(uint32_t),
                    hipMemcpyHostToDevice));
+    std::vector<uint32_t> item_rep(prefix.back());
+    for (size_t r = 0; r < B.reps.size(); ++r)
+        for (uint32_t i = prefix[r]; i < prefix[r + 1]; ++i) item_rep[i] = (uint32_t)r;
+    if (B.d_item_rep) hipFree(B.d_item_rep);
+    B.d_item_rep = nullptr;
+    if (hipMalloc(&B.d_item_rep, std::max<size_t>(item_rep.size(), 1) * sizeof(uint32_t)) != hipSuccess) {
+        hipGetLastError();
+        B.d_item_rep = nullptr;
+        return bfail(SU2_ENOMEM, "cannot allocate the item table");
+    }
+    BTRY(hipMemcpy(B.d_item_rep, item_rep.data(), item_rep.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
     B.per_pass = prefix.back();
     B.k = k;
     drop_graphs();
@@ -499,13 +521,17 @@ int build_grouped_graph()
     BatchDev d = dev();
     const uint32_t *sp = B.d_sweep;
     uint32_t k = B.k;
-    uint32_t pp[8], mm[8];
+    uint32_t chunk = (B.per_pass + 7u) / 8u, total = B.per_pass;
+    const uint32_t *ir = B.d_item_rep;
+    const void *pass_fn[4] = { reinterpret_cast<const void *>(&k_batch_pass<0>),
+                               reinterpret_cast<const void *>(&k_batch_pass<1>),
+                               reinterpret_cast<const void *>(&k_batch_pass<2>),
+                               reinterpret_cast<const void *>(&k_batch_pass<3>) };
+    uint32_t pp[8];
     for (int i = 0; i < 8 && rc == SU2_OK; ++i) {
-        pp[i] = i < 4 ? 1u : 0u;  // odd sites first (Sec. 2.4)
-        mm[i] = (uint32_t)(i & 3);
-        void *args[] = { &d, &pp[i], &mm[i], &sp, &k };
-        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_pass), dim3(B.per_pass),
-                      dim3(kBlock), B.lds, args);
+        pp[i] = i < 4 ? 1u : 0u;  // odd sites first (Sec. 2.4), mu = 0..3
+        void *args[] = { &d, &pp[i], &sp, &k, &chunk, &total, &ir };
+        rc = add_node(g, &prev, pass_fn[i & 3], dim3(8u * chunk), dim3(kBlock), B.lds, args);
     }
     uint32_t one = 1;
     uint32_t *spw = B.d_sweep;

@@ -557,6 +557,14 @@ def ising_2d():
     return out
 
 
+EXTRAS = ("batched_replicas", "couplings_32x32x32x32", "learned_proposal", "overrelaxation",
+          "strong_coupling", "ising_2d", "paper_table1")
+EXTRA_FUNCS = {"batched_replicas": batched_replicas, "couplings_32x32x32x32": couplings_32,
+               "learned_proposal": learned_proposal, "overrelaxation": overrelaxation,
+               "strong_coupling": strong_coupling, "ising_2d": lambda su2: ising_2d(),
+               "paper_table1": paper_table1}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -565,7 +573,10 @@ def main():
     ap.add_argument("--lattice", type=int, default=64, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the batched-replica and learned-proposal workloads")
+                    help="skip the extra workloads (batched replicas, 32^4 couplings, learned "
+                         "proposal, overrelaxation, strong coupling, Ising, Table-1 geometries)")
+    ap.add_argument("--extra", action="append", choices=EXTRAS, default=None,
+                    help="run only this extra workload (repeatable); default: all of them")
     ap.add_argument("--tune", action="store_true",
                     help="pick the pass-kernel launch plan with su2_tune instead of the workload's")
     ap.add_argument("--plan", type=int, nargs=2, metavar=("ORDER", "LDS"), default=None,
@@ -694,14 +705,10 @@ def main():
     su2.su2_finalize()
     check = None
     if not args.no_extras:
-        rec["batched_replicas"] = batched_replicas(su2)
-        check = rec["batched_replicas"].pop("_check")
-        rec["couplings_32x32x32x32"] = couplings_32(su2)
-        rec["learned_proposal"] = learned_proposal(su2)
-        rec["overrelaxation"] = overrelaxation(su2)
-        rec["strong_coupling"] = strong_coupling(su2)
-        rec["ising_2d"] = ising_2d()
-        rec["paper_table1"] = paper_table1(su2)
+        for name in args.extra or EXTRAS:
+            rec[name] = EXTRA_FUNCS[name](su2)
+        if "batched_replicas" in rec:
+            check = rec["batched_replicas"].pop("_check")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(w)
         if check is not None:

@@ -226,7 +226,8 @@ int su2_set_stream(void *hip_stream);
 int su2_set_plan(int32_t order_kind, int32_t lds_bytes);
 
 /* Launch-plan tuner (no passage of the paper; speed only).
- * Time each plan in {order 0, 4, 8, 16, 108, 208, 1000, 1008, 1108, 1208, 300}
+ * Time each plan in {order 0, 4, 8, 16, 108, 208, 1000, 1008, 1104, 1108, 1116,
+ * 1204, 1208, 300}
  * x {LDS 0, 16, 24, 32, 40 KiB} on a scratch copy of the links (reps measured
  * sweeps each, in three rounds over
  * all plans; the lattice, sweep index and all counters are untouched) and

@@ -100,7 +100,7 @@ static __device__ __align__(256) double scratch[kNoAllocDoubles];
 
 namespace {
 
-constexpr int kGraphSweeps = 16;  // sweeps per replay of the large graph
+constexpr int kGraphSweeps = (int)kSweepSlots;  // sweeps per replay of the large graph
 
 struct Context {
     bool ready = false;
@@ -110,7 +110,7 @@ struct Context {
     uint64_t V = 0;
     float4 *links = nullptr;
     bool owns_links = false;
-    uint32_t *d_sweep = nullptr;        // device-resident sweep index
+    uint32_t *d_sweep = nullptr;        // device-resident sweep index: kSweepSlots words, index + j
     uint64_t sweep = 0;                 // host mirror
     unsigned long long *d_counters = nullptr;  // per-wave (attempts, failures)
     uint32_t n_waves = 0;
@@ -230,8 +230,9 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
         const bool measure = measure_last && s == nsweeps - 1;
         // eight passes (Sec. 2.4: odd sites for every direction, then even
         // sites), or four fused pairs of them
+        // sweep s of the graph reads sweep-index word s (= index + s)
         std::vector<PassLaunch> pls = sweep_launches(ctx.links, ctx.g, ctx.key, (float)ctx.beta,
-                                                     ctx.d_sweep, ctx.d_counters,
+                                                     ctx.d_sweep + s, ctx.d_counters,
                                                      measure ? ctx.d_meas : nullptr, ctx.plan);
         for (PassLaunch &pl : pls) {
             pl.bind();
@@ -251,16 +252,19 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
             }
             prev = node;
         }
-        if (rc != SU2_OK) break;
-        uint32_t *sp = ctx.d_sweep;
-        void *targs[1] = { &sp };
+    }
+    // one tick after the graph's sweeps advances every sweep-index word by them
+    uint32_t *sp = ctx.d_sweep;
+    uint32_t nadv = (uint32_t)nsweeps;
+    if (rc == SU2_OK) {
+        void *targs[2] = { &sp, &nadv };
         hipKernelNodeParams kt{};
         kt.func = const_cast<void *>(tick_func());
         kt.gridDim = dim3(1);
-        kt.blockDim = dim3(1);
+        kt.blockDim = dim3(kWave);
         kt.kernelParams = targs;
         hipGraphNode_t node;
-        hipError_t e = hipGraphAddKernelNode(&node, graph, &prev, 1, &kt);
+        hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kt);
         if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
         prev = node;
     }
@@ -341,6 +345,17 @@ int set_plan(int32_t kind, uint32_t lds)
     ctx.meas_fresh = false;  // partials of a measured sweep are laid out per plan
     release_graphs();
     return SU2_OK;
+}
+
+// Device sweep-index words index + j, j < kSweepSlots (the copy is complete
+// when the call returns).
+hipError_t write_sweep_index(uint32_t index)
+{
+    uint32_t w[kSweepSlots];
+    for (uint32_t j = 0; j < kSweepSlots; ++j) w[j] = index + j;
+    hipError_t e = hipMemcpyAsync(ctx.d_sweep, w, sizeof w, hipMemcpyHostToDevice, ctx.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
+    return e;
 }
 
 int require_ready()
@@ -442,7 +457,7 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
         }
         ctx.owns_links = true;
     }
-    if (hipMalloc(&ctx.d_sweep, sizeof(uint32_t)) != hipSuccess ||
+    if (hipMalloc(&ctx.d_sweep, kSweepSlots * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&ctx.d_counters, (size_t)ctx.n_waves * 2 * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&ctx.d_partials, (size_t)nb * sizeof(double2)) != hipSuccess ||
         hipMalloc(&ctx.d_meas, n_meas * sizeof(double2)) != hipSuccess ||
@@ -452,7 +467,7 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
         release_all();
         return fail(SU2_ENOMEM, "cannot allocate work buffers");
     }
-    HIP_TRY(hipMemsetAsync(ctx.d_sweep, 0, sizeof(uint32_t), ctx.stream));
+    HIP_TRY(write_sweep_index(0));
     HIP_TRY(hipMemsetAsync(ctx.d_counters, 0, (size_t)ctx.n_waves * 2 * sizeof(unsigned long long),
                            ctx.stream));
     HIP_TRY(launch_init(ctx.links, ctx.g, ctx.key, start == SU2_HOT, ctx.stream));
@@ -692,8 +707,7 @@ int su2_set_links(const float *host_in, size_t n_floats, uint64_t sweep_index)
                                   ctx.stream);
     if (e == hipSuccess) e = launch_unpack(ctx.links, ctx.g, stage, ctx.stream);
     ctx.meas_fresh = false;
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx.d_sweep, &s32, sizeof s32, hipMemcpyHostToDevice, ctx.stream);
+    if (e == hipSuccess) e = write_sweep_index(s32);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
     hipStreamSynchronize(ctx.stream);
     hipFree(stage);
@@ -823,8 +837,9 @@ int su2_tune(int32_t reps, int32_t out[2])
     // measured sweeps (as su2_sweep_measured runs them) of a copy of the links,
     // in three rounds over all candidates; the median of its rounds ranks it,
     // so slow drifts of the clock or of the cache state do not pick the plan.
-    const int32_t kinds[] = { 0, 4, 8, 16, 108, 208, kAlternate, kAlternate + 8, kAlternate + 108,
-                              kAlternate + 208, kFusedPairs };
+    const int32_t kinds[] = { 0, 4, 8, 16, 108, 208, kAlternate, kAlternate + 8, kAlternate + 104,
+                              kAlternate + 108, kAlternate + 116, kAlternate + 204, kAlternate + 208,
+                              kFusedPairs };
     const uint32_t ldss[] = { 0u, 16384u, 24576u, 32768u, 40960u };
     constexpr int kRounds = 3;
     std::vector<int32_t> cand_kind;

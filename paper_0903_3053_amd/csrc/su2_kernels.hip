@@ -8,7 +8,7 @@
 //   k_pair       the passes of U_0 and U_1 (or U_2 and U_3) of one parity in
 //                one launch (su2_pair.hpp)
 //   k_or         one overrelaxation pass (U -> V U^dag V about the staple)
-//   k_tick       advances the device-resident sweep index (graph-friendly)
+//   k_tick       advances the device-resident sweep index words (graph-friendly)
 //   k_plaquette  per-workgroup FP64 partial sums of spatial / temporal
 //                plaquettes (Sec. 2.4, Eq. (3))
 //   k_polyakov   per-workgroup FP64 partial sums of the Polyakov loop
@@ -75,9 +75,12 @@ __global__ __launch_bounds__(kBlock) void k_or(float4 *__restrict__ L, Geo g, ui
     st4_stream<OFF32>(L + arr(g, MU, p), h, unitize(qmul(qmul(V, qdag(t.uold)), V)));
 }
 
-__global__ void k_tick(uint32_t *sweep_ptr)
+// The sweep index lives in kSweepSlots consecutive words, word j holding
+// index + j, so that sweep j of a graph of several sweeps reads word j and a
+// single tick per graph advances all of them by the graph's sweeps.
+__global__ void k_tick(uint32_t *sweep_ptr, uint32_t n)
 {
-    if (threadIdx.x == 0) *sweep_ptr += 1u;
+    if (threadIdx.x < kSweepSlots) sweep_ptr[threadIdx.x] += n;
 }
 
 // ---------------------------------------------------------------------------
@@ -501,9 +504,9 @@ PassLaunch or_launch(float4 *links, const Geo &g, uint32_t p, uint32_t mu, const
     return pl;
 }
 
-hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st)
+hipError_t launch_tick(uint32_t *sweep_ptr, uint32_t n, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_tick, dim3(1), dim3(1), 0, st, sweep_ptr);
+    hipLaunchKernelGGL(k_tick, dim3(1), dim3(kWave), 0, st, sweep_ptr, n);
     return hipGetLastError();
 }
 

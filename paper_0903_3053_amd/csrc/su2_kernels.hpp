@@ -99,7 +99,9 @@ uint32_t meas_partials(const Geo &g, const PassPlan &plan);
 PassLaunch or_launch(float4 *links, const Geo &g, uint32_t p, uint32_t mu, const PassPlan &plan);
 hipError_t launch(PassLaunch &pl, hipStream_t st);
 hipError_t launch_init(float4 *links, const Geo &g, Key key, int hot, hipStream_t st);
-hipError_t launch_tick(uint32_t *sweep_ptr, hipStream_t st);
+// The device sweep index: kSweepSlots words, word j = index + j (see k_tick).
+constexpr uint32_t kSweepSlots = 16;
+hipError_t launch_tick(uint32_t *sweep_ptr, uint32_t n, hipStream_t st);
 const void *tick_func();
 
 uint32_t plaquette_blocks(const Geo &g);

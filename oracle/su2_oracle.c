@@ -261,8 +261,9 @@ int oracle_kp_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t 
 /*   x0 = 1 + ln(y) / alpha has density proportional to exp(alpha x0) on       */
 /*   [-1, 1]; accept iff u1 <= sqrt(1 - x0^2), i.e. u1^2 <= 1 - x0^2.          */
 /* (log1p and expm1 evaluate ln y and 1 - exp(-2 alpha) without cancellation.) */
-/* prec32 takes the decision in FP32 on m = 1 - x0, with 1 - x0^2 = m (2 - m);  */
-/* x0 and |a| come from the FP64 m.                                            */
+/* prec32 takes the decision in FP32, on L = alpha m = -ln y, multiplied       */
+/* through by alpha^2: L (2 alpha - L) - (alpha u1)^2 >= 0 (last multiply-add  */
+/* rounded once); x0 and |a| come from the FP64 m.                            */
 /* Returns the accepting attempt (0..7) or -1; *margin as in oracle_kp_draw.   */
 /* ------------------------------------------------------------------------- */
 int oracle_creutz_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint32_t sweep,
@@ -281,12 +282,12 @@ int oracle_creutz_draw(double alpha, uint64_t seed, uint32_t site, int mu, uint3
             float af = (float)alpha;
             float df = (float)(-expm1(-2.0 * (double)af));
             float z = -(1.0f - (float)u[0]) * df;
-            float mf = -(float)log1p((double)z) / af;
-            float u1f = (float)u[1];
-            float lf = u1f * u1f;
-            float rf = mf * (2.0f - mf);
-            lhs = (double)lf;
-            rhs = (double)rf;
+            float lf = -(float)log1p((double)z);
+            float au = af * (float)u[1];
+            float tf = fmaf(lf, 2.0f * af - lf, -(au * au));
+            /* accept iff tf >= 0; the margin in the units of 1 - x0^2 */
+            lhs = 0.0;
+            rhs = (double)tf / ((double)af * (double)af);
         } else {
             double x0 = 1.0 - m;
             lhs = u[1] * u[1];

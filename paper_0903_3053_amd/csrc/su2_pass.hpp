@@ -143,21 +143,25 @@ __device__ __forceinline__ float kp_lambda2(float num, float two_alpha)
 // Creutz's draw (Phys. Rev. D 21 (1980) 2308), the better heat-bath at small
 // alpha: y uniform on [exp(-2 alpha), 1] makes x0 = 1 + ln(y) / alpha
 // distributed as exp(alpha x0) on [-1, 1], and the attempt is accepted with
-// probability sqrt(1 - x0^2).  Returns m = 1 - x0 = -ln(y) / alpha (so m / 2
-// plays the part of lambda^2) from y = 1 - (1 - u) (1 - exp(-2 alpha)),
-// written with expm1 and log1p so that m stays accurate as alpha -> 0.
-__device__ __forceinline__ float creutz_m(float u, float alpha)
+// probability sqrt(1 - x0^2).  With m = 1 - x0 = -ln(y) / alpha (so m / 2
+// plays the part of lambda^2) and y = 1 - (1 - u) (1 - exp(-2 alpha)), this
+// returns L = alpha m = -ln y, written with expm1 and log1p so that m stays
+// accurate as alpha -> 0; the test and m need only one division, for the
+// accepted attempt.
+__device__ __forceinline__ float creutz_l(float u, float alpha)
 {
 #pragma clang fp contract(off)
     const float d = -expm1f(-2.0f * alpha);
-    return -log1pf(-(1.0f - u) * d) / alpha;
+    return -log1pf(-(1.0f - u) * d);
 }
 
-// u1 <= sqrt(1 - x0^2) with 1 - x0^2 = m (2 - m)
-__device__ __forceinline__ bool creutz_accept(float u1, float m)
+// u1 <= sqrt(1 - x0^2) with 1 - x0^2 = m (2 - m) = L (2 alpha - L) / alpha^2,
+// taken multiplied by alpha^2: L (2 alpha - L) - (alpha u1)^2 >= 0
+__device__ __forceinline__ bool creutz_accept(float u1, float l, float alpha, float two_alpha)
 {
 #pragma clang fp contract(off)
-    return u1 * u1 <= m * (2.0f - m);
+    const float au = alpha * u1;
+    return __builtin_fmaf(l, two_alpha - l, -(au * au)) >= 0.0f;
 }
 
 // A double moved across lanes by a DPP control (both 32-bit halves).
@@ -391,10 +395,10 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
         if (!done) {
             const uint4 r = draw(key, lex, MU, kPurposeUpdate, s, t);
             if (creutz) {
-                const float m = creutz_m(unit24(r.x), alpha);
-                if (creutz_accept(unit24(r.y), m)) {
+                const float l = creutz_l(unit24(r.x), alpha);
+                if (creutz_accept(unit24(r.y), l, alpha, two_alpha)) {
                     done = true;
-                    lam2 = 0.5f * m;
+                    num_acc = l;
                 }
             } else {
                 const float num = kp_num(unit24(r.x), unit24(r.y), unit24(r.z));
@@ -405,7 +409,9 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
             }
         }
     }
-    if (!creutz) lam2 = kp_lambda2(num_acc, two_alpha);
+    // lambda^2 of the accepted attempt: -num / (2 alpha) (Kennedy-Pendleton) or
+    // m / 2 = L / (2 alpha) (Creutz)
+    lam2 = kp_lambda2(creutz ? -num_acc : num_acc, two_alpha);
     const bool failed = valid && !done;
     const unsigned long long failures = __popcll(__ballot(failed));
     float4 un = make_float4(0.f, 0.f, 0.f, 0.f);

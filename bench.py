@@ -202,13 +202,15 @@ CHECK_SWEEPS = 200   # recorded sweeps of each
 TABLE_ROWS = 31
 
 
-def learned_proposal(su2, sweeps=1000, train_steps=3000):
+def learned_proposal(su2, sweeps=100000, train_steps=30000):
     """The learned-proposal workload: the network trained on the device on the
     integrated CDFs of 4096 alphas, then 32^4 beta = 2.3 from the same hot start
-    for `sweeps` sweeps with the heat-bath and with the learned independence-
-    Metropolis step; plaquette measured every sweep, averages after a 20 %
+    for `sweeps` sweeps with the heat-bath, with the learned independence-
+    Metropolis step, and with the same step reading the integrated CDF's knots
+    instead of the network's (the ablation: what the network's approximation
+    costs); plaquette measured every sweep, averages after a 10 %
     thermalisation cut with Gamma-method errors and integrated autocorrelation
-    times; updates/s of the two from interleaved timing rounds."""
+    times; updates/s of the three from interleaved timing rounds."""
     import numpy as np
     import torch
     import su2_inputs
@@ -224,60 +226,82 @@ def learned_proposal(su2, sweeps=1000, train_steps=3000):
     su2.su2_mlp_tabulate(TABLE_ROWS)
     t_train = time.perf_counter() - t0
 
+    chains = (("kennedy_pendleton", 0, None), ("learned_imh", 1, su2.su2_mlp_tabulate),
+              ("exact_knots_imh", 1, su2.su2_cdf_tabulate))
+
+    def use(kind, table, plan=None):
+        if table is not None:
+            table(TABLE_ROWS)
+        if plan is not None:
+            su2.su2_set_plan(*plan)
+        su2.su2_set_proposal(kind)
+
     out = {}
     plans = {}
-    for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
+    for name, kind, table in chains:
         # each proposal runs with the launch plan tuned for it
         su2.su2_init(dims, beta, seed, 1)
-        su2.su2_set_proposal(kind)
+        use(kind, table)
         su2.su2_sweep(5)
-        plans[kind] = su2.su2_tune(2)
+        plans[name] = su2.su2_tune(2)
         su2.su2_init(dims, beta, seed, 1)
-        su2.su2_set_plan(*plans[kind])
-        su2.su2_set_proposal(kind)
+        use(kind, table, plans[name])
         h = su2.su2_sweep_measure(sweeps, 1)[:, 0]
-        m, e, tau, dtau, _ = gamma_method(h[sweeps // 5:])
+        m, e, tau, dtau, _ = gamma_method(h[sweeps // 10:])
         rec = {"plaquette": m, "plaquette_err": e, "tau_int_sweeps": tau, "tau_int_err": dtau,
-               "pass_plan": {"tile_order": plans[kind][0], "lds_bytes": plans[kind][1]}}
+               "sweeps_analysed": sweeps - sweeps // 10,
+               "pass_plan": {"tile_order": plans[name][0], "lds_bytes": plans[name][1]}}
         if kind:
             prop, acc = su2.su2_imh_counters()
             rec["acceptance"] = acc / max(prop, 1)
         out[name] = rec
-    # rates: TIMING_ROUNDS rounds alternating the two proposals on the same
-    # equilibrated chain (200 sweeps each, after 2 untimed sweeps that build the
-    # graphs of the switched plan), so clock or cache drifts hit both alike;
+    # rates: TIMING_ROUNDS rounds cycling through the three on the same
+    # equilibrated chain (200 sweeps each, after 2 untimed sweeps that build
+    # the graphs of the switched plan), so clock or cache drifts hit all alike;
     # the median of each and of the per-round ratios is reported
     su2.su2_init(dims, beta, seed, 1)
     su2.su2_sweep(200)
-    rates = {0: [], 1: []}
+    rates = {name: [] for name, _, _ in chains}
     for _ in range(TIMING_ROUNDS):
-        for kind in (0, 1):
-            su2.su2_set_plan(*plans[kind])
-            su2.su2_set_proposal(kind)
+        for name, kind, table in chains:
+            use(kind, table, plans[name])
             su2.su2_sweep(2)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             su2.su2_sweep(200)
             torch.cuda.synchronize()
-            rates[kind].append(4 * V * 200 / (time.perf_counter() - t0))
-    ratios = [b / a for a, b in zip(rates[0], rates[1])]
-    for name, kind in (("kennedy_pendleton", 0), ("learned_imh", 1)):
-        out[name]["link_updates_per_s"] = float(np.median(rates[kind]))
-        out[name]["link_updates_per_s_rounds"] = rates[kind]
-    kp, lp = out["kennedy_pendleton"], out["learned_imh"]
-    scan = beta_scan(su2, dims, seed, plans)
+            rates[name].append(4 * V * 200 / (time.perf_counter() - t0))
+    for name, _, _ in chains:
+        out[name]["link_updates_per_s"] = float(np.median(rates[name]))
+        out[name]["link_updates_per_s_rounds"] = rates[name]
+    kp = out["kennedy_pendleton"]
+    for name in ("learned_imh", "exact_knots_imh"):
+        r = out[name]
+        ratios = [b / a for a, b in zip(rates["kennedy_pendleton"], rates[name])]
+        r["speed_ratio"] = float(np.median(ratios))
+        r["speed_ratio_rounds"] = ratios
+        # updates/s per integrated autocorrelation time of <P>: independent
+        # samples/s, relative to the heat-bath; the error from the two tau_int
+        eff = r["speed_ratio"] * kp["tau_int_sweeps"] / r["tau_int_sweeps"]
+        r["effective_speed_ratio"] = eff
+        r["effective_speed_ratio_err"] = eff * float(np.hypot(kp["tau_int_err"] / kp["tau_int_sweeps"],
+                                                              r["tau_int_err"] / r["tau_int_sweeps"]))
+        r["z_plaquette_vs_heat_bath"] = (r["plaquette"] - kp["plaquette"]) / float(
+            np.hypot(kp["plaquette_err"], r["plaquette_err"]))
+    su2.su2_mlp_tabulate(TABLE_ROWS)
+    scan = beta_scan(su2, dims, seed, {0: plans["kennedy_pendleton"], 1: plans["learned_imh"]})
     su2.su2_finalize()
-    return {"workload": f"32^4 beta 2.3 hot seed 1, {sweeps} sweeps, heat-bath vs learned proposal",
+    lp = out["learned_imh"]
+    return {"workload": f"32^4 beta 2.3 hot seed 1, {sweeps} sweeps each: heat-bath, learned proposal, "
+                        f"and the same proposal on the integrated CDF's knots",
             "beta_scan": scan,
             "training": {"steps": train_steps, "alphas": 4096, "seconds": t_train, "table_rows": TABLE_ROWS,
                          "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
             **out,
-            "z_plaquette": (lp["plaquette"] - kp["plaquette"]) / float(np.hypot(kp["plaquette_err"], lp["plaquette_err"])),
-            "speed_ratio": float(np.median(ratios)),
-            "speed_ratio_rounds": ratios,
-            # updates/s per integrated autocorrelation time of <P>: independent samples/s
-            "effective_speed_ratio": (lp["link_updates_per_s"] / lp["tau_int_sweeps"])
-                                     / (kp["link_updates_per_s"] / kp["tau_int_sweeps"])}
+            "z_plaquette": lp["z_plaquette_vs_heat_bath"],
+            "speed_ratio": lp["speed_ratio"],
+            "effective_speed_ratio": lp["effective_speed_ratio"],
+            "effective_speed_ratio_err": lp["effective_speed_ratio_err"]}
 
 
 def couplings_32(su2, therm=100, sweeps=200):
@@ -706,7 +730,10 @@ def main():
     check = None
     if not args.no_extras:
         for name in args.extra or EXTRAS:
+            t_x = time.perf_counter()
+            print(f"extra workload {name} ...", file=sys.stderr, flush=True)
             rec[name] = EXTRA_FUNCS[name](su2)
+            print(f"extra workload {name} done in {time.perf_counter() - t_x:.1f} s", file=sys.stderr, flush=True)
         if "batched_replicas" in rec:
             check = rec["batched_replicas"].pop("_check")
     if not args.no_cpu_baseline:

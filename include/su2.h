@@ -241,7 +241,10 @@ int su2_tune(int32_t reps, int32_t out[2]);
  * rejection loop's cost on a SIMD machine, Sec. 2.4 and Sec. 3, which this
  * removes).  The heat-bath's x0 has density ~ sqrt(1 - x^2) exp(alpha x), alpha = beta |W|
  * (the local conditional of Eqs. (2), (3), (6)).  A small network maps alpha to
- * a 32-segment monotone piecewise-linear inverse CDF of x0; used as an
+ * the 33 knots of 32 equal-probability segments of x0; the proposal picks a
+ * segment with probability 1/32 and draws x0 inside it from the density ~
+ * exp(alpha x0) (the conditional's exponential factor, so that the accept
+ * step corrects only sqrt(1 - x0^2) and the knots' errors).  Used as an
  * independence-Metropolis proposal with the exact acceptance ratio it leaves
  * that conditional invariant, with the Kennedy-Pendleton draw as the fallback
  * outside the network's range.  Network: 1 -> 64 -> 64 -> 33 on alpha / 40,
@@ -291,6 +294,13 @@ int su2_mlp_tabulate(int32_t points);
 
 /* Copy the current knot table (n_floats = 33 * points). */
 int su2_mlp_table(float *host_out, size_t n_floats);
+
+/* Fill the same knot table with the integrated CDF knots instead of the
+ * network's: `points` alphas evenly spaced on [0, 40], knots from
+ * su2_cdf_knots' kernel (FP64) rounded to FP32.  The proposal without the
+ * network's approximation, to measure what the network costs; needs no
+ * parameters.  points in 2..65536, else SU2_EINVAL. */
+int su2_cdf_tabulate(int32_t points);
 
 const char *su2_mlp_last_error(void);
 

@@ -471,11 +471,15 @@ int oracle_update_sites(const int dims[4], double beta, uint64_t seed, uint32_t 
 
 /* ------------------------------------------------------------------------- */
 /* Learned-proposal variant: an independence-Metropolis step for x0.          */
-/* The proposal q(x0 | alpha) is a monotone piecewise-linear inverse CDF with */
-/* 32 equal-probability segments between knots y_0 = -1 < ... < y_32 = 1; the */
+/* The proposal q(x0 | alpha) puts probability 1/32 on each of 32 segments    */
+/* between knots y_0 = -1 < ... < y_32 = 1 and, inside segment j, density     */
+/* proportional to exp(alpha x0): with w_j = y_{j+1} - y_j and                */
+/* E_j = exp(alpha w_j) - 1, q(x) = alpha exp(alpha (x - y_j)) / (32 E_j),     */
+/* drawn as x = y_j + ln(1 + v E_j) / alpha for v uniform on [0, 1).  The     */
 /* knots at alpha come from `table` (G rows of 33 knots at alpha_g = g *      */
 /* alpha_max / (G - 1)) by linear interpolation in alpha.  One Philox call    */
-/* (purpose 2, slot 0): u0 -> proposal, u1 -> accept, (u2, u3) -> direction.  */
+/* (purpose 2, slot 0): u0 -> segment j = floor(32 u0) and v = 32 u0 - j,     */
+/* u1 -> accept, (u2, u3) -> direction.                                        */
 /* The target for x0 is pi(x) ~ sqrt(1 - x^2) exp(alpha x) (the same local     */
 /* conditional the heat-bath samples); the step accepts with probability      */
 /* min(1, [pi(x') / q(x')] / [pi(x) / q(x)]), x = dot(U_old, V), so it leaves */
@@ -520,23 +524,27 @@ static void update_one_imh(const int dims[4], double beta, uint64_t seed, uint32
     draw4(seed, (uint32_t)lex, mu, PURPOSE_IMH, sweep, 0u, u);
     int jp = (int)floor(32.0 * u[0]);
     if (jp > 31) jp = 31;
-    double xp = y[jp] + (32.0 * u[0] - (double)jp) * (y[jp + 1] - y[jp]);
+    double v = 32.0 * u[0] - (double)jp;
+    double Ep = expm1(alpha * (y[jp + 1] - y[jp]));
+    double xp = y[jp] + log1p(v * Ep) / alpha;
     double V[4] = { w[0] / k, w[1] / k, w[2] / k, w[3] / k };
     const double *uo = link(U, lex, mu);
     double xc = uo[0] * V[0] + uo[1] * V[1] + uo[2] * V[2] + uo[3] * V[3];
     if (xc > 1.0) xc = 1.0;
     if (xc < -1.0) xc = -1.0;
     int jc = segment_of(y, xc);
-    /* log of the acceptance ratio: pi ratio times the inverse q ratio (q is
-     * (1/32) / width on each segment) */
+    double Ec = expm1(alpha * (y[jc + 1] - y[jc]));
+    /* log of the acceptance ratio: pi(x) / q(x) = 32 sqrt(1 - x^2)        */
+    /* exp(alpha y_j) E_j / alpha on segment j, so                         */
+    /* r = sqrt((1 - x'^2) / (1 - x^2)) exp(alpha (y_jp - y_jc)) E_jp / E_jc */
     double lr_terms[3];
     double num = 1.0 - xp * xp, den = 1.0 - xc * xc;
     int accept_always = 0, reject_always = 0;
-    if (num <= 0.0) reject_always = 1;
+    if (num <= 0.0 || Ep == 0.0) reject_always = 1;
     else if (den <= 0.0) accept_always = 1;
     lr_terms[0] = (num > 0.0 && den > 0.0) ? 0.5 * log(num / den) : 0.0;
-    lr_terms[1] = alpha * (xp - xc);
-    lr_terms[2] = log((y[jp + 1] - y[jp]) / (y[jc + 1] - y[jc]));
+    lr_terms[1] = alpha * (y[jp] - y[jc]);
+    lr_terms[2] = (Ep > 0.0 && Ec > 0.0) ? log(Ep / Ec) : 0.0;
     int acc;
     double m;
     if (reject_always) { acc = 0; m = INFINITY; }

@@ -711,6 +711,47 @@ int su2_mlp_tabulate(int32_t points)
     return SU2_OK;
 }
 
+int su2_cdf_tabulate(int32_t points)
+{
+    if (points < 2 || points > (1 << 16)) return lfail(SU2_EINVAL, "points must be in 2..65536");
+    const uint32_t G = (uint32_t)points, n = G * 33u;
+    std::vector<double> a(G);
+    for (uint32_t g = 0; g < G; ++g) a[g] = (double)g * (double)kAlphaMax / (double)(G - 1);
+    double *d_a = nullptr, *d_k = nullptr;
+    if (hipMalloc(&d_a, G * sizeof(double)) != hipSuccess || hipMalloc(&d_k, n * sizeof(double)) != hipSuccess) {
+        hipGetLastError();
+        if (d_a) hipFree(d_a);
+        return lfail(SU2_ENOMEM, "cannot allocate");
+    }
+    if (LN.table && LN.G != G) {
+        hipFree(LN.table);
+        LN.table = nullptr;
+        LN.G = 0;
+    }
+    hipError_t e = hipSuccess;
+    if (!LN.table && hipMalloc(&LN.table, (size_t)n * sizeof(float)) != hipSuccess) {
+        hipGetLastError();
+        LN.table = nullptr;
+        e = hipErrorOutOfMemory;
+    }
+    if (e == hipSuccess) e = hipMemcpy(d_a, a.data(), G * sizeof(double), hipMemcpyHostToDevice);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_cdf, dim3(G), dim3(kBlock), 0, nullptr, d_a, d_k);
+        hipLaunchKernelGGL(k_f64_to_f32, dim3(nb(n)), dim3(256), 0, nullptr, d_k, n, LN.table);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    hipFree(d_a);
+    hipFree(d_k);
+    if (e != hipSuccess) {
+        LN.G = 0;
+        return lfail(e == hipErrorOutOfMemory ? SU2_ENOMEM : SU2_EDEVICE, "su2_cdf_tabulate: %s",
+                     hipGetErrorString(e));
+    }
+    LN.G = G;
+    return SU2_OK;
+}
+
 int su2_mlp_table(float *host_out, size_t n_floats)
 {
     if (!LN.table) return lfail(SU2_ESTATE, "no table: call su2_mlp_tabulate");

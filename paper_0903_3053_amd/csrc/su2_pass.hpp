@@ -234,14 +234,55 @@ __device__ __forceinline__ double block_sum(double a)
     return r;
 }
 
+// (e^z - 1) / z for z >= 0 to a few units in the last place: the Taylor
+// series to z^4 below 1/16 (the remainder, about z^5/720, is below 2^-29),
+// hardware exp2 above (where e^z - 1 >= e^z / 17 keeps the subtraction's
+// relative error near 2e-6 at worst).
+// z <= 80 in use, so e^z stays finite.
+__device__ __forceinline__ float expm1_over(float z)
+{
+#pragma clang fp contract(off)
+    if (z < 0.0625f)
+        return __builtin_fmaf(z, __builtin_fmaf(z, __builtin_fmaf(z, __builtin_fmaf(z, 0x1.111112p-7f, 0x1.555556p-5f),
+                                                                   0x1.555556p-3f), 0.5f), 1.0f);
+    return (__builtin_amdgcn_exp2f(z * 1.44269504f) - 1.0f) * __builtin_amdgcn_rcpf(z);
+}
+
+// ln(1 + t) / t for t >= 0: the series to t^6 below 1/16 (remainder below
+// t^7/8 < 2^-31), hardware log2 of the rounded 1 + t above (relative error
+// below 1e-6 there)
+__device__ __forceinline__ float log1p_over(float t)
+{
+#pragma clang fp contract(off)
+    if (t < 0.0625f) {
+        float q = __builtin_fmaf(t, 0x1.24924ap-3f, -0x1.555556p-3f);
+        q = __builtin_fmaf(t, q, 0.2f);
+        q = __builtin_fmaf(t, q, -0.25f);
+        q = __builtin_fmaf(t, q, 0x1.555556p-2f);
+        q = __builtin_fmaf(t, q, -0.5f);
+        return __builtin_fmaf(t, q, 1.0f);
+    }
+    return __builtin_amdgcn_logf(1.0f + t) * 0.693147181f * __builtin_amdgcn_rcpf(t);
+}
+
 // Independence-Metropolis decision of the learned proposal at one link.  r0
 // points at row g0 of the knot table (row g0 + 1 follows at r0 + 33); the
 // proposal's knots are the rows' linear mix with weight f (y_0 = -1 and
-// y_32 = +1 in every row).  u0 picks the proposed x0 from the piecewise-linear
-// inverse CDF, u1 decides; xc is the current link's x0.  Returns whether the
-// proposal is accepted and sets xp (the proposed x0) and num = 1 - xp^2.  Ptr
-// is an LDS or a global pointer type, so each table location gets its own
-// load instructions.
+// y_32 = +1 in every row).  Segment j = floor(32 u0) is chosen with
+// probability 1/32 and x0 drawn inside it from the density proportional to
+// exp(alpha x) -- the exponential factor of the target, so that only the
+// slowly varying sqrt(1 - x^2) is left for the accept step to correct.  u1
+// decides; xc is the current link's x0.  Returns whether the proposal is
+// accepted and sets xp (the proposed x0) and num = 1 - xp^2.  Ptr is an LDS
+// or a global pointer type, so each table location gets its own load
+// instructions.
+//
+// With w = y_{j+1} - y_j, E = e^{alpha w} - 1 and s = E / alpha (which stays
+// finite as alpha -> 0), the draw is x = y_j + ln(1 + v E) / alpha for
+// v = 32 u0 - j, and the proposal density is q(x) = e^{alpha (x - y_j)} / (32 s).
+// The target pi(x) = sqrt(1 - x^2) e^{alpha x} over q is then
+// 32 sqrt(1 - x^2) e^{alpha y_j} s, and the acceptance ratio
+// r = sqrt((1 - x'^2) / (1 - xc^2)) e^{alpha (y_j' - y_jc)} s_j' / s_jc.
 template <typename Ptr>
 __device__ __forceinline__ bool imh_decide(Ptr r0, float f, float u0, float u1, float alpha,
                                            float xc, float &xp, float &num)
@@ -260,21 +301,44 @@ __device__ __forceinline__ bool imh_decide(Ptr r0, float f, float u0, float u1, 
         if (xc >= knot(lo + step)) lo += step;
     const float ylo = lo == 0u ? -1.0f : knot(lo);
     const float yhi = lo == 31u ? 1.0f : knot(lo + 1u);
-    const float wc = yhi - ylo;
-    xp = ya + (32.0f * u0 - (float)jp) * (yb - ya);
+    const float wp = yb - ya, wc = yhi - ylo;
+    const float v = 32.0f * u0 - (float)jp;  // exact
+    const float zp = alpha * wp, zc = alpha * wc;
+    // x' and the ratio E_j' / E_jc (= s_j' / s_jc).  With alpha >= 1/8 and both
+    // z = alpha w >= 1/256 (segments of a table near the integrated one are
+    // wider than 1/30 at small alpha, so that is nearly every update), e^z - 1
+    // and ln(1 + v E) straight from hardware exp2 and log2 (absolute error
+    // ~1.2e-7 in e^z and ~6e-8 in 1 + v E) move x' by about 2e-7 / alpha at
+    // most and the ratio by 1.2e-7 / z <= 3e-5 relative; otherwise the series
+    // forms keep a few ulps down to alpha -> 0.
+    float e_ratio;
+    if (alpha >= 0.125f && zp >= 0x1p-8f && zc >= 0x1p-8f) {
+        const float Ep = __builtin_amdgcn_exp2f(zp * 1.44269504f) - 1.0f;
+        const float Ec = __builtin_amdgcn_exp2f(zc * 1.44269504f) - 1.0f;
+        xp = ya + __builtin_amdgcn_logf(__builtin_fmaf(v, Ep, 1.0f)) *
+                      (0.693147181f * __builtin_amdgcn_rcpf(alpha));
+        e_ratio = Ep * __builtin_amdgcn_rcpf(Ec);
+    } else {
+        // ln(1 + v E) / alpha = v s Q(v E), Q(t) = ln(1 + t) / t
+        const float sp = wp * expm1_over(zp), sc = wc * expm1_over(zc);
+        const float vs = v * sp;
+        xp = ya + vs * log1p_over(alpha * vs);
+        e_ratio = sp * __builtin_amdgcn_rcpf(sc);
+    }
     num = 1.0f - xp * xp;
     const float den = 1.0f - xc * xc;
-    if (num <= 0.0f) return false;  // target density vanishes at the proposal
-    if (den <= 0.0f) return true;   // ... or at the current value
-    // r = [pi(x') / q(x')] / [pi(x) / q(x)] with pi(x) = sqrt(1 - x^2) e^{alpha x}
-    // and q = (1/32) / width.  alpha <= 40 keeps the exponent within +-80, so
-    // the product cannot overflow to anything but +inf (accept) or underflow to
-    // anything but 0 (reject, as u1 >= 2^-24); hardware exp2, rcp and sqrt
-    // carry relative errors of order 1e-6, far inside the statistical slack of
-    // an accept decision.
-    const float e = __builtin_amdgcn_exp2f(alpha * (xp - xc) * 1.44269504f);
-    const float ratio = __builtin_amdgcn_sqrtf(num * __builtin_amdgcn_rcpf(den)) * (yb - ya) *
-                        __builtin_amdgcn_rcpf(wc) * e;
+    // the target density vanishes at the proposal, or the proposal sits on a
+    // zero-width segment (an atom of q): reject; else if it vanishes at the
+    // current value: accept
+    if (num <= 0.0f || wp == 0.0f) return false;
+    if (den <= 0.0f) return true;
+    // alpha <= 40 keeps alpha (y_j' - y_jc) within +-80.  Overflow to +inf
+    // needs a true ratio far above 1 (accept), underflow to 0 one far below
+    // u1 >= 2^-24 (reject).
+    // Hardware exp2, rcp and sqrt carry relative errors of order 1e-6, far
+    // inside the statistical slack of an accept decision.
+    const float e = __builtin_amdgcn_exp2f(alpha * (ya - ylo) * 1.44269504f);
+    const float ratio = __builtin_amdgcn_sqrtf(num * __builtin_amdgcn_rcpf(den)) * (e * e_ratio);
     return u1 <= ratio;
 }
 

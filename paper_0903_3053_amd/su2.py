@@ -31,7 +31,7 @@ EXPORTS = (
     "su2_batch_set_spin_limit", "su2_batch_plaquette", "su2_batch_links", "su2_batch_counters",
     "su2_batch_sweep_index", "su2_batch_last_error", "su2_batch_finalize",
     "su2_cdf_knots", "su2_mlp_set_params", "su2_mlp_get_params", "su2_mlp_forward",
-    "su2_mlp_loss_grad", "su2_mlp_train", "su2_mlp_tabulate", "su2_mlp_table",
+    "su2_mlp_loss_grad", "su2_mlp_train", "su2_mlp_tabulate", "su2_mlp_table", "su2_cdf_tabulate",
     "su2_mlp_last_error", "su2_set_proposal", "su2_set_creutz", "su2_imh_counters",
 )
 
@@ -111,6 +111,7 @@ def load():
                           ctypes.c_int),
         "su2_mlp_tabulate": ([ctypes.c_int32], ctypes.c_int),
         "su2_mlp_table": ([fp, ctypes.c_size_t], ctypes.c_int),
+        "su2_cdf_tabulate": ([ctypes.c_int32], ctypes.c_int),
         "su2_mlp_last_error": ([], ctypes.c_char_p),
         "su2_set_proposal": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_uint16), ctypes.c_size_t],
                              ctypes.c_int),
@@ -446,6 +447,12 @@ def su2_mlp_train(alphas, steps, lr0=3e-3, lr_min=1e-5):
 
 def su2_mlp_tabulate(points=4096):
     _mcheck(load().su2_mlp_tabulate(int(points)))
+    _keep["table_points"] = int(points)
+
+
+def su2_cdf_tabulate(points=31):
+    """The knot table from the integrated CDF instead of the network."""
+    _mcheck(load().su2_cdf_tabulate(int(points)))
     _keep["table_points"] = int(points)
 
 

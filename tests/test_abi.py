@@ -132,6 +132,9 @@ def test_extension_entry_points_reject_bad_arguments(lib):
     kf = (ctypes.c_float * 33)()
     assert lib.su2_mlp_forward(af, 1, kf) == su2.SU2_ESTATE
     assert lib.su2_mlp_tabulate(31) == su2.SU2_ESTATE
+    # the CDF table needs no parameters; its size is checked before any device call
+    assert lib.su2_cdf_tabulate(1) == su2.SU2_EINVAL
+    assert lib.su2_cdf_tabulate(65537) == su2.SU2_EINVAL
     # the lattice is gone after su2_finalize: proposal selection is a state error
     lib.su2_finalize()
     assert lib.su2_set_proposal(1, None, 0) == su2.SU2_ESTATE

@@ -103,16 +103,49 @@ def _table_with_row(alpha_exact_row, knots_row):
     return t
 
 
+def _expected_acceptance(alpha, knots, per_segment=4000):
+    """Stationary acceptance of the independence sampler, E min(1, W(x')/W(x))
+    for x ~ pi, x' ~ q, W = pi / q, by midpoint quadrature: pi(x) ~
+    sqrt(1 - x^2) e^{alpha x} and q = 1/32 per segment, ~ e^{alpha x} inside.
+    Written from those two densities alone (no part of the oracle's draw)."""
+    xs, pis, qs = [], [], []
+    for j in range(32):
+        a, b = knots[j], knots[j + 1]
+        h = (b - a) / per_segment
+        x = a + h * (np.arange(per_segment) + 0.5)
+        t = np.exp(alpha * (x - b))                     # e^{alpha (x - b)} <= 1
+        qx = t / np.sum(t) / 32.0                       # segment mass 1/32
+        xs.append(x)
+        qs.append(qx)
+        pis.append(np.sqrt(1.0 - x * x) * np.exp(alpha * (x - 1.0)) * h)
+    x, q, pi = np.concatenate(xs), np.concatenate(qs), np.concatenate(pis)
+    pi /= pi.sum()
+    W = pi / q
+    order = np.argsort(W)
+    W, q, pi = W[order], q[order], pi[order]
+    # for x at rank i: proposals with W' >= W_i accept surely, the others with W'/W_i
+    q_above = np.cumsum(q[::-1])[::-1]
+    qw_below = np.concatenate([[0.0], np.cumsum(q * W)[:-1]])
+    return float(np.sum(pi * (q_above + qw_below / W)))
+
+
 def test_imh_step_leaves_the_conditional_invariant():
+    """At alpha = 6 every link runs its own chain: its x0 samples follow the
+    conditional (KS), and the acceptance rate equals the quadrature value for
+    the tilted proposal (it would be 0.935 for one flat inside each segment)."""
     beta = 1.0  # alpha = 6: row 6 of a 41-row table on [0, 40]
     exact = cdf.knots(6.0)
     x, rate = _imh_chain_samples(_table_with_row(6, exact), beta, 400)
-    assert rate > 0.9
+    want = _expected_acceptance(6.0, exact)
+    print(f"alpha 6, exact knots: acceptance {rate:.4f}, quadrature {want:.4f}")
+    assert want > 0.97 and abs(rate - want) < 3e-3
     assert stats.kstest(x, X0Cdf(6.0)).pvalue > 1e-3
     # a poor proposal (uniform knots) is slower but still exact
-    x2, rate2 = _imh_chain_samples(np.tile(np.linspace(-1, 1, 33), (41, 1)), beta, 1200, thin=30,
-                                   burn=120)
-    assert rate2 < rate
+    uniform = np.linspace(-1, 1, 33)
+    x2, rate2 = _imh_chain_samples(np.tile(uniform, (41, 1)), beta, 1200, thin=30, burn=120)
+    want2 = _expected_acceptance(6.0, uniform)
+    print(f"alpha 6, uniform knots: acceptance {rate2:.4f}, quadrature {want2:.4f}")
+    assert rate2 < rate and abs(rate2 - want2) < 6e-3
     assert stats.kstest(x2, X0Cdf(6.0)).pvalue > 1e-3
 
 

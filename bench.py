@@ -43,8 +43,10 @@ WORKLOADS = {
 FUSED_PAIRS = 300  # the launch plan that runs each parity as two fused-pair launches
 SWEEPS_PER_STEP = 5  # Sec. 2.4: measured configurations are 5 sweeps apart
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_pass_traffic.json")
+# everything the pass kernel is compiled from, and the build flags
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_0903_3053_amd", "csrc", f)
-                  for f in ("su2_kernels.hip", "su2_device.hpp", "su2_pass.hpp")]
+                  for f in ("su2_kernels.hip", "su2_kernels.hpp", "su2_device.hpp", "su2_pass.hpp",
+                            "su2_pair.hpp")] + [os.path.join(ROOT, "paper_0903_3053_amd", "build.py")]
 
 
 def kernel_hash():
@@ -607,6 +609,8 @@ def main():
                     help="use this pass-kernel launch plan")
     ap.add_argument("--therm", type=int, default=300,
                     help="untimed sweeps after the hot start, before the warm-up steps")
+    ap.add_argument("--learned-sweeps", type=int, default=100000,
+                    help="sweeps of each chain in the learned-proposal workload")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device copy (torch), so that a counter "
                          "profile of this command also holds the copy of known size")
@@ -732,7 +736,10 @@ def main():
         for name in args.extra or EXTRAS:
             t_x = time.perf_counter()
             print(f"extra workload {name} ...", file=sys.stderr, flush=True)
-            rec[name] = EXTRA_FUNCS[name](su2)
+            if name == "learned_proposal":
+                rec[name] = learned_proposal(su2, sweeps=args.learned_sweeps)
+            else:
+                rec[name] = EXTRA_FUNCS[name](su2)
             print(f"extra workload {name} done in {time.perf_counter() - t_x:.1f} s", file=sys.stderr, flush=True)
         if "batched_replicas" in rec:
             check = rec["batched_replicas"].pop("_check")

@@ -82,7 +82,8 @@ def test_gradient_matches_finite_differences(rounded):
 def _imh_chain_samples(table, beta, passes, thin=10, burn=40):
     """All links equal to g: every (parity 0, mu 1) link has staple 6 g and keeps
     it while that pass is repeated, so each link runs its own chain at alpha = 6
-    beta.  Returns thinned x0 = dot(U, g) samples and the acceptance rate."""
+    beta.  Returns thinned x0 = dot(U, g) samples and the acceptance rate
+    after the burn-in."""
     dims = (4, 4, 4, 4)
     g = np.array([0.5, 0.5, -0.5, 0.5])
     U = np.tile(g, (256, 4, 1)).copy()
@@ -90,8 +91,9 @@ def _imh_chain_samples(table, beta, passes, thin=10, burn=40):
     xs, prop, acc = [], 0, 0
     for s in range(passes):
         _, _, p, a = oracle.imh_pass(dims, U, beta, 7, s, 0, 1, table)
-        prop += p
-        acc += a
+        if s >= burn:  # the start (x0 = 1, where pi vanishes) accepts every proposal
+            prop += p
+            acc += a
         if s >= burn and s % thin == 0:
             xs.append(U[par == 0, 1] @ g)
     return np.concatenate(xs), acc / prop
@@ -147,6 +149,28 @@ def test_imh_step_leaves_the_conditional_invariant():
     print(f"alpha 6, uniform knots: acceptance {rate2:.4f}, quadrature {want2:.4f}")
     assert rate2 < rate and abs(rate2 - want2) < 6e-3
     assert stats.kstest(x2, X0Cdf(6.0)).pvalue > 1e-3
+
+
+def test_imh_knots_between_table_rows():
+    """alpha = 6.5 lies halfway between rows 6 and 7 of a 41-row table on
+    [0, 40]: row 6 holds the exact knots at alpha 6, row 7 uniform knots, so
+    the proposal uses their even mix.  The chain stays exact (KS against the
+    exact CDF at 6.5) and its acceptance equals the quadrature value for the
+    mixed knots -- far from that of either row alone."""
+    t = np.tile(np.linspace(-1, 1, 33), (41, 1))
+    t[6] = cdf.knots(6.0)
+    beta = 6.5 / 6.0
+    x, rate = _imh_chain_samples(t, beta, 800, thin=20, burn=80)
+    mixed = 0.5 * (t[6] + t[7])
+    want = _expected_acceptance(6.5, mixed)
+    only6, only7 = _expected_acceptance(6.5, t[6]), _expected_acceptance(6.5, t[7])
+    print(f"alpha 6.5 between rows: acceptance {rate:.4f}, quadrature {want:.4f} "
+          f"(row 6 alone {only6:.4f}, row 7 alone {only7:.4f})")
+    # at 36 % acceptance the accept indicator is correlated over many passes:
+    # about 0.004 of statistical spread, far below the rows' own values
+    assert abs(rate - want) < 1e-2
+    assert min(abs(want - only6), abs(want - only7)) > 0.1
+    assert stats.kstest(x, X0Cdf(6.5)).pvalue > 1e-3
 
 
 def test_imh_fallbacks_by_alpha():

@@ -290,6 +290,35 @@ def learned_proposal(su2, sweeps=100000, train_steps=30000):
                                                               r["tau_int_err"] / r["tau_int_sweeps"]))
         r["z_plaquette_vs_heat_bath"] = (r["plaquette"] - kp["plaquette"]) / float(
             np.hypot(kp["plaquette_err"], r["plaquette_err"]))
+    # what training buys: the same step on the untrained network's table and
+    # on uniform knots (all parameters zero: equal softmax widths), shorter
+    # chains, rates timed beside the heat-bath's on the learned plan
+    trained, _ = su2.su2_mlp_get_params()
+    ablations = {}
+    for name, params in (("untrained_imh", su2_inputs.mlp_init(1)),
+                         ("uniform_knots_imh", np.zeros_like(trained))):
+        su2.su2_mlp_set_params(params)
+        su2.su2_mlp_tabulate(TABLE_ROWS)
+        su2.su2_init(dims, beta, seed, 1)
+        use(1, None, plans["learned_imh"])
+        n_ab = max(sweeps // 5, 1000)
+        h = su2.su2_sweep_measure(n_ab, 1)[:, 0]
+        prop, acc = su2.su2_imh_counters()
+        m, e, tau, dtau, _ = gamma_method(h[n_ab // 10:])
+        t = {}
+        for kind in (0, 1):
+            use(kind, None, plans["learned_imh"])
+            su2.su2_sweep(2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            su2.su2_sweep(200)
+            torch.cuda.synchronize()
+            t[kind] = 4 * V * 200 / (time.perf_counter() - t0)
+        ablations[name] = {"acceptance": acc / max(prop, 1), "sweeps": n_ab, "plaquette": m, "plaquette_err": e,
+                           "tau_int_sweeps": tau, "tau_int_err": dtau, "link_updates_per_s": t[1],
+                           "heat_bath_link_updates_per_s_same_plan": t[0],
+                           "effective_speed_ratio": (t[1] / tau) / (t[0] / kp["tau_int_sweeps"])}
+    su2.su2_mlp_set_params(trained)
     su2.su2_mlp_tabulate(TABLE_ROWS)
     scan = beta_scan(su2, dims, seed, {0: plans["kennedy_pendleton"], 1: plans["learned_imh"]})
     su2.su2_finalize()
@@ -297,6 +326,7 @@ def learned_proposal(su2, sweeps=100000, train_steps=30000):
     return {"workload": f"32^4 beta 2.3 hot seed 1, {sweeps} sweeps each: heat-bath, learned proposal, "
                         f"and the same proposal on the integrated CDF's knots",
             "beta_scan": scan,
+            "ablations": ablations,
             "training": {"steps": train_steps, "alphas": 4096, "seconds": t_train, "table_rows": TABLE_ROWS,
                          "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
             **out,
@@ -310,7 +340,8 @@ def couplings_32(su2, therm=100, sweeps=200):
     """The 32^4 workload (hot start, Philox seed 1, plain heat-bath) at beta in
     {2.2, 2.3, 2.4, 2.5}, each with the tuned launch plan: `sweeps` sweeps
     after `therm`, the plaquette reduced in FP64 after every sweep into a
-    device history (su2_sweep_measure), timed on the library's stream.  The
+    device history (su2_sweep_measure), timed on the library's stream; then
+    as many sweeps without measurement, timed alike.  The
     lattice (64 MiB) fits the 256 MB Infinity Cache, so the bytes fraction is
     of the algorithmic traffic, not a measure of HBM."""
     import numpy as np
@@ -329,10 +360,18 @@ def couplings_32(su2, therm=100, sweeps=200):
         h = su2.su2_sweep_measure(sweeps, 1)
         dt = time.perf_counter() - t0
         rate = 4 * V * sweeps / dt
+        # the sweeps alone (no measurement), on the library's stream
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        su2.su2_sweep(sweeps)
+        torch.cuda.synchronize()
+        rate_sweeps = 4 * V * sweeps / (time.perf_counter() - t0)
         m, e, tau, _, _ = gamma_method(h[:, 0])
         rows.append({"beta": beta, "link_updates_per_s": rate,
                      "algorithmic_GBps": rate * BYTES_PER_UPDATE / 1e9,
                      "algorithmic_frac": rate * BYTES_PER_UPDATE / 1e9 / HBM_PEAK_GBS,
+                     "sweeps_only_link_updates_per_s": rate_sweeps,
+                     "sweeps_only_algorithmic_frac": rate_sweeps * BYTES_PER_UPDATE / 1e9 / HBM_PEAK_GBS,
                      "plaquette": m, "plaquette_err": e, "tau_int_sweeps": tau,
                      "pass_plan": {"tile_order": plan[0], "lds_bytes": plan[1]}})
     su2.su2_finalize()

@@ -539,9 +539,13 @@ static void update_one_imh(const int dims[4], double beta, uint64_t seed, uint32
     /* r = sqrt((1 - x'^2) / (1 - x^2)) exp(alpha (y_jp - y_jc)) E_jp / E_jc */
     double lr_terms[3];
     double num = 1.0 - xp * xp, den = 1.0 - xc * xc;
+    /* a proposal on a segment of zero (or, from rounding, negative) width is
+     * an atom of q: reject it; a current value on such a segment, or where
+     * pi vanishes, accepts any proposal */
+    double wp = y[jp + 1] - y[jp], wc = y[jc + 1] - y[jc];
     int accept_always = 0, reject_always = 0;
-    if (num <= 0.0 || Ep == 0.0) reject_always = 1;
-    else if (den <= 0.0) accept_always = 1;
+    if (num <= 0.0 || !(wp > 0.0)) reject_always = 1;
+    else if (den <= 0.0 || !(wc > 0.0)) accept_always = 1;
     lr_terms[0] = (num > 0.0 && den > 0.0) ? 0.5 * log(num / den) : 0.0;
     lr_terms[1] = alpha * (y[jp] - y[jc]);
     lr_terms[2] = (Ep > 0.0 && Ec > 0.0) ? log(Ep / Ec) : 0.0;

@@ -328,10 +328,11 @@ __device__ __forceinline__ bool imh_decide(Ptr r0, float f, float u0, float u1, 
     num = 1.0f - xp * xp;
     const float den = 1.0f - xc * xc;
     // the target density vanishes at the proposal, or the proposal sits on a
-    // zero-width segment (an atom of q): reject; else if it vanishes at the
-    // current value: accept
-    if (num <= 0.0f || wp == 0.0f) return false;
-    if (den <= 0.0f) return true;
+    // segment of zero (or, from rounding, negative) width, an atom of q:
+    // reject; else if it vanishes at the current value, or the current value
+    // sits on such a segment: accept
+    if (num <= 0.0f || !(wp > 0.0f)) return false;
+    if (den <= 0.0f || !(wc > 0.0f)) return true;
     // alpha <= 40 keeps alpha (y_j' - y_jc) within +-80.  Overflow to +inf
     // needs a true ratio far above 1 (accept), underflow to 0 one far below
     // u1 >= 2^-24 (reject).

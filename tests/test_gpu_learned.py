@@ -288,6 +288,21 @@ def test_imh_pass_small_alpha(lib, beta, all_series):
     assert np.all(codes >= 10) and flips <= 2
 
 
+def test_imh_pass_zero_width_segment(lib):
+    """A network whose output 5 has bias -1000: segment 5 has width exactly 0
+    in every table row on both sides (the softmax underflows in FP32 and FP64),
+    an atom of the proposal.  Proposals drawn there are rejected and current
+    values there accept; link for link as the oracle's."""
+    p = su2_inputs.mlp_init(5).copy()
+    p[mlp.NPARAM - 33 + 5] = -1000.0  # b3[5]
+    dims = (12, 12, 12, 12)
+    codes, alphas, flips = _imh_case(lib, dims, su2_inputs.near_identity_links(dims, 21, 0.35), 2.3, 31, p)
+    table = lib.su2_mlp_table()
+    assert np.all(table[:, 6] == table[:, 5])
+    print(f"IMH zero-width segment: acceptance {np.mean(codes == 10):.4f}, {flips} flips")
+    assert np.all(codes >= 10) and flips <= 2
+
+
 def test_imh_pass_alpha_above_table_falls_back_to_heat_bath(lib):
     """beta = 12 on near-identity links: every alpha is above 40, so every
     update takes the capped Kennedy-Pendleton fallback (no proposals), link

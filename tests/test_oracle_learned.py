@@ -128,7 +128,9 @@ def _expected_acceptance(alpha, knots, per_segment=4000):
     # for x at rank i: proposals with W' >= W_i accept surely, the others with W'/W_i
     q_above = np.cumsum(q[::-1])[::-1]
     qw_below = np.concatenate([[0.0], np.cumsum(q * W)[:-1]])
-    return float(np.sum(pi * (q_above + qw_below / W)))
+    # a current value where W = 0 (a zero-width segment: pi puts no mass there) adds nothing
+    safe = np.where(W > 0, W, 1.0)
+    return float(np.sum(np.where(W > 0, pi * (q_above + qw_below / safe), 0.0)))
 
 
 def test_imh_step_leaves_the_conditional_invariant():
@@ -171,6 +173,23 @@ def test_imh_knots_between_table_rows():
     assert abs(rate - want) < 1e-2
     assert min(abs(want - only6), abs(want - only7)) > 0.1
     assert stats.kstest(x, X0Cdf(6.5)).pvalue > 1e-3
+
+
+def test_imh_zero_width_segment():
+    """A table whose segment 10 has zero width (an atom of the proposal):
+    proposals drawn there are rejected and the chain stays exact; the
+    acceptance equals the quadrature value, in which that atom contributes
+    nothing (0.92, against 0.98 with the exact knots: the neighbouring segment
+    also carries two quantiles' mass at one quantile's probability)."""
+    k = cdf.knots(6.0).copy()
+    k[11] = k[10]
+    t = np.tile(np.linspace(-1, 1, 33), (41, 1))
+    t[6] = k
+    x, rate = _imh_chain_samples(t, 1.0, 400)
+    want = _expected_acceptance(6.0, k)
+    print(f"alpha 6, zero-width segment: acceptance {rate:.4f}, quadrature {want:.4f}")
+    assert abs(rate - want) < 5e-3 and want < 0.97
+    assert stats.kstest(x, X0Cdf(6.0)).pvalue > 1e-3
 
 
 def test_imh_fallbacks_by_alpha():

@@ -144,15 +144,20 @@ __device__ __forceinline__ float kp_lambda2(float num, float two_alpha)
 // alpha: y uniform on [exp(-2 alpha), 1] makes x0 = 1 + ln(y) / alpha
 // distributed as exp(alpha x0) on [-1, 1], and the attempt is accepted with
 // probability sqrt(1 - x0^2).  With m = 1 - x0 = -ln(y) / alpha (so m / 2
-// plays the part of lambda^2) and y = 1 - (1 - u) (1 - exp(-2 alpha)), this
-// returns L = alpha m = -ln y, written with expm1 and log1p so that m stays
-// accurate as alpha -> 0; the test and m need only one division, for the
-// accepted attempt.
-__device__ __forceinline__ float creutz_l(float u, float alpha)
+// plays the part of lambda^2) and y = 1 + z, z = -(1 - u) d, d = 1 - exp(-2
+// alpha) (formed once per update, with expm1), this returns L = alpha m =
+// -ln(1 + z); the test and m need only one division, for the accepted attempt.
+// ln(1 + z) is Kahan's ln(y) z / (y - 1) with y the rounded 1 + z: the factor
+// undoes the rounding of y, so L keeps a few ulps as z -> 0 (m accurate as
+// alpha -> 0) with the hardware log2, which is within one ulp of its result
+// also next to 1.
+__device__ __forceinline__ float creutz_l(float u, float d)
 {
 #pragma clang fp contract(off)
-    const float d = -expm1f(-2.0f * alpha);
-    return -log1pf(-(1.0f - u) * d);
+    const float z = -(1.0f - u) * d;  // in (-1, 0]
+    const float y = 1.0f + z;
+    const float l = -(ln_unit(y) * (z * __builtin_amdgcn_rcpf(y - 1.0f)));
+    return y == 1.0f ? -z : l;
 }
 
 // u1 <= sqrt(1 - x0^2) with 1 - x0^2 = m (2 - m) = L (2 alpha - L) / alpha^2,
@@ -451,6 +456,9 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
     // below the switch the attempts draw Creutz's way (same cap, same slots)
     const bool creutz = CREUTZ && alpha < imh.creutz_below;
     const float two_alpha = 2.0f * alpha;
+    float creutz_d = 0.0f;  // 1 - exp(-2 alpha), for the Creutz lanes
+    if constexpr (CREUTZ)
+        if (creutz) creutz_d = -expm1f(-two_alpha);
     float lam2 = 0.0f, num_acc = 0.0f;
     unsigned long long attempts = 0;
     for (uint32_t t = 0; t < 8u; ++t) {
@@ -460,7 +468,7 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
         if (!done) {
             const uint4 r = draw(key, lex, MU, kPurposeUpdate, s, t);
             if (creutz) {
-                const float l = creutz_l(unit24(r.x), alpha);
+                const float l = creutz_l(unit24(r.x), creutz_d);
                 if (creutz_accept(unit24(r.y), l, alpha, two_alpha)) {
                     done = true;
                     num_acc = l;

@@ -247,7 +247,9 @@ int su2_tune(int32_t reps, int32_t out[2]);
  * step corrects only sqrt(1 - x0^2) and the knots' errors).  Used as an
  * independence-Metropolis proposal with the exact acceptance ratio it leaves
  * that conditional invariant, with the Kennedy-Pendleton draw as the fallback
- * outside the network's range.  Network: 1 -> 64 -> 64 -> 33 on alpha / 40,
+ * outside the network's range.  A rejected proposal keeps the link's x0 and
+ * still redraws its direction about the staple (a Gibbs step: the direction
+ * is uniform given x0).  Network: 1 -> 64 -> 64 -> 33 on alpha / 40,
  * SiLU, BF16 weights with FP32 accumulation; outputs 0..31 give segment widths
  * 2 softmax(z), output 32 is reserved.  Parameters: 6433 float32 in the order
  * W1 (64x1), b1 (64), W2 (64x64), b2 (64), W3 (33x64), b3 (33), row-major.

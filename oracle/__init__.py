@@ -245,7 +245,8 @@ def _table(table):
 def imh_pass(dims, U, beta, seed, sweep_index, parity, mu, table, alpha_max=40.0, prec32=True):
     """In-place pass with the learned independence-Metropolis proposal.
     Returns (result codes per site, margins, proposals, accepts); codes 10 =
-    accepted, 11 = rejected, 0..9 = plain heat-bath codes."""
+    accepted, 11 = rejected (x0 kept, direction redrawn), 0..9 = plain
+    heat-bath codes."""
     lib = _load()
     d = _dims(dims)
     if not (isinstance(U, np.ndarray) and U.dtype == np.float64 and U.flags.c_contiguous):

@@ -483,8 +483,10 @@ int oracle_update_sites(const int dims[4], double beta, uint64_t seed, uint32_t 
 /* The target for x0 is pi(x) ~ sqrt(1 - x^2) exp(alpha x) (the same local     */
 /* conditional the heat-bath samples); the step accepts with probability      */
 /* min(1, [pi(x') / q(x')] / [pi(x) / q(x)]), x = dot(U_old, V), so it leaves */
-/* that conditional invariant.  alpha = 0 takes the Haar draw and alpha above */
-/* alpha_max the capped Kennedy-Pendleton draw, as in the plain pass.         */
+/* that conditional invariant.  On rejection x0 keeps its value and the      */
+/* direction is drawn afresh (a Gibbs step on the uniform direction).         */
+/* alpha = 0 takes the Haar draw and alpha above alpha_max the capped         */
+/* Kennedy-Pendleton draw, as in the plain pass.                              */
 /* ------------------------------------------------------------------------- */
 static void knots_at(const double *table, int G, double alpha_max, double alpha, double y[33])
 {
@@ -504,7 +506,7 @@ static int segment_of(const double y[33], double x)
     return j;
 }
 
-/* *res: 10 = proposal accepted, 11 = rejected (link kept), or the plain-pass
+/* *res: 10 = proposal accepted, 11 = rejected (x0 kept, direction redrawn), or the plain-pass
  * codes (0..9) when the plain heat-bath handled the update. */
 static void update_one_imh(const int dims[4], double beta, uint64_t seed, uint32_t sweep, int mu,
                            int prec32, const double *U, long lex, const double *table, int G,
@@ -565,18 +567,18 @@ static void update_one_imh(const int dims[4], double beta, uint64_t seed, uint32
         m = fabs(lu - lr);
     }
     *margin = m;
-    if (!acc) {
-        memcpy(out, uo, 4 * sizeof(double));
-        *res = 11;
-        return;
-    }
+    /* accepted: x0 = x'; rejected: x0 stays x (the current value) and the  */
+    /* direction about V is drawn afresh from (u2, u3) all the same -- the  */
+    /* conditional of the direction given x0 is uniform, so this Gibbs step */
+    /* keeps the target invariant                                           */
+    double x0 = acc ? xp : xc;
     double c = 2.0 * u[2] - 1.0, phi = 2.0 * M_PI * u[3];
-    double sn = sqrt(1.0 - c * c), am = sqrt(1.0 - xp * xp);
-    double X[4] = { xp, am * sn * cos(phi), am * sn * sin(phi), am * c };
+    double sn = sqrt(1.0 - c * c), am = sqrt(fmax(0.0, 1.0 - x0 * x0));
+    double X[4] = { x0, am * sn * cos(phi), am * sn * sin(phi), am * c };
     double Un[4];
     oracle_qmul(X, V, Un);
     store_unit(out, Un, prec32);
-    *res = 10;
+    *res = acc ? 10 : 11;
 }
 
 /* One pass with the learned proposal; stats[0] += independence-Metropolis

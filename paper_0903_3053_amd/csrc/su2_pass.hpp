@@ -513,16 +513,16 @@ __device__ __forceinline__ float4 update_link(float4 *__restrict__ L, const Geo 
                 acc = imh_decide((const __attribute__((address_space(1))) float *)imh.knots + 33u * g0, f,
                                  unit24(r.x), unit24(r.y), alpha, xc, xp, num);
             }
-            if (acc) {
-                rotate = true;
-                x0n = xp;
-                amag = __builtin_amdgcn_sqrtf(num);
-                rz = r.z;
-                rphi = r.w;
-            } else {
-                un = uold;
-                rejected = true;
-            }
+            // accepted: x0 = x'; rejected: x0 keeps the current value xc but the
+            // direction about V is drawn afresh all the same (the target's
+            // conditional of the direction given x0 is uniform, so this Gibbs
+            // step costs nothing in exactness and refreshes the rejected link)
+            rotate = true;
+            x0n = acc ? xp : xc;
+            amag = __builtin_amdgcn_sqrtf(acc ? num : fmaxf(0.0f, 1.0f - xc * xc));
+            rz = r.z;
+            rphi = r.w;
+            rejected = !acc;
         }
         const unsigned long long nprop = __popcll(__ballot(imh_lane));
         const unsigned long long nacc = __popcll(__ballot(imh_lane && !rejected));

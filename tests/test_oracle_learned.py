@@ -192,6 +192,35 @@ def test_imh_zero_width_segment():
     assert stats.kstest(x, X0Cdf(6.0)).pvalue > 1e-3
 
 
+def test_imh_rejection_redraws_the_direction():
+    """A rejected proposal keeps x0 = dot(U, V) and draws the direction about V
+    afresh: after a pass with a poor (uniform) table on Haar links (FP64
+    links), every rejected link has the same x0 to 1e-12, the direction n of
+    U' V^dag is uniform on the sphere (KS of n_z on [-1, 1] and of its
+    azimuth) and uncorrelated with the old one."""
+    import su2_np
+    dims = (8, 8, 8, 8)
+    U0 = su2_inputs.random_links(dims, 17).astype(np.float64)
+    mu, parity = 2, 0
+    W = su2_np.staples(U0, dims)[:, mu]
+    V = W / np.linalg.norm(W, axis=1)[:, None]
+    U = U0.copy()
+    res, _, p, a = oracle.imh_pass(dims, U, 1.0, 3, 0, parity, mu, np.tile(np.linspace(-1, 1, 33), (5, 1)),
+                                   prec32=False)
+    rej = res == 11
+    assert rej.sum() > 500 and p - a == rej.sum()
+
+    def x_of(Q):  # Q V^dag as quaternions
+        return su2_np.from_matrix(su2_np.to_matrix(Q) @ su2_np.dag(su2_np.to_matrix(V[rej])))
+    xn, xo = x_of(U[rej, mu]), x_of(U0[rej, mu])
+    assert np.max(np.abs(xn[:, 0] - xo[:, 0])) < 1e-12
+    n_new = xn[:, 1:] / np.linalg.norm(xn[:, 1:], axis=1)[:, None]
+    n_old = xo[:, 1:] / np.linalg.norm(xo[:, 1:], axis=1)[:, None]
+    assert stats.kstest(n_new[:, 2], stats.uniform(-1, 2).cdf).pvalue > 1e-3
+    assert stats.kstest(np.arctan2(n_new[:, 1], n_new[:, 0]), stats.uniform(-np.pi, 2 * np.pi).cdf).pvalue > 1e-3
+    assert abs(np.mean(np.sum(n_new * n_old, axis=1))) < 4.0 / np.sqrt(rej.sum())
+
+
 def test_imh_fallbacks_by_alpha():
     """Updates whose alpha lies above the table's range use the plain heat-bath
     (identical links and codes); those inside use the proposal; alpha = 0 takes

@@ -4,8 +4,8 @@
 Network 1 -> 64 -> 64 -> 33 on t = alpha / ALPHA_MAX:
     h1 = silu(W1 t + b1), h2 = silu(W2 h1 + b2), z = W3 h2 + b3,
     silu(a) = a / (1 + exp(-a)).
-The first 32 outputs give the segment widths of a monotone piecewise-linear
-inverse CDF of x0 on [-1, 1]: w = 2 softmax(z[0:32]), knots
+The first 32 outputs give the widths of the proposal's 32 equal-probability
+segments of x0 on [-1, 1]: w = 2 softmax(z[0:32]), knots
 y_0 = -1, y_j = -1 + sum_{i<j} w_i (so y_32 = +1).  Output 32 is reserved: it
 enters neither the proposal nor the loss.
 Loss: L = mean over samples and the 32 segments of (log w_j - log w*_j)^2,

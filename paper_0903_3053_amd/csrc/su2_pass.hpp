@@ -12,7 +12,7 @@ constexpr int kBlock = 256;
 constexpr int kWave = 64;
 
 // Knot table of the learned proposal: rows g = 0..G-1 hold the 33 knots
-// y_0 = -1 < ... < y_32 = +1 of the piecewise-linear inverse CDF of x0 at
+// y_0 = -1 < ... < y_32 = +1 of the 32 equal-probability segments of x0 at
 // alpha_g = g * alpha_max / (G - 1).  Knots at other alpha <= alpha_max are the
 // linear mix of the two neighbouring rows (still monotone with the same ends).
 // The descriptor travels by value as a kernel argument, so its fields are at

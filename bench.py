@@ -50,10 +50,19 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_0903_3053_amd", "csrc", f)
 
 
 def kernel_hash():
+    """Hash of the pass kernel's sources and build flags with comments and
+    blank space taken out, so that a stored counter run stays valid across
+    edits of comments only."""
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(f, "rb") as fh:
-            h.update(fh.read())
+        with open(f, "r") as fh:
+            text = fh.read()
+        if f.endswith(".py"):
+            text = re.sub(r"#[^\n]*", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", re.sub(r"//[^\n]*", "", text), flags=re.S)
+        h.update(re.sub(r"\s+", " ", text).encode())
     return h.hexdigest()[:16]
 
 

@@ -13,3 +13,22 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_traffic_record_key_ignores_comments_only(tmp_path):
+    """The stored counter run is keyed by the pass sources with comments and
+    blank space removed: a comment edit keeps the key, a code edit changes it."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src = tmp_path / "k.hpp"
+    src.write_text("int f(int x) { return x + 1; }  // one\n")
+    saved = list(bench.KERNEL_SOURCES)
+    try:
+        bench.KERNEL_SOURCES[:] = [str(src)]
+        h0 = bench.kernel_hash()
+        src.write_text("/* a new\n   comment */ int f(int x)   { return x + 1; }\n// two\n")
+        assert bench.kernel_hash() == h0
+        src.write_text("int f(int x) { return x + 2; }\n")
+        assert bench.kernel_hash() != h0
+    finally:
+        bench.KERNEL_SOURCES[:] = saved

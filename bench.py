@@ -62,7 +62,7 @@ def kernel_hash():
             text = re.sub(r"#[^\n]*", "", text)
         else:
             text = re.sub(r"/\*.*?\*/", "", re.sub(r"//[^\n]*", "", text), flags=re.S)
-        h.update(re.sub(r"\s+", " ", text).encode())
+        h.update(re.sub(r"\s+", " ", text).strip().encode())
     return h.hexdigest()[:16]
 
 

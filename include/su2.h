@@ -319,6 +319,14 @@ const char *su2_mlp_last_error(void);
  * proposal to 0.  SU2_EINVAL for another kind or a wrong n_weights. */
 int su2_set_proposal(int32_t kind, const uint16_t *bf16_weights, size_t n_weights);
 
+/* Element offsets of the pass, pair and overrelaxation kernels: on = 1 forms
+ * them in 64 bits even where 32-bit ones suffice (a link array below 4 GiB,
+ * i.e. V below 2^29, where they are used by default); 0 = automatic.  The
+ * 64-bit forms are what lattices of 2^29 sites and more run; this lets a
+ * small lattice exercise them.  Results are identical either way.  su2_init
+ * resets it to 0.  SU2_EINVAL for another value, SU2_ESTATE before init. */
+int su2_set_wide_offsets(int32_t on);
+
 /* Small-alpha switch of the heat-bath (proposal 0): an update with 0 < alpha <
  * alpha_below draws x0 by Creutz's method (Phys. Rev. D 21 (1980) 2308)
  * instead of Kennedy-Pendleton's, with the same cap of 8 attempts and the same

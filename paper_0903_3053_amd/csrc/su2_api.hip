@@ -983,6 +983,17 @@ int su2_set_proposal(int32_t kind, const uint16_t *bf16_weights, size_t n_weight
     return SU2_OK;
 }
 
+int su2_set_wide_offsets(int32_t on)
+{
+    int rc = require_ready();
+    if (rc) return rc;
+    if (on != 0 && on != 1) return fail(SU2_EINVAL, "on must be 0 or 1");
+    HIP_TRY(hipStreamSynchronize(ctx.stream));
+    ctx.plan.wide = on == 1;
+    release_graphs();
+    return SU2_OK;
+}
+
 int su2_set_creutz(double alpha_below)
 {
     int rc = require_ready();

@@ -345,7 +345,7 @@ PassLaunch pass_launch(float4 *links, const Geo &g, Key key, float beta, uint32_
     pl.lds = plan.learned ? std::max(plan.lds_bytes, plan.imh_lds_bytes) : plan.lds_bytes;
     pl.order = plan.order;
     const bool measure = meas_out != nullptr && p == 0u && mu >= 1u;
-    pl.func = pass_func(mu, use_off32(g), measure, plan.learned,
+    pl.func = pass_func(mu, use_off32(g) && !plan.wide, measure, plan.learned,
                         !plan.learned && plan.imh.creutz_below > 0.0f);
     pl.imh = plan.imh;
     pl.grid = dim3(pass_blocks(g));
@@ -451,7 +451,7 @@ std::vector<PassLaunch> sweep_launches(float4 *links, const Geo &g, Key key, flo
             pl.lds = plan.learned ? std::max(plan.lds_bytes, plan.imh_lds_bytes) : plan.lds_bytes;
             pl.order = nullptr;
             const bool small = pg.n_t <= kPairLanes;
-            pl.func = pair_func(mu, use_off32(g), measure, plan.learned,
+            pl.func = pair_func(mu, use_off32(g) && !plan.wide, measure, plan.learned,
                                 !plan.learned && plan.imh.creutz_below > 0.0f, small);
             pl.imh = plan.imh;
             pl.grid = dim3(pg.n_wg);
@@ -489,7 +489,7 @@ static const void *or_func_mu(bool off32)
 PassLaunch or_launch(float4 *links, const Geo &g, uint32_t p, uint32_t mu, const PassPlan &plan)
 {
     PassLaunch pl{};
-    const bool off32 = use_off32(g);
+    const bool off32 = use_off32(g) && !plan.wide;
     pl.func = mu == 0u ? or_func_mu<0>(off32) : mu == 1u ? or_func_mu<1>(off32)
             : mu == 2u ? or_func_mu<2>(off32) : or_func_mu<3>(off32);
     pl.grid = dim3(pass_blocks(g));

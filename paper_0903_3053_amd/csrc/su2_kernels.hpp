@@ -21,6 +21,7 @@ struct PassPlan {
     bool learned = false;           // learned proposal (imh) or heat-bath only
     ImhTable imh;                   // the learned proposal's table, passed by value
     uint32_t imh_lds_bytes = 0;     // LDS the learned-proposal pass stages its table in
+    bool wide = false;              // 64-bit element offsets even where 32-bit ones suffice
 };
 
 // Arguments of one k_pass or k_pair launch, kept together so a graph node can

@@ -32,7 +32,7 @@ EXPORTS = (
     "su2_batch_sweep_index", "su2_batch_last_error", "su2_batch_finalize",
     "su2_cdf_knots", "su2_mlp_set_params", "su2_mlp_get_params", "su2_mlp_forward",
     "su2_mlp_loss_grad", "su2_mlp_train", "su2_mlp_tabulate", "su2_mlp_table", "su2_cdf_tabulate",
-    "su2_mlp_last_error", "su2_set_proposal", "su2_set_creutz", "su2_imh_counters",
+    "su2_mlp_last_error", "su2_set_proposal", "su2_set_creutz", "su2_set_wide_offsets", "su2_imh_counters",
 )
 
 
@@ -116,6 +116,7 @@ def load():
         "su2_set_proposal": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_uint16), ctypes.c_size_t],
                              ctypes.c_int),
         "su2_set_creutz": ([ctypes.c_double], ctypes.c_int),
+        "su2_set_wide_offsets": ([ctypes.c_int32], ctypes.c_int),
         "su2_imh_counters": ([u64p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -478,6 +479,11 @@ def su2_set_proposal(kind, bf16_weights=None):
 def su2_set_creutz(alpha_below=CREUTZ_SWITCH):
     """Heat-bath updates with alpha below alpha_below draw Creutz's way (0 = off)."""
     _check(load().su2_set_creutz(float(alpha_below)))
+
+
+def su2_set_wide_offsets(on=True):
+    """64-bit element offsets in the pass kernels even on a small lattice."""
+    _check(load().su2_set_wide_offsets(1 if on else 0))
 
 
 def su2_imh_counters():

@@ -139,3 +139,4 @@ def test_extension_entry_points_reject_bad_arguments(lib):
     lib.su2_finalize()
     assert lib.su2_set_proposal(1, None, 0) == su2.SU2_ESTATE
     assert lib.su2_set_creutz(ctypes.c_double(1.0)) == su2.SU2_ESTATE
+    assert lib.su2_set_wide_offsets(1) == su2.SU2_ESTATE

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import su2_inputs
-from parity import FLIP_MARGIN, UNIT_TOL, compare_links, parity_of, unitarity_error
+from parity import FLIP_MARGIN, LINK_TOL, UNIT_TOL, compare_links, parity_of, unitarity_error
 
 pytestmark = pytest.mark.gpu
 
@@ -442,6 +442,41 @@ def test_launch_plans_bit_identical(lib):
         lib.su2_set_plan(1003, 0)
     with pytest.raises(lib.Su2Error):
         lib.su2_set_plan(2000, 0)
+
+
+@pytest.mark.parametrize("dims", [(8, 6, 10, 4), (12, 12, 12, 12)])
+def test_wide_offsets_bit_identical(lib, dims):
+    """The 64-bit element offsets that lattices of 2^29 sites and more use,
+    forced on small lattices (su2_set_wide_offsets): heat-bath sweeps with
+    single passes and with fused pairs, the Creutz switch and overrelaxation
+    leave every link, counter and in-sweep plaquette bit-identical to the
+    32-bit offsets; one pass also matches the oracle."""
+    def run(wide, plan):
+        lib.su2_init(dims, 2.3, 7, lib.HOT)
+        lib.su2_set_plan(*plan)
+        if wide:
+            lib.su2_set_wide_offsets(True)
+        lib.su2_sweep(2)
+        lib.su2_set_creutz(1.0)
+        lib.su2_sweep(1)
+        lib.su2_set_creutz(0.0)
+        lib.su2_overrelax(1)
+        m = lib.su2_sweep_measure(1, 1)
+        return lib.su2_links(), lib.su2_counters(), m
+    for plan in ((0, 0), (lib.FUSED_PAIRS, 0)):
+        u0, c0, m0 = run(False, plan)
+        u1, c1, m1 = run(True, plan)
+        assert np.array_equal(u0, u1) and c0 == c1 and np.array_equal(m0, m1), plan
+    U0 = su2_inputs.random_links(dims, 12)
+    lib.su2_init(dims, 2.3, 9, lib.COLD)
+    lib.su2_set_wide_offsets(True)
+    lib.su2_set_links(U0, 3)
+    lib.su2_pass(0, 1)
+    gpu = lib.su2_links()
+    U = U0.astype(np.float64)
+    res = oracle.heatbath_pass(dims, U, 2.3, 9, 3, 0, 1)
+    flips, worst = compare_links(gpu[:, 1], U[:, 1], res.margin)
+    assert flips <= 2 and worst <= LINK_TOL
 
 
 @pytest.mark.parametrize("dims", [(8, 6, 4, 10), (8, 8, 8, 4), (16, 16, 16, 8)])

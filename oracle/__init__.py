@@ -51,6 +51,9 @@ def _load():
     lib.oracle_creutz_draw.restype = ctypes.c_int
     lib.oracle_init.argtypes = [i32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int, dp]
     lib.oracle_init.restype = ctypes.c_int
+    lib.oracle_init_sites.argtypes = [i32p, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.c_long, dp]
+    lib.oracle_init_sites.restype = ctypes.c_int
     lib.oracle_pass.argtypes = [i32p, ctypes.c_double, ctypes.c_uint64, ctypes.c_uint32,
                                 ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, dp, i8p,
                                 dp, dp, u64p]
@@ -140,6 +143,21 @@ def init(dims, seed, start, prec32=True):
     if rc:
         raise ValueError("oracle_init rejected its arguments")
     return U
+
+
+def init_sites(dims, seed, start, sites, prec32=True):
+    """The links init() gives the listed sites, float64 [n, 4, 4], without
+    forming the lattice (for lattices too large to hold)."""
+    lib = _load()
+    d = _dims(dims)
+    sites = np.ascontiguousarray(np.asarray(sites, dtype=np.int64))
+    out = np.zeros((len(sites), 4, 4))
+    rc = lib.oracle_init_sites(_ptr(d, ctypes.c_int32), ctypes.c_uint64(seed), int(start),
+                               int(bool(prec32)), _ptr(sites, ctypes.c_int64), len(sites),
+                               _ptr(out, ctypes.c_double))
+    if rc:
+        raise ValueError("oracle_init_sites rejected its arguments")
+    return out
 
 
 def _links(U):

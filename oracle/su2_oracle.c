@@ -338,23 +338,40 @@ static void store_unit(double *dst, const double q[4], int prec32)
 /* Lattice initialisation (Sec. 2.1 and Sec. 2.4): cold = identity on every   */
 /* link; hot = a Haar-random SU(2) element per link from a predefined seed.   */
 /* ------------------------------------------------------------------------- */
+static void init_link(uint64_t seed, int start, int prec32, long lex, int mu, double out[4])
+{
+    double q[4] = { 1.0, 0.0, 0.0, 0.0 };
+    if (start == 1) {
+        double u[4];
+        draw4(seed, (uint32_t)lex, mu, PURPOSE_HOT, 0u, 0u, u);
+        haar_from_uniforms(u, q);
+    }
+    store(out, q, prec32);
+}
+
 int oracle_init(const int dims[4], uint64_t seed, int start, int prec32, double *U)
 {
     geom_t g;
     if (geom_init(&g, dims)) return -1;
     if (start != 0 && start != 1) return -1;
 #pragma omp parallel for schedule(static)
-    for (long lex = 0; lex < g.V; ++lex) {
-        for (int mu = 0; mu < 4; ++mu) {
-            double q[4] = { 1.0, 0.0, 0.0, 0.0 };
-            if (start == 1) {
-                double u[4];
-                draw4(seed, (uint32_t)lex, mu, PURPOSE_HOT, 0u, 0u, u);
-                haar_from_uniforms(u, q);
-            }
-            store(U + (lex * 4 + mu) * 4, q, prec32);
-        }
-    }
+    for (long lex = 0; lex < g.V; ++lex)
+        for (int mu = 0; mu < 4; ++mu) init_link(seed, start, prec32, lex, mu, U + (lex * 4 + mu) * 4);
+    return 0;
+}
+
+/* The links oracle_init would write at the listed sites: out[(i*4 + mu)*4 ..]
+ * for sites[i], mu = 0..3 (no lattice of V sites is formed). */
+int oracle_init_sites(const int dims[4], uint64_t seed, int start, int prec32, const int64_t *sites,
+                      long n, double *out)
+{
+    geom_t g;
+    if (geom_init(&g, dims)) return -1;
+    if (start != 0 && start != 1) return -1;
+    for (long i = 0; i < n; ++i)
+        if (sites[i] < 0 || sites[i] >= g.V) return -1;
+    for (long i = 0; i < n; ++i)
+        for (int mu = 0; mu < 4; ++mu) init_link(seed, start, prec32, (long)sites[i], mu, out + (i * 4 + mu) * 4);
     return 0;
 }
 

@@ -201,6 +201,17 @@ def test_update_sites_equals_pass():
     np.testing.assert_array_equal(tries, res.tries[sites])
 
 
+def test_init_sites_equals_init():
+    dims = (4, 6, 4, 2)
+    sites = np.array([0, 1, 5, 77, 190, 191])
+    for start in (0, 1):
+        for prec32 in (True, False):
+            U = oracle.init(dims, SEED, start, prec32)
+            np.testing.assert_array_equal(oracle.init_sites(dims, SEED, start, sites, prec32), U[sites])
+    with pytest.raises(ValueError):
+        oracle.init_sites(dims, SEED, 1, [192])
+
+
 @pytest.mark.parametrize("draw", [oracle.kp_draw, oracle.creutz_draw])
 def test_fp32_mode_changes_only_the_decision(draw):
     """With FP32 link storage (the paper's, Sec. 2.4) only the accept test is

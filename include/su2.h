@@ -63,6 +63,8 @@ int su2_init(const int32_t dims[4], double beta, uint64_t seed, int32_t start);
 /* As su2_init, but the links live in a caller-owned device buffer (e.g. a
  * torch tensor) of at least 64*V bytes, 16-byte aligned; the caller keeps it
  * alive until su2_finalize or the next init.  dev_links == NULL allocates.
+ * Layout: eight arrays of V/2 float4, array 2*mu + parity; the link U_mu of
+ * site lex sits at element lex / 2 (integer division) of its parity's array.
  * (Sec. 2.1: the lattice lives in one buffer of GPU memory for the whole run.) */
 int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start,
                 void *dev_links, size_t bytes);
@@ -74,7 +76,7 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
  * own link allocation, if any, is released, and all later work reads and
  * writes the caller's buffer, which the caller keeps alive until su2_finalize
  * or the next init.  Links, sweep index and counters are unchanged.  Layout:
- * eight arrays [mu][parity] of V/2 float4 (see su2_links for the host order).
+ * as su2_init_ex (eight arrays [mu][parity] of V/2 float4).
  * (Sec. 2.1: the lattice stays in GPU memory; here in memory the caller
  * manages.)  SU2_ESTATE without a lattice; SU2_EINVAL for NULL, a short,
  * misaligned or overlapping buffer. */

@@ -1,0 +1,197 @@
+"""The largest lattices: 2^29 sites (128 x 128 x 128 x 256, 32 GiB of FP32
+links), the size from which the link arrays pass 4 GiB and the kernels take
+64-bit element offsets by themselves.  The oracle cannot form such a lattice,
+so it checks sampled links: an update it recomputes reads only the links it
+is given -- the 18 staple inputs of Eq. (6) and the link itself, gathered
+from the GPU's own field -- which sit in an FP64 field of the full size held
+in lazily mapped memory (only the pages written take host memory).
+
+Bars as in the other parity tests: hot-start links <= 1e-6; updated links
+the per-link conditioned bar, with decision flips counted; unitarity
+<= 1e-6; links a pass does not own bit-identical.
+"""
+import mmap
+
+import numpy as np
+import pytest
+
+import oracle
+from parity import UNIT_TOL, compare_links_conditioned, staple_inputs, unitarity_error
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (128, 128, 128, 256)
+V = 1 << 29
+HALF = V // 2
+BETA, SEED = 2.4, 5
+LINK_BYTES = 64 * V
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+    assert torch.cuda.is_available(), "GPU test without a GPU"
+    free, _ = torch.cuda.mem_get_info()
+    if free < LINK_BYTES + (8 << 30):
+        pytest.skip(f"needs {(LINK_BYTES >> 30) + 8} GiB of free GPU memory, {free >> 30} GiB free")
+    from paper_0903_3053_amd import su2
+    su2.load()
+    yield su2
+    su2.su2_finalize()
+
+
+@pytest.fixture(scope="module")
+def links(lib):
+    """The caller-owned device field every test of this module re-initialises."""
+    import torch
+    buf = torch.empty(16 * V, dtype=torch.float32, device="cuda")
+    yield buf
+    lib.su2_finalize()
+    del buf
+    torch.cuda.empty_cache()
+
+
+@pytest.fixture(scope="module")
+def field():
+    """float64 [V, 4, 4] of zeros in anonymous memory without huge pages."""
+    mem = mmap.mmap(-1, V * 16 * 8, flags=mmap.MAP_PRIVATE)
+    if hasattr(mmap, "MADV_NOHUGEPAGE"):
+        mem.madvise(mmap.MADV_NOHUGEPAGE)
+    yield np.frombuffer(mem, dtype=np.float64).reshape(V, 4, 4)
+
+
+def init(lib, buf, start):
+    lib.su2_init_ex(DIMS, BETA, SEED, start, buf.data_ptr(), buf.numel() * 4)
+
+
+def parity(lex):
+    lex = np.asarray(lex, dtype=np.int64)
+    L0, L1, L2 = DIMS[:3]
+    return (lex % L0 + (lex // L0) % L1 + (lex // (L0 * L1)) % L2 + lex // (L0 * L1 * L2)) % 2
+
+
+def gather(buf, lex, mu):
+    """Links U_mu(lex) (broadcast shapes) from the device field, float64
+    [..., 4]: array 2 mu + parity, element lex / 2 (the su2_init_ex layout)."""
+    import torch
+    lex, mu = np.broadcast_arrays(np.asarray(lex, dtype=np.int64), np.asarray(mu, dtype=np.int64))
+    el = (2 * mu + parity(lex)) * HALF + lex // 2
+    idx = torch.from_numpy(np.ascontiguousarray(el.ravel())).to(buf.device)
+    return buf.view(-1, 4)[idx].double().cpu().numpy().reshape(lex.shape + (4,))
+
+
+def sample_sites(rng, n, p=None):
+    """n random sites plus the corners of the lattice (first and last sites,
+    the last time slice, the end of each parity's array), all of parity p if
+    given (x0 moved by one where needed)."""
+    slab = DIMS[0] * DIMS[1] * DIMS[2]
+    lex = np.concatenate([rng.integers(0, V, size=n, dtype=np.int64),
+                          [0, 1, V - 2, V - 1, V - slab, V - slab + 3, slab - 1]])
+    if p is not None:
+        lex = np.where(parity(lex) == p, lex, lex ^ 1)
+    return np.unique(lex)
+
+
+def test_hot_start_sampled(lib, links):
+    init(lib, links, lib.HOT)
+    sites = sample_sites(np.random.default_rng(1), 600)
+    got = gather(links, sites[:, None], np.arange(4)[None, :])
+    ref = oracle.init_sites(DIMS, SEED, 1, sites)
+    assert np.max(np.abs(got - ref)) <= 1e-6
+    assert unitarity_error(got) <= UNIT_TOL
+    # Haar links: the mean of 1/2 Tr over 6 V plaquettes (each of standard
+    # deviation 1/2) and over the 2^21 Polyakov loops is 0 within about
+    # 1e-5 and 3.5e-4
+    P = lib.su2_plaquette_st()
+    L = lib.su2_polyakov()
+    print(f"2^29 sites, hot start: P = {P[0]:.2e} (P_s {P[1]:.2e}, P_t {P[2]:.2e}), L = {L:.2e}")
+    assert np.max(np.abs(P)) < 1e-4 and abs(L) < 2.5e-3
+
+
+def test_sweep_pass_by_pass_sampled(lib, links, field):
+    """Two sweeps from the hot start with the benchmark's launch plan (tile
+    order 1108, 32 KiB LDS), then each pass of the third sweep on its own:
+    sampled updated links against the oracle's update of the same inputs."""
+    init(lib, links, lib.HOT)
+    lib.su2_set_plan(1108, 32768)
+    lib.su2_sweep(2)
+    s = lib.su2_sweep_index()
+    rng = np.random.default_rng(2)
+    n_upd = flips = 0
+    worst = 0.0
+    for p in (1, 0):
+        for mu in range(4):
+            sites = sample_sites(rng, 250, p)
+            src, dirs = staple_inputs(DIMS, sites, mu)
+            all_lex = np.concatenate([src.ravel(), sites])
+            all_mu = np.concatenate([dirs.ravel(), np.full(len(sites), mu)])
+            before = gather(links, all_lex, all_mu)
+            field[all_lex, all_mu] = before
+            lib.su2_pass(p, mu)
+            after = gather(links, all_lex, all_mu)
+            owned = (all_mu == mu) & (parity(all_lex) == p)
+            assert np.array_equal(after[~owned], before[~owned]), (p, mu)
+            new = gather(links, sites, mu)
+            out, tries, margin = oracle.update_sites(DIMS, field, BETA, SEED, s, mu, sites)
+            w = np.array([oracle.staple(DIMS, field, int(x), mu) for x in sites])
+            k = np.sqrt(np.sum(w * w, axis=1))
+            x0 = np.where(tries <= 7, np.sum(out * w, axis=1) / k, np.nan)
+            st = compare_links_conditioned(new, out, margin, k, x0)
+            assert st["unexplained"] == 0, (p, mu, st)
+            assert unitarity_error(new) <= UNIT_TOL
+            n_upd += len(sites)
+            flips += st["flips"]
+            worst = max(worst, st["max_err_rest"])
+    print(f"2^29 sites, sweep {s} pass by pass: {n_upd} sampled updates, {flips} flipped "
+          f"decisions, max err {worst:.2e}")
+    assert flips <= 2
+    assert lib.su2_sweep_index() == s
+
+
+def test_overrelax_pass_sampled(lib, links, field):
+    """One overrelaxation pass: sampled links become V U^dag V (V = w/|w|)
+    from the oracle's staple of the same inputs."""
+    init(lib, links, lib.HOT)
+    lib.su2_set_plan(1108, 32768)
+    lib.su2_sweep(1)
+    p, mu = 0, 2
+    sites = sample_sites(np.random.default_rng(3), 250, p)
+    src, dirs = staple_inputs(DIMS, sites, mu)
+    all_lex = np.concatenate([src.ravel(), sites])
+    all_mu = np.concatenate([dirs.ravel(), np.full(len(sites), mu)])
+    field[all_lex, all_mu] = gather(links, all_lex, all_mu)
+    lib.su2_overrelax_pass(p, mu)
+    new = gather(links, sites, mu)
+    ref = np.zeros_like(new)
+    for i, x in enumerate(sites):
+        w = oracle.staple(DIMS, field, int(x), mu)
+        Vq = w / np.sqrt(np.sum(w * w))
+        u = field[x, mu] * np.array([1.0, -1.0, -1.0, -1.0])
+        ref[i] = oracle.qmul(oracle.qmul(Vq, u), Vq)
+    assert np.max(np.abs(new - ref)) <= 1e-5
+    assert unitarity_error(new) <= UNIT_TOL
+
+
+def test_plans_agree_at_full_size(lib, links):
+    """Two measured sweeps from the hot start with the benchmark's plan, the
+    fused pairs and the identity tile order: sampled links and the counters
+    bit-identical, the in-sweep plaquettes equal to 1e-13, and the in-sweep
+    plaquette equal to the plaquette kernel's on the same links."""
+    sites = sample_sites(np.random.default_rng(4), 4000)
+    res = []
+    for plan in ((1108, 32768), (lib.FUSED_PAIRS, 0), (0, 0)):
+        init(lib, links, lib.HOT)
+        lib.su2_set_plan(*plan)
+        hist = lib.su2_sweep_measure(2, 1)
+        fused = lib.su2_plaquette_st()
+        lib.su2_set_plan(*plan)  # discards the in-sweep partials
+        direct = lib.su2_plaquette_st()
+        assert np.max(np.abs(fused - direct)) <= 2e-6, plan
+        np.testing.assert_allclose(fused, hist[-1], rtol=0, atol=1e-13)
+        res.append((gather(links, sites[:, None], np.arange(4)[None, :]), lib.su2_counters(), hist))
+    print(f"2^29 sites, beta {BETA}: P after 2 sweeps {res[0][2][-1]}")
+    for got, counters, hist in res[1:]:
+        assert np.array_equal(got, res[0][0])
+        assert counters == res[0][1]
+        np.testing.assert_allclose(hist, res[0][2], rtol=0, atol=1e-13)
+    assert unitarity_error(res[0][0]) <= UNIT_TOL

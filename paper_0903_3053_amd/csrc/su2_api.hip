@@ -125,6 +125,10 @@ struct Context {
     hipGraphExec_t graphN = nullptr;    // kGraphSweeps sweeps
     hipGraphExec_t graphM = nullptr;    // one sweep that also measures the plaquette
     hipGraphExec_t graphOR = nullptr;   // one overrelaxation sweep
+    hipGraphExec_t graphMH = nullptr;   // kGraphSweeps measured sweeps, each reduced into d_hist
+    double *d_hist = nullptr;           // plaquette history of su2_sweep_measure (3 doubles each)
+    size_t hist_cap = 0;                // ... entries it has room for
+    uint32_t *d_cursor = nullptr;       // next history entry graphMH writes
     PassPlan plan;                      // launch plan of k_pass (tile order, LDS reservation)
     uint32_t *d_order = nullptr;        // device tile-order table of the plan
     int32_t order_kind = 0;
@@ -165,7 +169,8 @@ void release_graphs()
     if (ctx.graphN) hipGraphExecDestroy(ctx.graphN);
     if (ctx.graphM) hipGraphExecDestroy(ctx.graphM);
     if (ctx.graphOR) hipGraphExecDestroy(ctx.graphOR);
-    ctx.graph1 = ctx.graphN = ctx.graphM = ctx.graphOR = nullptr;
+    if (ctx.graphMH) hipGraphExecDestroy(ctx.graphMH);
+    ctx.graph1 = ctx.graphN = ctx.graphM = ctx.graphOR = ctx.graphMH = nullptr;
 }
 
 void release_all()
@@ -182,6 +187,8 @@ void release_all()
     if (ctx.d_table) hipFree(ctx.d_table);
     if (ctx.d_imh_stats) hipFree(ctx.d_imh_stats);
     if (ctx.d_out) hipFree(ctx.d_out);
+    if (ctx.d_hist) hipFree(ctx.d_hist);
+    if (ctx.d_cursor) hipFree(ctx.d_cursor);
     hipStream_t keep = ctx.stream;
     ctx = Context{};
     ctx.stream = keep;
@@ -220,14 +227,40 @@ Geo make_geo(const int32_t dims[4], uint64_t V)
     return g;
 }
 
-int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
+// A graph of nsweeps sweeps and one sweep-index tick.  measure_last: the last
+// sweep also sums the plaquette (its partials stay in d_meas).  measure_each:
+// every sweep does, and each is followed by the reduction of its partials
+// into the next entry of d_hist (at d_cursor).
+int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out, bool measure_each = false)
 {
+    ReduceLaunch rl;
+    if (measure_each &&
+        !measure_reduce_launch(ctx.d_meas, meas_partials(ctx.g, ctx.plan), ctx.g, ctx.d_hist,
+                               ctx.d_cursor, rl))
+        return fail(SU2_EDEVICE, "a measured sweep's partials need a two-level reduction");
     hipGraph_t graph;
     HIP_TRY(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
     int rc = SU2_OK;
+    auto add = [&](const void *func, dim3 grid, dim3 block, uint32_t lds, void **args) {
+        hipKernelNodeParams kp{};
+        kp.func = const_cast<void *>(func);
+        kp.gridDim = grid;
+        kp.blockDim = block;
+        kp.sharedMemBytes = lds;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+        if (e != hipSuccess) {
+            rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+            return false;
+        }
+        prev = node;
+        return true;
+    };
     for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
-        const bool measure = measure_last && s == nsweeps - 1;
+        const bool measure = measure_each || (measure_last && s == nsweeps - 1);
         // eight passes (Sec. 2.4: odd sites for every direction, then even
         // sites), or four fused pairs of them
         // sweep s of the graph reads sweep-index word s (= index + s)
@@ -236,21 +269,11 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
                                                      measure ? ctx.d_meas : nullptr, ctx.plan);
         for (PassLaunch &pl : pls) {
             pl.bind();
-            hipKernelNodeParams kp{};
-            kp.func = const_cast<void *>(pl.func);
-            kp.gridDim = pl.grid;
-            kp.blockDim = pl.block;
-            kp.sharedMemBytes = pl.lds;
-            kp.kernelParams = pl.args;
-            kp.extra = nullptr;
-            hipGraphNode_t node;
-            hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr,
-                                                 prev ? 1 : 0, &kp);
-            if (e != hipSuccess) {
-                rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
-                break;
-            }
-            prev = node;
+            if (!add(pl.func, pl.grid, pl.block, pl.lds, pl.args)) break;
+        }
+        if (measure_each && rc == SU2_OK) {
+            rl.bind();
+            add(rl.func, dim3(1), dim3(kBlock), 0, rl.args);
         }
     }
     // one tick after the graph's sweeps advances every sweep-index word by them
@@ -258,15 +281,7 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out)
     uint32_t nadv = (uint32_t)nsweeps;
     if (rc == SU2_OK) {
         void *targs[2] = { &sp, &nadv };
-        hipKernelNodeParams kt{};
-        kt.func = const_cast<void *>(tick_func());
-        kt.gridDim = dim3(1);
-        kt.blockDim = dim3(kWave);
-        kt.kernelParams = targs;
-        hipGraphNode_t node;
-        hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kt);
-        if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
-        prev = node;
+        add(tick_func(), dim3(1), dim3(kWave), 0, targs);
     }
     if (rc == SU2_OK) {
         hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
@@ -462,7 +477,8 @@ int su2_init_ex(const int32_t dims[4], double beta, uint64_t seed, int32_t start
         hipMalloc(&ctx.d_partials, (size_t)nb * sizeof(double2)) != hipSuccess ||
         hipMalloc(&ctx.d_meas, n_meas * sizeof(double2)) != hipSuccess ||
         hipMalloc(&ctx.d_scratch, (size_t)reduce_scratch() * sizeof(double2)) != hipSuccess ||
-        hipMalloc(&ctx.d_out, 3 * sizeof(double)) != hipSuccess) {
+        hipMalloc(&ctx.d_out, 3 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&ctx.d_cursor, sizeof(uint32_t)) != hipSuccess) {
         hipGetLastError();
         release_all();
         return fail(SU2_ENOMEM, "cannot allocate work buffers");
@@ -644,26 +660,51 @@ int su2_sweep_measure(int32_t n, int32_t every, double *host_hist)
         return fail(SU2_EINVAL, "sweep index would pass 2^32 - 1");
     const int32_t m = n / every;
     if (m == 0) return SU2_OK;
-    double *d_hist = nullptr;
-    if (hipMalloc(&d_hist, (size_t)m * 3 * sizeof(double)) != hipSuccess) {
-        hipGetLastError();
-        return fail(SU2_ENOMEM, "cannot allocate the measurement history");
+    // the history stays on the device until the end, in a buffer the context
+    // keeps (the graph below writes it in place, so it bakes in its address)
+    if (ctx.hist_cap < (size_t)m) {
+        HIP_TRY(hipStreamSynchronize(ctx.stream));
+        if (ctx.graphMH) hipGraphExecDestroy(ctx.graphMH);
+        ctx.graphMH = nullptr;
+        if (ctx.d_hist) hipFree(ctx.d_hist);
+        ctx.d_hist = nullptr;
+        ctx.hist_cap = 0;
+        const size_t cap = std::max<size_t>((size_t)m, 1024);
+        if (hipMalloc(&ctx.d_hist, cap * 3 * sizeof(double)) != hipSuccess) {
+            hipGetLastError();
+            ctx.d_hist = nullptr;
+            return fail(SU2_ENOMEM, "cannot allocate the measurement history");
+        }
+        ctx.hist_cap = cap;
     }
-    for (int32_t i = 0; i < m && rc == SU2_OK; ++i) {
+    int32_t i = 0;
+    // a measurement after every sweep: graphs of kGraphSweeps measured sweeps,
+    // each followed by the one-workgroup reduction of its partials into the
+    // next history entry (the same kernel and order as enqueue_plaquette)
+    if (every == 1 && m >= kGraphSweeps && meas_partials(ctx.g, ctx.plan) <= kReduceOneLevel) {
+        if (!ctx.graphMH) {
+            rc = build_graph(kGraphSweeps, false, &ctx.graphMH, true);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipMemsetAsync(ctx.d_cursor, 0, sizeof(uint32_t), ctx.stream));
+        for (; i + kGraphSweeps <= m; i += kGraphSweeps) HIP_TRY(hipGraphLaunch(ctx.graphMH, ctx.stream));
+        ctx.sweep += (uint64_t)i;
+        ctx.meas_fresh = true;
+    }
+    for (; i < m && rc == SU2_OK; ++i) {
         rc = run_sweeps(every, true);
         if (rc == SU2_OK) {
-            hipError_t e = enqueue_plaquette(d_hist + 3 * i);
+            hipError_t e = enqueue_plaquette(ctx.d_hist + 3 * (size_t)i);
             if (e != hipSuccess) rc = fail(SU2_EDEVICE, "plaquette launch: %s", hipGetErrorString(e));
         }
     }
     if (rc == SU2_OK) {
-        hipError_t e = hipMemcpyAsync(host_hist, d_hist, (size_t)m * 3 * sizeof(double),
+        hipError_t e = hipMemcpyAsync(host_hist, ctx.d_hist, (size_t)m * 3 * sizeof(double),
                                       hipMemcpyDeviceToHost, ctx.stream);
         if (e == hipSuccess) e = hipStreamSynchronize(ctx.stream);
         if (e != hipSuccess) rc = fail(SU2_EDEVICE, "history copy: %s", hipGetErrorString(e));
     }
     hipStreamSynchronize(ctx.stream);
-    hipFree(d_hist);
     return rc;
 }
 

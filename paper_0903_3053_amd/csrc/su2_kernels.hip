@@ -165,10 +165,14 @@ __global__ __launch_bounds__(kBlock) void k_reduce_chunks(const double2 *__restr
 
 // Final level, one workgroup: thread j sums j, j+256, ... in order, then a
 // fixed tree.  Mode 0 (plaquette): out[0] = (a*sa + b*sb)/2, out[1] = a*sa,
-// out[2] = b*sb.  Mode 1 (single value): out[0] = a*sa.
+// out[2] = b*sb.  Mode 1 (single value): out[0] = a*sa.  With a cursor the
+// results go to entry *cursor of a history (out + 3 * *cursor in mode 0) and
+// the cursor advances by one, so a graph of measured sweeps fills a history
+// in place.
 __global__ __launch_bounds__(kBlock) void k_reduce(const double2 *__restrict__ partials,
                                                    uint32_t n, double sa, double sb, int mode,
-                                                   double *__restrict__ out)
+                                                   double *__restrict__ out,
+                                                   uint32_t *__restrict__ cursor)
 {
     __shared__ double sh[2][kBlock];
     double a = 0.0, b = 0.0;
@@ -187,6 +191,10 @@ __global__ __launch_bounds__(kBlock) void k_reduce(const double2 *__restrict__ p
         __syncthreads();
     }
     if (threadIdx.x == 0) {
+        if (cursor) {
+            out += (size_t)(mode == 0 ? 3u : 1u) * *cursor;
+            *cursor += 1u;
+        }
         const double A = sh[0][0] * sa, B = sh[1][0] * sb;
         if (mode == 0) {
             out[0] = 0.5 * (A + B);
@@ -518,16 +526,44 @@ uint32_t polyakov_blocks(const Geo &g)
 uint32_t counter_waves(const Geo &g) { return blocks_for(g.half) * (kBlock / kWave); }
 uint32_t reduce_scratch() { return kBlock; }
 
-// Two-level deterministic sum of n double2 partials into out (mode as k_reduce).
+// Deterministic sum of n double2 partials into out (mode as k_reduce): one
+// workgroup straight over the partials up to kReduceOneLevel of them, else a
+// first level of up to 256 workgroups over fixed chunks and a second over their
+// results.
 static hipError_t reduce2(const double2 *partials, uint32_t n, double2 *scratch, double sa,
                           double sb, int mode, double *out, hipStream_t st)
 {
+    uint32_t *no_cursor = nullptr;
+    if (n <= kReduceOneLevel) {
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, partials, n, sa, sb, mode, out,
+                           no_cursor);
+        return hipGetLastError();
+    }
     const uint32_t nb1 = std::min<uint32_t>(kBlock, std::max<uint32_t>(1u, (n + 1023u) / 1024u));
     const uint32_t chunk = (n + nb1 - 1) / nb1;
     hipLaunchKernelGGL(k_reduce_chunks, dim3(nb1), dim3(kBlock), 0, st, partials, n, chunk,
                        scratch);
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, scratch, nb1, sa, sb, mode, out);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kBlock), 0, st, scratch, nb1, sa, sb, mode, out,
+                       no_cursor);
     return hipGetLastError();
+}
+
+static double plaquette_scale(const Geo &g) { return 1.0 / (3.0 * 2.0 * (double)g.half); }
+
+bool measure_reduce_launch(const double2 *meas_partials, uint32_t n, const Geo &g, double *hist,
+                           uint32_t *cursor, ReduceLaunch &rl)
+{
+    if (n > kReduceOneLevel) return false;
+    rl = ReduceLaunch{};
+    rl.func = reinterpret_cast<const void *>(&k_reduce);
+    rl.partials = meas_partials;
+    rl.n = n;
+    rl.sa = rl.sb = plaquette_scale(g);
+    rl.mode = 0;
+    rl.out = hist;
+    rl.cursor = cursor;
+    rl.bind();
+    return true;
 }
 
 hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials,
@@ -535,16 +571,14 @@ hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials
 {
     const uint32_t nb = plaquette_blocks(g);
     hipLaunchKernelGGL(k_plaquette, dim3(nb), dim3(kBlock), 0, st, links, g, partials);
-    const double scale = 1.0 / (3.0 * 2.0 * (double)g.half);
-    return reduce2(partials, nb, scratch, scale, scale, 0, out, st);
+    return reduce2(partials, nb, scratch, plaquette_scale(g), plaquette_scale(g), 0, out, st);
 }
 
 hipError_t launch_measure_reduce(const double2 *meas_partials, uint32_t n, const Geo &g,
                                  double2 *scratch, double *out, hipStream_t st)
 {
     // spatial planes from the mu = 1, 2 updates (x), temporal from mu = 3 (y)
-    const double scale = 1.0 / (3.0 * 2.0 * (double)g.half);
-    return reduce2(meas_partials, n, scratch, scale, scale, 0, out, st);
+    return reduce2(meas_partials, n, scratch, plaquette_scale(g), plaquette_scale(g), 0, out, st);
 }
 
 hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials,

@@ -113,6 +113,29 @@ hipError_t launch_plaquette(const float4 *links, const Geo &g, double2 *partials
                             double2 *scratch, double *out, hipStream_t st);
 hipError_t launch_measure_reduce(const double2 *meas_partials, uint32_t n, const Geo &g,
                                  double2 *scratch, double *out, hipStream_t st);
+// Partials that one workgroup reduces directly (one kernel instead of two).
+constexpr uint32_t kReduceOneLevel = 4096;
+// The reduction of a measured sweep's partials as a graph kernel node: the
+// plaquette triple goes to hist + 3 * (*cursor), and the cursor advances by
+// one.  The same kernel and order as launch_measure_reduce, so the values are
+// bit-identical.  false when n > kReduceOneLevel (two levels needed).
+struct ReduceLaunch {
+    const void *func = nullptr;
+    const double2 *partials = nullptr;
+    uint32_t n = 0;
+    double sa = 0.0, sb = 0.0;
+    int mode = 0;
+    double *out = nullptr;
+    uint32_t *cursor = nullptr;
+    void *args[7];
+    void bind()
+    {
+        void *a[7] = { &partials, &n, &sa, &sb, &mode, &out, &cursor };
+        for (int i = 0; i < 7; ++i) args[i] = a[i];
+    }
+};
+bool measure_reduce_launch(const double2 *meas_partials, uint32_t n, const Geo &g, double *hist,
+                           uint32_t *cursor, ReduceLaunch &rl);
 hipError_t launch_polyakov(const float4 *links, const Geo &g, double2 *partials,
                            double2 *scratch, double *out, hipStream_t st);
 hipError_t launch_pack(const float4 *links, const Geo &g, float4 *stage, hipStream_t st);

@@ -368,6 +368,39 @@ def test_measure_device_matches_host_calls(lib):
     assert np.all(np.isnan(out.cpu().numpy()[0]))
 
 
+@pytest.mark.parametrize("plan,learned", [((0, 0), False), ((300, 0), False), ((300, 0), True),
+                                          ((1108, 32768), False)])
+def test_measure_every_sweep_graph_equals_single_calls(lib, plan, learned):
+    """A measurement after every sweep runs as graphs of 16 measured sweeps,
+    each reducing its plaquette into the next history entry on the device:
+    the history (two calls in a row, 40 and then 21 sweeps, the remainders
+    measured one by one), the links and the counters equal those of 61 calls
+    of one measured sweep each, bit for bit."""
+    dims = (64, 64, 8, 8)  # fits tile order 1108
+    if learned:
+        lib.su2_cdf_tabulate(31)
+
+    def start():
+        lib.su2_init(dims, 2.3, 21, lib.HOT)
+        lib.su2_set_plan(*plan)
+        if learned:
+            lib.su2_set_proposal(1)
+
+    start()
+    h = np.concatenate([lib.su2_sweep_measure(40, 1), lib.su2_sweep_measure(21, 1)])
+    got = lib.su2_links(), lib.su2_counters(), lib.su2_plaquette_st()
+    start()
+    ref = np.concatenate([lib.su2_sweep_measure(1, 1) for _ in range(61)])
+    assert np.array_equal(h, ref)
+    assert np.array_equal(got[0], lib.su2_links()) and got[1] == lib.su2_counters()
+    assert np.array_equal(got[2], ref[-1])
+    assert lib.su2_sweep_index() == 61
+    # the last entry against the oracle's plaquette of the final links
+    assert np.max(np.abs(ref[-1] - oracle.plaquette(dims, got[0].astype(np.float64)))) <= 2e-6
+    if learned:
+        lib.su2_set_proposal(0)
+
+
 @pytest.mark.parametrize("dims,beta", [((8, 6, 10, 4), 2.3), ((12, 12, 12, 12), 2.5),
                                        ((4, 4, 4, 4), 0.05), ((2, 4, 2, 6), 1.0)])
 def test_fused_measurement_equals_plaquette_kernel(lib, dims, beta):

@@ -631,6 +631,34 @@ def ising_2d():
     return out
 
 
+def host_transfer(su2, V, updates, timed_ms, reps=3):
+    """The links through host memory: su2_links (device -> host) and
+    su2_set_links (host -> device, same values and sweep index, so the chain
+    is unchanged) on the benchmark's lattice, each timed over reps calls after
+    one untimed call; and the rate of a run that loads its configuration from
+    host memory, takes the timed steps and reads the result back.  Context
+    only: the bench value keeps the links resident in HBM."""
+    import numpy as np
+    s0 = su2.su2_sweep_index()
+    U = su2.su2_links()
+    t = time.perf_counter()
+    for _ in range(reps):
+        U = su2.su2_links()
+    t_out = (time.perf_counter() - t) / reps
+    su2.su2_set_links(U, s0)
+    t = time.perf_counter()
+    for _ in range(reps):
+        su2.su2_set_links(U, s0)
+    t_in = (time.perf_counter() - t) / reps
+    assert np.array_equal(su2.su2_links(), U)
+    nbytes = 64 * V
+    return {"bytes": nbytes, "links_out_ms": t_out * 1e3, "links_in_ms": t_in * 1e3,
+            "GBps_out": nbytes / t_out / 1e9, "GBps_in": nbytes / t_in / 1e9,
+            "pcie_inclusive_link_updates_per_s": updates / (timed_ms / 1e3 + t_in + t_out),
+            "note": "pageable numpy buffers through the library's staging copy; the timed steps with "
+                    "one load from and one copy back to host memory added; not the bench value"}
+
+
 EXTRAS = ("batched_replicas", "couplings_32x32x32x32", "learned_proposal", "overrelaxation",
           "strong_coupling", "ising_2d", "paper_table1")
 EXTRA_FUNCS = {"batched_replicas": batched_replicas, "couplings_32x32x32x32": couplings_32,
@@ -778,6 +806,8 @@ def main():
     }
     rec["observables"]["kp_attempts_per_update"] = (c_end[0] - c_start[0]) / updates
     rec["observables"]["kp_cap_failures_per_update"] = (c_end[1] - c_start[1]) / updates
+    if not args.no_extras:
+        rec["host_transfer"] = host_transfer(su2, V, updates, ms_per_step * args.steps)
     su2.su2_finalize()
     check = None
     if not args.no_extras:

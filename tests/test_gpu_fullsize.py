@@ -17,7 +17,7 @@ import numpy as np
 import pytest
 
 import oracle
-from parity import (FLIP_MARGIN, KAPPA_OVERRELAX, LINK_TOL, UNIT_TOL, compare_links_conditioned,
+from parity import (KAPPA_OVERRELAX, LINK_TOL, UNIT_TOL, compare_links_conditioned,
                     link_tolerance, parity_of, pass_index, staple_inputs, unitarity_error)
 
 pytestmark = pytest.mark.gpu

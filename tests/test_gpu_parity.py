@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import su2_inputs
-from parity import FLIP_MARGIN, LINK_TOL, UNIT_TOL, compare_links, parity_of, unitarity_error
+from parity import LINK_TOL, UNIT_TOL, compare_links, parity_of, unitarity_error
 
 pytestmark = pytest.mark.gpu
 

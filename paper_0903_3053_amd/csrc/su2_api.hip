@@ -121,9 +121,9 @@ struct Context {
     double *d_out = nullptr;            // 3 doubles for scalar results
     bool meas_fresh = false;            // d_meas holds the plaquette of the current links
     hipStream_t stream = nullptr;
-    hipGraphExec_t graph1 = nullptr;    // one sweep
-    hipGraphExec_t graphN = nullptr;    // kGraphSweeps sweeps
-    hipGraphExec_t graphM = nullptr;    // one sweep that also measures the plaquette
+    // graphS[m][k]: k = 1..kGraphSweeps sweeps and one sweep-index tick; with
+    // m = 1 the last of them also measures the plaquette (built on first use)
+    hipGraphExec_t graphS[2][kGraphSweeps + 1] = {};
     hipGraphExec_t graphOR = nullptr;   // one overrelaxation sweep
     hipGraphExec_t graphMH = nullptr;   // kGraphSweeps measured sweeps, each reduced into d_hist
     double *d_hist = nullptr;           // plaquette history of su2_sweep_measure (3 doubles each)
@@ -165,12 +165,14 @@ int fail(int code, const char *fmt, ...)
 
 void release_graphs()
 {
-    if (ctx.graph1) hipGraphExecDestroy(ctx.graph1);
-    if (ctx.graphN) hipGraphExecDestroy(ctx.graphN);
-    if (ctx.graphM) hipGraphExecDestroy(ctx.graphM);
+    for (auto &row : ctx.graphS)
+        for (hipGraphExec_t &gr : row) {
+            if (gr) hipGraphExecDestroy(gr);
+            gr = nullptr;
+        }
     if (ctx.graphOR) hipGraphExecDestroy(ctx.graphOR);
     if (ctx.graphMH) hipGraphExecDestroy(ctx.graphMH);
-    ctx.graph1 = ctx.graphN = ctx.graphM = ctx.graphOR = ctx.graphMH = nullptr;
+    ctx.graphOR = ctx.graphMH = nullptr;
 }
 
 void release_all()
@@ -384,25 +386,27 @@ int require_ready()
 int run_sweeps(int32_t n, bool measured = false)
 {
     if (n <= 0) return SU2_OK;
-    if (!ctx.graph1) {
-        int rc = build_graph(1, false, &ctx.graph1);
+    auto graph = [](int m, int32_t k, hipGraphExec_t **out) {
+        hipGraphExec_t &gr = ctx.graphS[m][k];
+        int rc = gr ? SU2_OK : build_graph(k, m == 1, &gr);
+        *out = &gr;
+        return rc;
+    };
+    // whole graphs of kGraphSweeps plain sweeps, then one graph for the rest
+    // (its last sweep measured when asked): one launch and one tick per graph
+    int32_t left = n;
+    hipGraphExec_t *gr = nullptr;
+    while (left > kGraphSweeps || (left == kGraphSweeps && !measured)) {
+        int rc = graph(0, kGraphSweeps, &gr);
         if (rc) return rc;
-    }
-    if (measured && !ctx.graphM) {
-        int rc = build_graph(1, true, &ctx.graphM);
-        if (rc) return rc;
-    }
-    int32_t left = measured ? n - 1 : n;
-    if (left >= kGraphSweeps && !ctx.graphN) {
-        int rc = build_graph(kGraphSweeps, false, &ctx.graphN);
-        if (rc) return rc;
-    }
-    while (left >= kGraphSweeps) {
-        HIP_TRY(hipGraphLaunch(ctx.graphN, ctx.stream));
+        HIP_TRY(hipGraphLaunch(*gr, ctx.stream));
         left -= kGraphSweeps;
     }
-    while (left-- > 0) HIP_TRY(hipGraphLaunch(ctx.graph1, ctx.stream));
-    if (measured) HIP_TRY(hipGraphLaunch(ctx.graphM, ctx.stream));
+    if (left > 0) {
+        int rc = graph(measured ? 1 : 0, left, &gr);
+        if (rc) return rc;
+        HIP_TRY(hipGraphLaunch(*gr, ctx.stream));
+    }
     ctx.sweep += (uint64_t)n;
     ctx.meas_fresh = measured;
     return SU2_OK;

@@ -279,18 +279,30 @@ def test_resume_is_bit_identical(lib):
 
 
 def test_graph_replay_matches_single_sweeps(lib):
-    """n >= 16 sweeps use the 16-sweep graph; the result must equal 1-sweep replays."""
+    """A run of n sweeps replays graphs of 16 sweeps and one graph of the
+    rest (its last sweep measured, for su2_sweep_measured); links, counters
+    and the measured plaquette equal those of 1-sweep replays."""
     dims, beta, seed = (6, 4, 8, 12), 2.2, 8
     lib.su2_init(dims, beta, seed, lib.HOT)
-    lib.su2_sweep(19)
-    a = lib.su2_links()
-    lib.su2_init(dims, beta, seed, lib.HOT)
-    for _ in range(19):
+    for _ in range(55):
         lib.su2_sweep(1)
-    assert np.array_equal(lib.su2_links(), a)
+    ref, c_ref = lib.su2_links(), lib.su2_counters()
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    for n in (2, 5, 15, 16, 17):  # 55 sweeps
+        lib.su2_sweep(n)
+    assert np.array_equal(lib.su2_links(), ref) and lib.su2_counters() == c_ref
+    for n in (1, 5, 16, 21):
+        lib.su2_init(dims, beta, seed, lib.HOT)
+        lib.su2_sweep(n - 1)
+        lib.su2_sweep_measured(1)
+        one = lib.su2_plaquette_st(), lib.su2_links()
+        lib.su2_init(dims, beta, seed, lib.HOT)
+        lib.su2_sweep_measured(n)
+        assert np.array_equal(lib.su2_plaquette_st(), one[0]) and np.array_equal(lib.su2_links(), one[1]), n
+        assert lib.su2_sweep_index() == n
     hist = lib.su2_sweep_measure(4, 2)
     assert hist.shape == (2, 3)
-    assert lib.su2_sweep_index() == 23
+    assert lib.su2_sweep_index() == 25
 
 
 def test_torch_stream_and_memory(lib):

@@ -253,9 +253,14 @@ __global__ __launch_bounds__(kIsingBlock) void k_ising_unpack_bits(uint32_t *__r
     P[w] = bits;
 }
 
-__global__ void k_ising_tick(uint32_t *sweep_ptr)
+// The sweep index lives in kIsingSweepSlots consecutive words, word j holding
+// index + j: sweep j of a graph of several sweeps reads word j, and one tick
+// at the end of the graph advances all of them by the graph's sweeps.
+constexpr uint32_t kIsingSweepSlots = 32;
+
+__global__ void k_ising_tick(uint32_t *sweep_ptr, uint32_t n)
 {
-    if (threadIdx.x == 0) *sweep_ptr += 1u;
+    if (threadIdx.x < kIsingSweepSlots) sweep_ptr[threadIdx.x] += n;
 }
 
 // Exact integer sums over all sites: bonds to the +x and +y neighbours, spins.
@@ -309,7 +314,7 @@ __global__ __launch_bounds__(kIsingBlock) void k_ising_unpack(int8_t *__restrict
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-constexpr int kIsingGraphSweeps = 32;
+constexpr int kIsingGraphSweeps = (int)kIsingSweepSlots;
 
 struct IsingCtx {
     bool ready = false;
@@ -324,7 +329,8 @@ struct IsingCtx {
     unsigned long long *d_acc = nullptr;   // accepted flips, kAccSlots partial counts
     unsigned long long *d_sums = nullptr;  // observables, kAccSlots (bonds, spins) partial sums
     uint64_t sweep = 0;
-    hipGraphExec_t graph1 = nullptr, graphN = nullptr;
+    // graphS[k]: k = 1..kIsingGraphSweeps sweeps and one tick (built on first use)
+    hipGraphExec_t graphS[kIsingGraphSweeps + 1] = {};
 };
 
 IsingCtx I;
@@ -349,12 +355,20 @@ int ifail(int code, const char *fmt, ...)
 void ising_release()
 {
     if (I.ready) hipDeviceSynchronize();
-    if (I.graph1) hipGraphExecDestroy(I.graph1);
-    if (I.graphN) hipGraphExecDestroy(I.graphN);
+    for (hipGraphExec_t gr : I.graphS)
+        if (gr) hipGraphExecDestroy(gr);
     void *ptrs[] = { I.S, I.P, I.d_sweep, I.d_acc, I.d_sums };
     for (void *p : ptrs)
         if (p) hipFree(p);
     I = IsingCtx{};
+}
+
+// Sets the device sweep-index words to index + j.
+hipError_t write_sweep_words(uint32_t index)
+{
+    uint32_t w[kIsingSweepSlots];
+    for (uint32_t j = 0; j < kIsingSweepSlots; ++j) w[j] = index + j;
+    return hipMemcpy(I.d_sweep, w, sizeof w, hipMemcpyHostToDevice);
 }
 
 uint32_t groups() { return (I.g.half + 3u) / 4u; }
@@ -370,8 +384,8 @@ int build_sweep_graph(int nsweeps, hipGraphExec_t *out)
     uint32_t *P = I.P;
     IsingGeo g = I.g;
     Key key = I.key;
-    const uint32_t *sp = I.d_sweep;
     uint32_t *spw = I.d_sweep;
+    uint32_t nadv = (uint32_t)nsweeps;
     uint32_t T4 = I.T4, T8 = I.T8;
     unsigned long long *acc = I.d_acc;
     uint32_t colours[2] = { 0u, 1u };
@@ -379,7 +393,7 @@ int build_sweep_graph(int nsweeps, hipGraphExec_t *out)
         hipKernelNodeParams kp{};
         kp.func = const_cast<void *>(func);
         kp.gridDim = grid;
-        kp.blockDim = dim3(func == reinterpret_cast<const void *>(&k_ising_tick) ? 1 : kIsingBlock);
+        kp.blockDim = dim3(func == reinterpret_cast<const void *>(&k_ising_tick) ? 64 : kIsingBlock);
         kp.sharedMemBytes = 0;
         kp.kernelParams = args;
         hipGraphNode_t node;
@@ -389,6 +403,7 @@ int build_sweep_graph(int nsweeps, hipGraphExec_t *out)
         return (int)SU2_OK;
     };
     for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
+        const uint32_t *sp = I.d_sweep + s;  // sweep s of the graph reads word s (= index + s)
         for (int c = 0; c < 2 && rc == SU2_OK; ++c) {
             if (I.bits) {
                 void *args[] = { &P, &g, &key, &colours[c], &sp, &T4, &T8, &acc };
@@ -398,10 +413,11 @@ int build_sweep_graph(int nsweeps, hipGraphExec_t *out)
                 rc = add(reinterpret_cast<const void *>(&k_ising_pass), dim3(blocks_of(groups())), args);
             }
         }
-        if (rc == SU2_OK) {
-            void *targs[] = { &spw };
-            rc = add(reinterpret_cast<const void *>(&k_ising_tick), dim3(1), targs);
-        }
+    }
+    // one tick after the graph's sweeps advances every sweep-index word by them
+    if (rc == SU2_OK) {
+        void *targs[] = { &spw, &nadv };
+        rc = add(reinterpret_cast<const void *>(&k_ising_tick), dim3(1), targs);
     }
     if (rc == SU2_OK) {
         hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
@@ -454,7 +470,7 @@ int ising_init_ex(const int32_t dims[2], double beta, uint64_t seed, int32_t sta
     I.T4 = (uint32_t)std::floor(std::exp(-4.0 * beta) * 16777216.0);
     I.T8 = (uint32_t)std::floor(std::exp(-8.0 * beta) * 16777216.0);
     const hipError_t ea = I.bits ? hipMalloc(&I.P, (size_t)N / 8) : hipMalloc(&I.S, (size_t)N);
-    if (ea != hipSuccess || hipMalloc(&I.d_sweep, sizeof(uint32_t)) != hipSuccess ||
+    if (ea != hipSuccess || hipMalloc(&I.d_sweep, kIsingSweepSlots * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&I.d_acc, kAccSlots * sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc(&I.d_sums, 2 * kAccSlots * sizeof(unsigned long long)) != hipSuccess) {
         hipGetLastError();
@@ -462,7 +478,7 @@ int ising_init_ex(const int32_t dims[2], double beta, uint64_t seed, int32_t sta
         return ifail(SU2_ENOMEM, "cannot allocate the Ising lattice");
     }
     I.ready = true;
-    ITRY(hipMemset(I.d_sweep, 0, sizeof(uint32_t)));
+    ITRY(write_sweep_words(0u));
     ITRY(hipMemset(I.d_acc, 0, kAccSlots * sizeof(unsigned long long)));
     if (I.bits)
         hipLaunchKernelGGL(k_ising_init_bits, dim3(blocks_of(I.g.nw), 2), dim3(kIsingBlock), 0, nullptr, I.P, I.g,
@@ -495,20 +511,16 @@ int ising_sweep(int32_t n)
     if (rc) return rc;
     if (n < 0) return ifail(SU2_EINVAL, "n must be >= 0");
     if (I.sweep + (uint64_t)n > 0xffffffffull) return ifail(SU2_EINVAL, "sweep index would pass 2^32 - 1");
-    int32_t left = n;
-    if (left >= kIsingGraphSweeps && !I.graphN) {
-        rc = build_sweep_graph(kIsingGraphSweeps, &I.graphN);
-        if (rc) return rc;
+    // graphs of kIsingGraphSweeps sweeps, then one graph for the rest
+    for (int32_t left = n; left > 0;) {
+        const int32_t k = std::min<int32_t>(left, kIsingGraphSweeps);
+        if (!I.graphS[k]) {
+            rc = build_sweep_graph(k, &I.graphS[k]);
+            if (rc) return rc;
+        }
+        ITRY(hipGraphLaunch(I.graphS[k], nullptr));
+        left -= k;
     }
-    while (left >= kIsingGraphSweeps) {
-        ITRY(hipGraphLaunch(I.graphN, nullptr));
-        left -= kIsingGraphSweeps;
-    }
-    if (left > 0 && !I.graph1) {
-        rc = build_sweep_graph(1, &I.graph1);
-        if (rc) return rc;
-    }
-    while (left-- > 0) ITRY(hipGraphLaunch(I.graph1, nullptr));
     I.sweep += (uint64_t)n;
     return SU2_OK;
 }
@@ -585,8 +597,7 @@ int ising_set_spins(const int8_t *host_in, size_t n, uint64_t sweep_index)
     if (e == hipSuccess) e = hipDeviceSynchronize();
     hipFree(stage);
     if (e != hipSuccess) return ifail(SU2_EDEVICE, "ising_set_spins: %s", hipGetErrorString(e));
-    const uint32_t s32 = (uint32_t)sweep_index;
-    ITRY(hipMemcpy(I.d_sweep, &s32, sizeof s32, hipMemcpyHostToDevice));
+    ITRY(write_sweep_words((uint32_t)sweep_index));
     I.sweep = sweep_index;
     return SU2_OK;
 }

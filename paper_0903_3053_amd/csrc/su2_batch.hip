@@ -119,9 +119,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_pass(BatchDev b, uint32_t p,
     }
 }
 
+// The sweep index lives in kBatchSweepSlots consecutive words, word j holding
+// index + j: sweep j of a grouped graph of several sweeps reads word j, the
+// persistent kernel word 0, and one tick per graph advances them all.
+constexpr uint32_t kBatchSweepSlots = 16;
+
 __global__ void k_batch_tick(uint32_t *sweep_ptr, uint32_t n)
 {
-    if (threadIdx.x == 0) *sweep_ptr += n;
+    if (threadIdx.x < kBatchSweepSlots) sweep_ptr[threadIdx.x] += n;
 }
 
 // Zero the persistent kernel's completion counters, queues and error flag (a
@@ -364,7 +369,7 @@ struct Batch {
     uint32_t grid_persistent = 0;
     unsigned long long spin_limit = 0;
     uint32_t per_pass = 0;
-    hipGraphExec_t graph = nullptr;     // grouped: one sweep
+    hipGraphExec_t graphS[kBatchSweepSlots + 1] = {};  // grouped: graphS[k] runs k sweeps
     hipGraphExec_t pgraph = nullptr;    // persistent: reset + kernel + tick for pgraph_n sweeps
     int32_t pgraph_n = 0;
 };
@@ -388,11 +393,22 @@ int bfail(int code, const char *fmt, ...)
             return bfail(SU2_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));    \
     } while (0)
 
+// Sets the device sweep-index words to index + j.
+hipError_t write_sweep_words(uint32_t index)
+{
+    uint32_t w[kBatchSweepSlots];
+    for (uint32_t j = 0; j < kBatchSweepSlots; ++j) w[j] = index + j;
+    return hipMemcpy(B.d_sweep, w, sizeof w, hipMemcpyHostToDevice);
+}
+
 void drop_graphs()
 {
-    if (B.graph) hipGraphExecDestroy(B.graph);
+    for (hipGraphExec_t &gr : B.graphS) {
+        if (gr) hipGraphExecDestroy(gr);
+        gr = nullptr;
+    }
     if (B.pgraph) hipGraphExecDestroy(B.pgraph);
-    B.graph = B.pgraph = nullptr;
+    B.pgraph = nullptr;
     B.pgraph_n = 0;
 }
 
@@ -512,14 +528,14 @@ int add_node(hipGraph_t g, hipGraphNode_t *prev, const void *func, dim3 grid, di
     return SU2_OK;
 }
 
-int build_grouped_graph()
+// nsweeps sweeps of eight grouped pass launches each, then one tick.
+int build_grouped_graph(int nsweeps, hipGraphExec_t *out)
 {
     hipGraph_t g;
     BTRY(hipGraphCreate(&g, 0));
     hipGraphNode_t prev = nullptr;
     int rc = SU2_OK;
     BatchDev d = dev();
-    const uint32_t *sp = B.d_sweep;
     uint32_t k = B.k;
     uint32_t chunk = (B.per_pass + 7u) / 8u, total = B.per_pass;
     const uint32_t *ir = B.d_item_rep;
@@ -528,19 +544,22 @@ int build_grouped_graph()
                                reinterpret_cast<const void *>(&k_batch_pass<2>),
                                reinterpret_cast<const void *>(&k_batch_pass<3>) };
     uint32_t pp[8];
-    for (int i = 0; i < 8 && rc == SU2_OK; ++i) {
-        pp[i] = i < 4 ? 1u : 0u;  // odd sites first (Sec. 2.4), mu = 0..3
-        void *args[] = { &d, &pp[i], &sp, &k, &chunk, &total, &ir };
-        rc = add_node(g, &prev, pass_fn[i & 3], dim3(8u * chunk), dim3(kBlock), B.lds, args);
+    for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
+        const uint32_t *sp = B.d_sweep + s;  // sweep s of the graph reads word s (= index + s)
+        for (int i = 0; i < 8 && rc == SU2_OK; ++i) {
+            pp[i] = i < 4 ? 1u : 0u;  // odd sites first (Sec. 2.4), mu = 0..3
+            void *args[] = { &d, &pp[i], &sp, &k, &chunk, &total, &ir };
+            rc = add_node(g, &prev, pass_fn[i & 3], dim3(8u * chunk), dim3(kBlock), B.lds, args);
+        }
     }
-    uint32_t one = 1;
+    uint32_t nadv = (uint32_t)nsweeps;
     uint32_t *spw = B.d_sweep;
     if (rc == SU2_OK) {
-        void *args[] = { &spw, &one };
-        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_tick), dim3(1), dim3(1), 0, args);
+        void *args[] = { &spw, &nadv };
+        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_tick), dim3(1), dim3(64), 0, args);
     }
     if (rc == SU2_OK) {
-        hipError_t e = hipGraphInstantiate(&B.graph, g, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
         if (e != hipSuccess) rc = bfail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
     }
     hipGraphDestroy(g);
@@ -577,7 +596,7 @@ int build_persistent_graph(int32_t n)
     uint32_t *spw = B.d_sweep;
     if (rc == SU2_OK) {
         void *a2[] = { &spw, &ns };
-        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_tick), dim3(1), dim3(1), 0, a2);
+        rc = add_node(g, &prev, reinterpret_cast<const void *>(&k_batch_tick), dim3(1), dim3(64), 0, a2);
     }
     if (rc == SU2_OK) {
         hipError_t e = hipGraphInstantiate(&B.pgraph, g, nullptr, nullptr, 0);
@@ -644,11 +663,16 @@ int run_batch(int32_t n, bool check = true)
 {
     if (n <= 0) return SU2_OK;
     if (B.mode == 0) {
-        if (!B.graph) {
-            int rc = build_grouped_graph();
-            if (rc) return rc;
+        // graphs of kBatchSweepSlots sweeps, then one graph for the rest
+        for (int32_t left = n; left > 0;) {
+            const int32_t m = std::min<int32_t>(left, (int32_t)kBatchSweepSlots);
+            if (!B.graphS[m]) {
+                int rc = build_grouped_graph(m, &B.graphS[m]);
+                if (rc) return rc;
+            }
+            BTRY(hipGraphLaunch(B.graphS[m], nullptr));
+            left -= m;
         }
-        for (int32_t i = 0; i < n; ++i) BTRY(hipGraphLaunch(B.graph, nullptr));
     } else {
         // the item counters of one launch (items plus one last take per
         // workgroup) must stay below 2^32
@@ -738,7 +762,7 @@ int su2_batch_init(int32_t n, const int32_t *dims, const double *betas, const ui
         hipMalloc(&B.d_site_prefix, site_prefix.size() * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&B.links, off * sizeof(float4)) != hipSuccess ||
         hipMalloc(&B.counters, coff * sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc(&B.d_sweep, sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&B.d_sweep, kBatchSweepSlots * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&B.d_done, reps.size() * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc(&B.d_next, kMaxXcd * sizeof(unsigned int)) != hipSuccess ||
         hipMalloc(&B.d_err, sizeof(unsigned int)) != hipSuccess ||
@@ -754,7 +778,7 @@ int su2_batch_init(int32_t n, const int32_t *dims, const double *betas, const ui
     BTRY(hipMemcpy(B.d_site_prefix, site_prefix.data(), site_prefix.size() * sizeof(uint32_t),
                    hipMemcpyHostToDevice));
     BTRY(hipMemset(B.counters, 0, coff * sizeof(unsigned long long)));
-    BTRY(hipMemset(B.d_sweep, 0, sizeof(uint32_t)));
+    BTRY(write_sweep_words(0u));
     BTRY(hipMemset(B.d_err, 0, sizeof(unsigned int)));
     int rc = set_items(1);
     if (rc) return rc;
@@ -859,8 +883,7 @@ int su2_batch_tune(int32_t sweeps, int32_t out[3])
     }
     BTRY(hipMemcpy(B.links, save_l, B.link_floats4 * sizeof(float4), hipMemcpyDeviceToDevice));
     BTRY(hipMemcpy(B.counters, save_c, B.n_counters * sizeof(unsigned long long), hipMemcpyDeviceToDevice));
-    const uint32_t s32 = (uint32_t)sweep0;
-    BTRY(hipMemcpy(B.d_sweep, &s32, sizeof s32, hipMemcpyHostToDevice));
+    BTRY(write_sweep_words((uint32_t)sweep0));
     B.sweep = sweep0;
     hipFree(save_l);
     hipFree(save_c);

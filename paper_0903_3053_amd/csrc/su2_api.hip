@@ -124,7 +124,7 @@ struct Context {
     // graphS[m][k]: k = 1..kGraphSweeps sweeps and one sweep-index tick; with
     // m = 1 the last of them also measures the plaquette (built on first use)
     hipGraphExec_t graphS[2][kGraphSweeps + 1] = {};
-    hipGraphExec_t graphOR = nullptr;   // one overrelaxation sweep
+    hipGraphExec_t graphOR[kGraphSweeps + 1] = {};  // graphOR[k]: k overrelaxation sweeps
     hipGraphExec_t graphMH = nullptr;   // kGraphSweeps measured sweeps, each reduced into d_hist
     double *d_hist = nullptr;           // plaquette history of su2_sweep_measure (3 doubles each)
     size_t hist_cap = 0;                // ... entries it has room for
@@ -170,9 +170,12 @@ void release_graphs()
             if (gr) hipGraphExecDestroy(gr);
             gr = nullptr;
         }
-    if (ctx.graphOR) hipGraphExecDestroy(ctx.graphOR);
+    for (hipGraphExec_t &gr : ctx.graphOR) {
+        if (gr) hipGraphExecDestroy(gr);
+        gr = nullptr;
+    }
     if (ctx.graphMH) hipGraphExecDestroy(ctx.graphMH);
-    ctx.graphOR = ctx.graphMH = nullptr;
+    ctx.graphMH = nullptr;
 }
 
 void release_all()
@@ -293,34 +296,38 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out, bool measur
     return rc;
 }
 
-// One overrelaxation sweep (the eight passes in the heat-bath sweep's order)
-// as a graph; no sweep-index tick (it draws no random numbers).
-int build_or_graph(hipGraphExec_t *out)
+// nsweeps overrelaxation sweeps (the eight passes each in the heat-bath
+// sweep's order) as a graph; no sweep-index tick (they draw no random numbers).
+int build_or_graph(int nsweeps, hipGraphExec_t *out)
 {
     hipGraph_t graph;
     HIP_TRY(hipGraphCreate(&graph, 0));
     hipGraphNode_t prev = nullptr;
     int rc = SU2_OK;
-    for (int p = 1; p >= 0 && rc == SU2_OK; --p)
-        for (uint32_t mu = 0; mu < 4 && rc == SU2_OK; ++mu) {
-            PassLaunch pl = or_launch(ctx.links, ctx.g, (uint32_t)p, mu, ctx.plan);
-            // as in the heat-bath sweep: odd passes walk the tile order backwards
-            if (ctx.plan.alternate && !ctx.plan.fused && (mu & 1u)) {
-                pl.order = ctx.plan.order + pass_blocks(ctx.g);
-                pl.bind();
+    for (int s = 0; s < nsweeps && rc == SU2_OK; ++s)
+        for (int p = 1; p >= 0 && rc == SU2_OK; --p)
+            for (uint32_t mu = 0; mu < 4 && rc == SU2_OK; ++mu) {
+                PassLaunch pl = or_launch(ctx.links, ctx.g, (uint32_t)p, mu, ctx.plan);
+                // as in the heat-bath sweep: odd passes walk the tile order backwards
+                if (ctx.plan.alternate && !ctx.plan.fused && (mu & 1u)) {
+                    pl.order = ctx.plan.order + pass_blocks(ctx.g);
+                    pl.bind();
+                }
+                hipKernelNodeParams kp{};
+                kp.func = const_cast<void *>(pl.func);
+                kp.gridDim = pl.grid;
+                kp.blockDim = pl.block;
+                kp.sharedMemBytes = pl.lds;
+                kp.kernelParams = pl.args;
+                kp.extra = nullptr;
+                hipGraphNode_t node;
+                hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                                     &kp);
+                if (e != hipSuccess)
+                    rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
+                else
+                    prev = node;
             }
-            hipKernelNodeParams kp{};
-            kp.func = const_cast<void *>(pl.func);
-            kp.gridDim = pl.grid;
-            kp.blockDim = pl.block;
-            kp.sharedMemBytes = pl.lds;
-            kp.kernelParams = pl.args;
-            kp.extra = nullptr;
-            hipGraphNode_t node;
-            hipError_t e = hipGraphAddKernelNode(&node, graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
-            if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphAddKernelNode: %s", hipGetErrorString(e));
-            else prev = node;
-        }
     if (rc == SU2_OK) {
         hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
         if (e != hipSuccess) rc = fail(SU2_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
@@ -542,11 +549,16 @@ int su2_overrelax(int32_t n)
     if (rc) return rc;
     if (n < 0) return fail(SU2_EINVAL, "n must be >= 0");
     if (n == 0) return SU2_OK;
-    if (!ctx.graphOR) {
-        rc = build_or_graph(&ctx.graphOR);
-        if (rc) return rc;
+    // graphs of kGraphSweeps sweeps, then one graph for the rest
+    for (int32_t left = n; left > 0;) {
+        const int32_t k = std::min<int32_t>(left, kGraphSweeps);
+        if (!ctx.graphOR[k]) {
+            rc = build_or_graph(k, &ctx.graphOR[k]);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipGraphLaunch(ctx.graphOR[k], ctx.stream));
+        left -= k;
     }
-    for (int32_t i = 0; i < n; ++i) HIP_TRY(hipGraphLaunch(ctx.graphOR, ctx.stream));
     ctx.meas_fresh = false;
     return SU2_OK;
 }

@@ -64,6 +64,22 @@ def test_overrelax_conserves_plaquette_and_undoes_itself(lib):
     assert float(np.max(np.abs(lib.su2_links() - U0))) <= 1e-6
 
 
+def test_overrelax_graphs_equal_single_sweeps(lib):
+    """Runs of overrelaxation sweeps replay graphs of up to 16 sweeps; the
+    links equal those of one-sweep calls, bit for bit."""
+    dims = (8, 6, 10, 4)
+    lib.su2_init(dims, 2.3, 9, lib.HOT)
+    lib.su2_sweep(2)
+    for _ in range(22):
+        lib.su2_overrelax(1)
+    ref = lib.su2_links()
+    lib.su2_init(dims, 2.3, 9, lib.HOT)
+    lib.su2_sweep(2)
+    lib.su2_overrelax(3)
+    lib.su2_overrelax(19)
+    assert np.array_equal(lib.su2_links(), ref)
+
+
 def test_overrelax_same_for_every_plan(lib):
     dims = (64, 64, 8, 8)
     ref = None

@@ -168,10 +168,10 @@ int su2_measure_device(double *dev_out);
  * device history that is copied once, at the end, to host_hist
  * [n / every][3] (Sec. 2.4: averages stay on the GPU until the run ends).
  * every >= 1; n must be a multiple of every.  The history buffer stays with
- * the lattice (grown as needed, SU2_ENOMEM if it cannot be); with every = 1
- * the sweeps run as graphs of 16 measured sweeps that each reduce into the
- * next history entry, with the same values as one call per sweep.
- * Synchronises. */
+ * the lattice (grown as needed, SU2_ENOMEM if it cannot be); with every <= 16
+ * the sweeps run as graphs of 16 / every measurements, each measured sweep
+ * reducing into the next history entry, with the same values as one call
+ * per measurement.  Synchronises. */
 int su2_sweep_measure(int32_t n, int32_t every, double *host_hist);
 
 /* Copy the links to host_out (float32 [V][4][4], caller-owned); n_floats must

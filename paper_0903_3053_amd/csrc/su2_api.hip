@@ -125,7 +125,9 @@ struct Context {
     // m = 1 the last of them also measures the plaquette (built on first use)
     hipGraphExec_t graphS[2][kGraphSweeps + 1] = {};
     hipGraphExec_t graphOR[kGraphSweeps + 1] = {};  // graphOR[k]: k overrelaxation sweeps
-    hipGraphExec_t graphMH = nullptr;   // kGraphSweeps measured sweeps, each reduced into d_hist
+    // graphMH[e]: kGraphSweeps / e measurements e sweeps apart, each reduced
+    // into the next entry of d_hist (built on first use)
+    hipGraphExec_t graphMH[kGraphSweeps + 1] = {};
     double *d_hist = nullptr;           // plaquette history of su2_sweep_measure (3 doubles each)
     size_t hist_cap = 0;                // ... entries it has room for
     uint32_t *d_cursor = nullptr;       // next history entry graphMH writes
@@ -174,8 +176,10 @@ void release_graphs()
         if (gr) hipGraphExecDestroy(gr);
         gr = nullptr;
     }
-    if (ctx.graphMH) hipGraphExecDestroy(ctx.graphMH);
-    ctx.graphMH = nullptr;
+    for (hipGraphExec_t &gr : ctx.graphMH) {
+        if (gr) hipGraphExecDestroy(gr);
+        gr = nullptr;
+    }
 }
 
 void release_all()
@@ -233,13 +237,13 @@ Geo make_geo(const int32_t dims[4], uint64_t V)
 }
 
 // A graph of nsweeps sweeps and one sweep-index tick.  measure_last: the last
-// sweep also sums the plaquette (its partials stay in d_meas).  measure_each:
-// every sweep does, and each is followed by the reduction of its partials
-// into the next entry of d_hist (at d_cursor).
-int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out, bool measure_each = false)
+// sweep also sums the plaquette (its partials stay in d_meas).  measure_every
+// = e > 0: sweeps e, 2e, ... do, and each is followed by the reduction of its
+// partials into the next entry of d_hist (at d_cursor).
+int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out, int measure_every = 0)
 {
     ReduceLaunch rl;
-    if (measure_each &&
+    if (measure_every > 0 &&
         !measure_reduce_launch(ctx.d_meas, meas_partials(ctx.g, ctx.plan), ctx.g, ctx.d_hist,
                                ctx.d_cursor, rl))
         return fail(SU2_EDEVICE, "a measured sweep's partials need a two-level reduction");
@@ -265,7 +269,8 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out, bool measur
         return true;
     };
     for (int s = 0; s < nsweeps && rc == SU2_OK; ++s) {
-        const bool measure = measure_each || (measure_last && s == nsweeps - 1);
+        const bool hist = measure_every > 0 && (s + 1) % measure_every == 0;
+        const bool measure = hist || (measure_last && s == nsweeps - 1);
         // eight passes (Sec. 2.4: odd sites for every direction, then even
         // sites), or four fused pairs of them
         // sweep s of the graph reads sweep-index word s (= index + s)
@@ -276,7 +281,7 @@ int build_graph(int nsweeps, bool measure_last, hipGraphExec_t *out, bool measur
             pl.bind();
             if (!add(pl.func, pl.grid, pl.block, pl.lds, pl.args)) break;
         }
-        if (measure_each && rc == SU2_OK) {
+        if (hist && rc == SU2_OK) {
             rl.bind();
             add(rl.func, dim3(1), dim3(kBlock), 0, rl.args);
         }
@@ -680,8 +685,10 @@ int su2_sweep_measure(int32_t n, int32_t every, double *host_hist)
     // keeps (the graph below writes it in place, so it bakes in its address)
     if (ctx.hist_cap < (size_t)m) {
         HIP_TRY(hipStreamSynchronize(ctx.stream));
-        if (ctx.graphMH) hipGraphExecDestroy(ctx.graphMH);
-        ctx.graphMH = nullptr;
+        for (hipGraphExec_t &gr : ctx.graphMH) {
+            if (gr) hipGraphExecDestroy(gr);
+            gr = nullptr;
+        }
         if (ctx.d_hist) hipFree(ctx.d_hist);
         ctx.d_hist = nullptr;
         ctx.hist_cap = 0;
@@ -694,17 +701,20 @@ int su2_sweep_measure(int32_t n, int32_t every, double *host_hist)
         ctx.hist_cap = cap;
     }
     int32_t i = 0;
-    // a measurement after every sweep: graphs of kGraphSweeps measured sweeps,
-    // each followed by the one-workgroup reduction of its partials into the
-    // next history entry (the same kernel and order as enqueue_plaquette)
-    if (every == 1 && m >= kGraphSweeps && meas_partials(ctx.g, ctx.plan) <= kReduceOneLevel) {
-        if (!ctx.graphMH) {
-            rc = build_graph(kGraphSweeps, false, &ctx.graphMH, true);
+    // measurements at most kGraphSweeps sweeps apart: graphs of k = 16 / every
+    // of them (k * every sweeps), each measured sweep followed by the
+    // one-workgroup reduction of its partials into the next history entry (the
+    // same kernel and order as enqueue_plaquette)
+    const int32_t k = every <= kGraphSweeps ? kGraphSweeps / every : 0;
+    if (k > 0 && m >= k && meas_partials(ctx.g, ctx.plan) <= kReduceOneLevel) {
+        hipGraphExec_t &gr = ctx.graphMH[every];
+        if (!gr) {
+            rc = build_graph(k * every, false, &gr, every);
             if (rc) return rc;
         }
         HIP_TRY(hipMemsetAsync(ctx.d_cursor, 0, sizeof(uint32_t), ctx.stream));
-        for (; i + kGraphSweeps <= m; i += kGraphSweeps) HIP_TRY(hipGraphLaunch(ctx.graphMH, ctx.stream));
-        ctx.sweep += (uint64_t)i;
+        for (; i + k <= m; i += k) HIP_TRY(hipGraphLaunch(gr, ctx.stream));
+        ctx.sweep += (uint64_t)i * (uint64_t)every;
         ctx.meas_fresh = true;
     }
     for (; i < m && rc == SU2_OK; ++i) {

@@ -413,6 +413,28 @@ def test_measure_every_sweep_graph_equals_single_calls(lib, plan, learned):
         lib.su2_set_proposal(0)
 
 
+@pytest.mark.parametrize("every", [3, 5, 16])
+def test_measure_every_few_sweeps_graph_equals_single_calls(lib, every):
+    """Measurements a few sweeps apart run as graphs of 16 // every of them,
+    each reducing into the next history entry: history, links and counters
+    equal those of one call per measurement (two calls in a row, the
+    remainders measured one by one)."""
+    dims = (8, 6, 10, 4)
+
+    def start():
+        lib.su2_init(dims, 2.3, 17, lib.HOT)
+        lib.su2_set_plan(lib.FUSED_PAIRS, 0)
+
+    start()
+    h = np.concatenate([lib.su2_sweep_measure(7 * every, every), lib.su2_sweep_measure(4 * every, every)])
+    got = lib.su2_links(), lib.su2_counters()
+    start()
+    ref = np.concatenate([lib.su2_sweep_measure(every, every) for _ in range(11)])
+    assert np.array_equal(h, ref)
+    assert np.array_equal(got[0], lib.su2_links()) and got[1] == lib.su2_counters()
+    assert lib.su2_sweep_index() == 11 * every
+
+
 @pytest.mark.parametrize("dims,beta", [((8, 6, 10, 4), 2.3), ((12, 12, 12, 12), 2.5),
                                        ((4, 4, 4, 4), 0.05), ((2, 4, 2, 6), 1.0)])
 def test_fused_measurement_equals_plaquette_kernel(lib, dims, beta):

@@ -24,9 +24,10 @@ CREUTZ_SWITCH = 1.6847376
 # every symbol include/su2.h declares
 EXPORTS = (
     "su2_init", "su2_init_ex", "su2_bind", "su2_sweep", "su2_sweep_measured", "su2_pass", "su2_overrelax",
-    "su2_overrelax_pass", "su2_plaquette", "su2_plaquette_st",
-    "su2_polyakov", "su2_polyakov_correlator", "su2_polyakov_correlator_noalloc", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links", "su2_sweep_index",
-    "su2_counters", "su2_set_stream", "su2_set_plan", "su2_tune", "su2_philox", "su2_synchronize", "su2_last_error",
+    "su2_overrelax_pass", "su2_plaquette", "su2_plaquette_st", "su2_polyakov", "su2_polyakov_correlator",
+    "su2_polyakov_correlator_noalloc", "su2_measure_device", "su2_sweep_measure", "su2_links", "su2_set_links",
+    "su2_sweep_index", "su2_counters", "su2_set_stream", "su2_set_plan", "su2_tune", "su2_philox",
+    "su2_synchronize", "su2_last_error",
     "su2_finalize", "su2_batch_init", "su2_batch_sweep", "su2_batch_set_mode", "su2_batch_tune",
     "su2_batch_set_spin_limit", "su2_batch_plaquette", "su2_batch_links", "su2_batch_counters",
     "su2_batch_sweep_index", "su2_batch_last_error", "su2_batch_finalize",

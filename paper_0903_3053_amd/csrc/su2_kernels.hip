@@ -388,6 +388,7 @@ bool make_pair_geo(const Geo &g, uint32_t counter_slots, PairGeo &pg01, PairGeo 
         pg->xcd_chunk = pg->n_wg % 8u == 0u ? pg->n_wg / 8u : 0u;
         pg->counter_slots = counter_slots;
         pg->dL3 = make_fastdiv(g.L[3]);
+        pg->dGC = make_fastdiv(gc);
     }
     return true;
 }

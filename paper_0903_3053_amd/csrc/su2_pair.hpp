@@ -20,7 +20,10 @@
 //   (2, 3): T = the parity-p sites with fixed x1 and (x2, x3) on one orbit of
 //           the step (-1, +1): points t = 0 .. lcm(L2, L3) - 1 at
 //           (x2, x3) = (-t mod L2, (o + t) mod L3), o < gcd(L2, L3); position
-//           pos = t * H0 + x0 / 2, whole x0 rows of 16-byte links.
+//           pos = t * H0 + x0 / 2, whole x0 rows of 16-byte links.  Set j is
+//           (x1, o) = (j / gcd, j mod gcd): the sets of one XCD's chunk take
+//           every orbit of a few x1 rows, so the x2 and x3 neighbours of a set
+//           (the next orbits) are mostly that XCD's own.
 //
 // A set of at most 1024 sites gets one lane per site (k_pair_small): every
 // U_MU update, one barrier, every U_NU update, the first pass's results in
@@ -45,6 +48,7 @@ struct PairGeo {
     uint32_t xcd_chunk = 0;   // != 0: workgroup w takes T number (w % 8) * xcd_chunk + w / 8
     uint32_t counter_slots = 0;
     FastDiv dL3;
+    FastDiv dGC;              // (2, 3): gcd(L2, L3), the orbits per x1
 };
 
 // Half index and site of position pos of the set T number j.
@@ -57,8 +61,8 @@ __device__ __forceinline__ uint32_t pair_site(const Geo &g, const PairGeo &pg, u
         x = site_of(g, h, p);
         return h;
     } else {
-        const uint32_t o = fdiv(j, g.dL1);
-        const uint32_t x1 = j - o * g.L[1];
+        const uint32_t x1 = fdiv(j, pg.dGC);
+        const uint32_t o = j - x1 * (pg.n_wg / g.L[1]);
         const uint32_t t = fdiv(pos, g.dH0);
         const uint32_t h0 = pos - t * g.H0;
         const uint32_t t2 = t - fdiv(t, g.dL2) * g.L[2];

@@ -52,7 +52,7 @@ def position_site(L, which, j, pos, p):
     if which == 0:
         h = j * H0 * L1 + pos
         return h, site_of(h, p)
-    o, x1 = divmod(j, L1)
+    x1, o = divmod(j, math.gcd(L2, L3))
     t, h0 = divmod(pos, H0)
     x2 = (L2 - t % L2) % L2
     x3 = (o + t) % L3

@@ -43,6 +43,30 @@ def trained(lib):
     return hist, params
 
 
+# distance of the current x0 from a knot below which FP32 (the kernel forms x0
+# = dot(U, w) / |w| and interpolates the knots in FP32, each to a few units of
+# 2^-24) and FP64 may place it in neighbouring segments, whose proposal
+# densities differ at the knot: a flipped segment decision
+KNOT_FLIP_MARGIN = 1e-6
+
+
+def _knots_at(table, alpha, alpha_max=40.0):
+    """The proposal's 33 knots at alpha: the table rows' linear mix (test-side
+    copy of the interpolation, used only to classify mismatches)."""
+    G = len(table)
+    t = alpha / (alpha_max / (G - 1))
+    g0 = min(max(int(np.floor(t)), 0), G - 2)
+    f = t - g0
+    return (1.0 - f) * table[g0] + f * table[g0 + 1]
+
+
+def _exact_table(points):
+    """The oracle's integrated-CDF knots at the table's alpha grid, stored in
+    FP32 as the library stores its table."""
+    grid = np.arange(points) * (40.0 / (points - 1))
+    return np.array([cdf.knots(a) for a in grid]).astype(np.float32).astype(np.float64)
+
+
 def _use(lib, params):
     lib.su2_mlp_set_params(params)
     lib.su2_mlp_tabulate(4096)
@@ -215,7 +239,7 @@ def test_imh_pass_parity(lib, dims, points):
 def test_cdf_tabulate_fills_the_proposal_table(lib):
     """su2_cdf_tabulate: the integrated knots at the table's alpha grid, in
     FP32, without network parameters; a learned-proposal pass reading that
-    table matches the oracle given the same FP32 table."""
+    table matches the oracle reading its own integrated knots rounded to FP32."""
     for points in (2, 31, 64):
         lib.su2_cdf_tabulate(points)
         got = lib.su2_mlp_table()
@@ -226,7 +250,7 @@ def test_cdf_tabulate_fills_the_proposal_table(lib):
     dims = (12, 12, 12, 12)
     U0 = su2_inputs.near_identity_links(dims, 21, 0.35)
     lib.su2_cdf_tabulate(31)
-    table = lib.su2_mlp_table().astype(np.float64)
+    table = _exact_table(31)
     flips = 0
     for parity, mu in ((1, 1), (0, 2)):
         lib.su2_init(dims, 2.3, 9, lib.COLD)
@@ -471,6 +495,83 @@ def test_learned_full_size_32x32x32x32(lib, trained):
           f"{m1:.6f}+-{s1:.6f} (tau_int {t1:.1f}), z = {z:+.2f}; acceptance {acc / prop:.4f}")
     assert abs(z) < 3.0
     assert acc / prop > 0.85
+
+
+def test_learned_pass_level_32x32x32x32(lib):
+    """The learned-proposal workload's lattice at full size: 32^4, beta 2.3,
+    hot start seed 1, a 31-row table of the integrated knots (su2_cdf_tabulate;
+    the oracle reads its own, rounded to FP32, so the pass alone is compared --
+    the network's tables are checked against the oracle's forward pass
+    elsewhere).  After 20 heat-bath sweeps, each of the eight passes of one
+    learned sweep, started from the oracle's state after the previous pass:
+    links within their bar (LINK_TOL grown with the update's conditioning,
+    evaluated at every link over LINK_TOL from the oracle's staple there),
+    flips only at small decision margins, the proposal counters equal where
+    nothing flipped, links outside the pass untouched.  (The fused-pair plan
+    the benchmark runs gives these links bit for bit:
+    test_learned_sweeps_identical_across_plans.)"""
+    from parity import LINK_TOL
+    dims, beta, seed = (32, 32, 32, 32), 2.3, 1
+    lib.su2_cdf_tabulate(31)
+    table_o = _exact_table(31)
+    lib.su2_init(dims, beta, seed, lib.HOT)
+    lib.su2_sweep(20)
+    s = lib.su2_sweep_index()
+    U = lib.su2_links().astype(np.float64)
+    lib.su2_set_proposal(1)
+    par = parity_of(dims)
+    n = flips = over = 0
+    worst = 0.0
+    for p in (1, 0):
+        sel = par == p
+        for mu in range(4):
+            prev = U.astype(np.float32)
+            prev64 = prev.astype(np.float64)
+            lib.su2_set_links(prev, s)
+            c0 = lib.su2_imh_counters()
+            lib.su2_pass(p, mu)
+            c1 = lib.su2_imh_counters()
+            gpu = lib.su2_links()
+            res, margin, po, ao = oracle.imh_pass(dims, U, beta, seed, s, p, mu, table_o)
+            err = np.max(np.abs(gpu[:, mu] - U[:, mu]), axis=1)
+            bad, seg_flip = [], {}
+            for i in np.flatnonzero(err > LINK_TOL):
+                w = oracle.staple(dims, prev64, int(i), mu)
+                k = float(np.sqrt(w @ w))
+                x0 = float(np.clip(U[i, mu] @ w / k, -1.0, 1.0))
+                tol = float(link_tolerance(k, x0))
+                if res[i] == 11:
+                    tol += 8.0 * 2.0 ** -24 * (1.0 + 6.0 / k) / max(np.sqrt(max(1.0 - x0 * x0, 0.0)), 1e-7)
+                if err[i] > tol:
+                    bad.append(i)
+                    # the other decision rounding can flip: the segment of the
+                    # current value xc, where xc lies within rounding of a knot
+                    xc = float(np.clip(prev64[i, mu] @ w / k, -1.0, 1.0))
+                    d_knot = float(np.min(np.abs(_knots_at(table_o, beta * k)[1:32] - xc)))
+                    seg_flip[len(bad) - 1] = d_knot < KNOT_FLIP_MARGIN
+                    print(f"    pass ({p}, {mu}) site {i}: err {err[i]:.2e} bar {tol:.2e} k {k:.4f} x0 {x0:+.6f} "
+                          f"code {res[i]} accept margin {margin[i]:.2e}, xc {d_knot:.1e} from a knot")
+            bad = np.asarray(bad, dtype=np.int64)
+            flip_ok = np.array([margin[i] < IMH_FLIP_MARGIN or seg_flip[j] for j, i in enumerate(bad)], dtype=bool)
+            print(f"  pass ({p}, {mu}): {int(np.sum(err > LINK_TOL))} over {LINK_TOL:g}, {len(bad)} beyond their "
+                  f"bar, proposals {c1[0] - c0[0]}/{po} accepts {c1[1] - c0[1]}/{ao}")
+            assert np.all(flip_ok), "unexplained IMH mismatch"
+            assert np.array_equal(gpu[~sel, mu], prev[~sel, mu])
+            for nu in range(4):
+                if nu != mu:
+                    assert np.array_equal(gpu[:, nu], prev[:, nu])
+            assert unitarity_error(gpu[sel, mu]) <= UNIT_TOL
+            if len(bad) == 0:
+                assert (c1[0] - c0[0], c1[1] - c0[1]) == (po, ao)
+            n += int(sel.sum())
+            flips += len(bad)
+            over += int(np.sum(err > LINK_TOL))
+            keep = np.ones(len(err), dtype=bool)
+            keep[bad] = False
+            worst = max(worst, float(err[sel & keep].max()))
+    print(f"32^4 learned pass level, one sweep: {n} updates, {flips} flipped decisions, {over} links over "
+          f"{LINK_TOL:g} (each within its bar or a flip), max err of the rest {worst:.2e}")
+    assert flips <= max(2, 1e-4 * n)
 
 
 def test_learned_wins_at_strong_coupling(lib, trained):

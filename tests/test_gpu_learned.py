@@ -502,8 +502,9 @@ def test_learned_pass_level_32x32x32x32(lib):
     hot start seed 1, a 31-row table of the integrated knots (su2_cdf_tabulate;
     the oracle reads its own, rounded to FP32, so the pass alone is compared --
     the network's tables are checked against the oracle's forward pass
-    elsewhere).  After 20 heat-bath sweeps, each of the eight passes of one
-    learned sweep, started from the oracle's state after the previous pass:
+    elsewhere).  From the oracle's hot start and 20 heat-bath sweeps, each of
+    the eight passes of one learned sweep, started from the oracle's state
+    after the previous pass:
     links within their bar (LINK_TOL grown with the update's conditioning,
     evaluated at every link over LINK_TOL from the oracle's staple there),
     flips only at small decision margins, the proposal counters equal where
@@ -514,10 +515,12 @@ def test_learned_pass_level_32x32x32x32(lib):
     dims, beta, seed = (32, 32, 32, 32), 2.3, 1
     lib.su2_cdf_tabulate(31)
     table_o = _exact_table(31)
+    # the start: the oracle's own hot start and 20 heat-bath sweeps
+    U = oracle.init(dims, seed, oracle.HOT)
+    for sw in range(20):
+        oracle.sweep(dims, U, beta, seed, sw)
+    s = 20
     lib.su2_init(dims, beta, seed, lib.HOT)
-    lib.su2_sweep(20)
-    s = lib.su2_sweep_index()
-    U = lib.su2_links().astype(np.float64)
     lib.su2_set_proposal(1)
     par = parity_of(dims)
     n = flips = over = 0

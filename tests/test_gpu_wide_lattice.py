@@ -136,6 +136,31 @@ def test_hot_start_sampled(lib, links):
     assert np.max(np.abs(P)) < 1e-4 and abs(L) < 2.5e-3
 
 
+def test_first_pass_from_the_oracles_hot_start(lib, links, field):
+    """The first pass of sweep 0 from the hot start: every input of the
+    sampled updates is the oracle's own hot-start link (oracle_init_sites),
+    none is read from the GPU."""
+    geo = links.geo
+    init(lib, links, lib.HOT)
+    lib.su2_set_plan(1108, 32768)
+    p, mu = 1, 0
+    sites = sample_sites(geo, np.random.default_rng(5), 250, p)
+    all_lex, all_mu = neighbourhood(geo, sites, mu)
+    lex_u = np.unique(all_lex)
+    field[lex_u] = oracle.init_sites(geo.dims, SEED, 1, lex_u)
+    lib.su2_pass(p, mu)
+    new = gather(links, sites, mu)
+    out, tries, margin = oracle.update_sites(geo.dims, field, BETA, SEED, 0, mu, sites)
+    w = np.array([oracle.staple(geo.dims, field, int(x), mu) for x in sites])
+    k = np.sqrt(np.sum(w * w, axis=1))
+    x0 = np.where(tries <= 7, np.sum(out * w, axis=1) / k, np.nan)
+    st = compare_links_conditioned(new, out, margin, k, x0)
+    print(f"{geo.dims}, first pass from the oracle's hot start: {st['n']} sampled updates, {st['flips']} flips, "
+          f"max err {st['max_err_rest']:.2e}")
+    assert st["unexplained"] == 0 and st["flips"] <= 2
+    assert unitarity_error(new) <= UNIT_TOL
+
+
 def test_sweep_pass_by_pass_sampled(lib, links, field):
     """Two sweeps from the hot start with the benchmark's launch plan (tile
     order 1108, 32 KiB LDS), then each pass of the third sweep on its own:

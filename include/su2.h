@@ -367,7 +367,8 @@ int su2_batch_init(int32_t n, const int32_t *dims, const double *betas, const ui
 int su2_batch_sweep(int32_t n);
 
 /* How su2_batch_sweep runs: mode 0 = one launch per (parity, mu) pass over
- * the tiles of all replicas, replayed from a hipGraph; mode 1 = one
+ * the tiles of all replicas, replayed from hipGraphs of up to 16 sweeps
+ * (each XCD takes a contiguous chunk of the tiles); mode 1 = one
  * persistent launch per call (graph-captured with a counter reset and a
  * completion check), in which each replica is pinned to one XCD (replicas
  * balanced over the XCDs by size) and the workgroups running on an XCD take
